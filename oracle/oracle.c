@@ -1,0 +1,478 @@
+/*
+ * oracle.c -- plain, slow, FP64 reference for the pore molecular-dynamics
+ * hot path (Korenkov, Nikonov, Popovicova, "Molecular dynamic simulation of
+ * water vapor interaction with various types of pores using hybrid computing
+ * structures", arXiv:1812.07993).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the checker the GPU library is
+ * measured against.  It is loaded by the tests, by the smoke check and by
+ * the benchmark's CPU-baseline leg, and by nothing else.  It shares no code,
+ * header, table or constant with the GPU library.
+ *
+ * What it computes, in the paper's terms:
+ *   - Newton's equations m_i d^2 r_i / dt^2 = f_i            (Sec. 2, eq. 1)
+ *   - f_i = -dU/dr_i + f_i^ex, with U a sum of Lennard-Jones pair terms and
+ *     f^ex the field of fixed pore-wall atoms                (Sec. 2, eq. 2)
+ *   - velocity Verlet in the order of the paper's GPU functions F2, F1, F3
+ *     (Sec. 3, the F2 update of r and the first half of v; F1 the
+ *     acceleration from r(t+dt); F3 the second half of v).
+ *   Every pair is visited (O(N^2)), as in the paper's F1 ("interactions
+ *   between all particles", Sec. 3).  A pair contributes only below the
+ *   cutoff, which is part of the model here, not an approximation.
+ *
+ * Readings where the paper is silent (each is listed with its reason in the
+ * design notes of the repository):
+ *   - 12-6 form u(r) = 4 eps [(sig/r)^12 - (sig/r)^6] (Sec. 2 names the LJ
+ *     potential and its sigma, epsilon but does not write the form);
+ *   - truncated at r_c (strict r < r_c) and shifted so that u(r_c) = 0; the
+ *     force is not shifted;
+ *   - vapour-wall pairs use (sig_w, eps_w) with the same r_c; wall-wall pairs
+ *     are never evaluated; walls never move;
+ *   - minimum-image periodic boundaries on all three axes; positions are
+ *     wrapped into [0, L) after each drift.
+ *
+ * Determinism: every per-particle sum runs over partners in ascending index
+ * order (vapour first, then walls), and every total is summed serially in
+ * ascending particle order, so results do not depend on the OpenMP thread
+ * count.
+ *
+ * Parity status: the pair term, the force sum, the integrator, the wall
+ * lattice, the cell sort and the pair sets are each pinned by tests against
+ * closed forms, invariants or brute force.  Long-run physical observables
+ * (adsorption, density profiles) are parity unpinned: the paper prints none.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Model parameters in reduced Lennard-Jones units. */
+typedef struct {
+    double box[3];
+    double sigma, epsilon, mass, cutoff, dt;
+    double sigma_wall, epsilon_wall;
+} orc_params;
+
+/* Pore description.  kind: 0 none (no walls), 1 plain slab, 2 cylinder,
+ * 3 slit (two slabs), 4 cone, 5 ink-bottle. */
+typedef struct {
+    int32_t kind;
+    int32_t pad_;
+    double lattice_a;
+    double slab_center_z;
+    double slab_thickness;
+    double r0, r1;
+    double slit_gap;
+} orc_pore;
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+/* ---------------------------------------------------------------------- */
+/* Pair term                                                               */
+/* ---------------------------------------------------------------------- */
+
+/* Lennard-Jones pair at squared distance r2, truncated and shifted.
+ * *u receives the pair energy, *w the scalar with force_on_i = w * (r_i - r_j),
+ * i.e. w = -(1/r) du/dr = 24 eps (2 (s/r)^12 - (s/r)^6) / r^2. */
+static void lj_pair(double r2, double sig, double eps, double rc,
+                    double *u, double *w)
+{
+    if (r2 >= rc * rc) {
+        *u = 0.0;
+        *w = 0.0;
+        return;
+    }
+    double s2 = (sig * sig) / r2;
+    double s6 = s2 * s2 * s2;
+    double s12 = s6 * s6;
+    double c2 = (sig * sig) / (rc * rc);
+    double c6 = c2 * c2 * c2;
+    double c12 = c6 * c6;
+    *u = 4.0 * eps * (s12 - s6) - 4.0 * eps * (c12 - c6);
+    *w = 24.0 * eps * (2.0 * s12 - s6) / r2;
+}
+
+/* Exported for the pair-term pins: energy and w at one distance r. */
+void orc_pair(double r, double sig, double eps, double rc, double *u, double *w)
+{
+    lj_pair(r * r, sig, eps, rc, u, w);
+}
+
+/* Minimum-image displacement a - b on a periodic box. */
+static void min_image(const double *a, const double *b, const double *box,
+                      double *d)
+{
+    for (int k = 0; k < 3; ++k) {
+        double dk = a[k] - b[k];
+        dk -= box[k] * nearbyint(dk / box[k]);
+        d[k] = dk;
+    }
+}
+
+/* ---------------------------------------------------------------------- */
+/* Forces (eq. 2), all pairs                                               */
+/* ---------------------------------------------------------------------- */
+
+/* Force on one vapour atom i from every other vapour atom and every wall
+ * atom; also its vapour-vapour energy over partners j > i and its
+ * vapour-wall energy. */
+static void force_on(int64_t i, int64_t nv, const double *xv, int64_t nw,
+                     const double *xw, const orc_params *p, double *f,
+                     double *pe_vv_upper, double *pe_vw)
+{
+    double fx = 0.0, fy = 0.0, fz = 0.0, evv = 0.0, evw = 0.0;
+    const double *xi = xv + 3 * i;
+    for (int64_t j = 0; j < nv; ++j) {
+        if (j == i) continue;
+        double d[3], u, w;
+        min_image(xi, xv + 3 * j, p->box, d);
+        lj_pair(d[0] * d[0] + d[1] * d[1] + d[2] * d[2], p->sigma,
+                p->epsilon, p->cutoff, &u, &w);
+        fx += w * d[0];
+        fy += w * d[1];
+        fz += w * d[2];
+        if (j > i) evv += u;
+    }
+    for (int64_t k = 0; k < nw; ++k) {
+        double d[3], u, w;
+        min_image(xi, xw + 3 * k, p->box, d);
+        lj_pair(d[0] * d[0] + d[1] * d[1] + d[2] * d[2], p->sigma_wall,
+                p->epsilon_wall, p->cutoff, &u, &w);
+        fx += w * d[0];
+        fy += w * d[1];
+        fz += w * d[2];
+        evw += u;
+    }
+    f[0] = fx;
+    f[1] = fy;
+    f[2] = fz;
+    *pe_vv_upper = evv;
+    *pe_vw = evw;
+}
+
+/* Forces on all vapour atoms, F[nv][3]; total vapour-vapour energy
+ * (each pair once) and vapour-wall energy.  If Fwall is not NULL it receives
+ * the reaction force on each wall atom, Fwall[nw][3] (used only to check
+ * Newton's third law). */
+void orc_forces(int64_t nv, const double *xv, int64_t nw, const double *xw,
+                const orc_params *p, double *F, double *pe_vv, double *pe_vw,
+                double *Fwall)
+{
+    double *evv = (double *)malloc(sizeof(double) * (size_t)(nv > 0 ? nv : 1));
+    double *evw = (double *)malloc(sizeof(double) * (size_t)(nv > 0 ? nv : 1));
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < nv; ++i)
+        force_on(i, nv, xv, nw, xw, p, F + 3 * i, &evv[i], &evw[i]);
+    double svv = 0.0, svw = 0.0;
+    for (int64_t i = 0; i < nv; ++i) {
+        svv += evv[i];
+        svw += evw[i];
+    }
+    *pe_vv = svv;
+    *pe_vw = svw;
+    free(evv);
+    free(evw);
+    if (Fwall) {
+#pragma omp parallel for schedule(static)
+        for (int64_t k = 0; k < nw; ++k) {
+            double gx = 0.0, gy = 0.0, gz = 0.0;
+            for (int64_t i = 0; i < nv; ++i) {
+                double d[3], u, w;
+                min_image(xw + 3 * k, xv + 3 * i, p->box, d);
+                lj_pair(d[0] * d[0] + d[1] * d[1] + d[2] * d[2],
+                        p->sigma_wall, p->epsilon_wall, p->cutoff, &u, &w);
+                gx += w * d[0];
+                gy += w * d[1];
+                gz += w * d[2];
+            }
+            Fwall[3 * k + 0] = gx;
+            Fwall[3 * k + 1] = gy;
+            Fwall[3 * k + 2] = gz;
+        }
+    }
+}
+
+/* Forces on a chosen subset of vapour atoms: F_sel[m][3] for atoms sel[0..m).
+ * pe_sel[m] (if not NULL) receives each atom's share of the potential energy,
+ * half of every vapour-vapour pair plus all of its vapour-wall pairs. */
+void orc_forces_subset(int64_t nv, const double *xv, int64_t nw,
+                       const double *xw, const orc_params *p, int64_t m,
+                       const int64_t *sel, double *F_sel, double *pe_sel)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t s = 0; s < m; ++s) {
+        int64_t i = sel[s];
+        double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0;
+        const double *xi = xv + 3 * i;
+        for (int64_t j = 0; j < nv; ++j) {
+            if (j == i) continue;
+            double d[3], u, w;
+            min_image(xi, xv + 3 * j, p->box, d);
+            lj_pair(d[0] * d[0] + d[1] * d[1] + d[2] * d[2], p->sigma,
+                    p->epsilon, p->cutoff, &u, &w);
+            fx += w * d[0];
+            fy += w * d[1];
+            fz += w * d[2];
+            e += 0.5 * u;
+        }
+        for (int64_t k = 0; k < nw; ++k) {
+            double d[3], u, w;
+            min_image(xi, xw + 3 * k, p->box, d);
+            lj_pair(d[0] * d[0] + d[1] * d[1] + d[2] * d[2], p->sigma_wall,
+                    p->epsilon_wall, p->cutoff, &u, &w);
+            fx += w * d[0];
+            fy += w * d[1];
+            fz += w * d[2];
+            e += u;
+        }
+        F_sel[3 * s + 0] = fx;
+        F_sel[3 * s + 1] = fy;
+        F_sel[3 * s + 2] = fz;
+        if (pe_sel) pe_sel[s] = e;
+    }
+}
+
+/* ---------------------------------------------------------------------- */
+/* Velocity Verlet (F2, F1, F3 of Sec. 3)                                  */
+/* ---------------------------------------------------------------------- */
+
+static double kinetic(int64_t nv, const double *v, double m)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < nv; ++i)
+        s += v[3 * i] * v[3 * i] + v[3 * i + 1] * v[3 * i + 1] +
+             v[3 * i + 2] * v[3 * i + 2];
+    return 0.5 * m * s;
+}
+
+/* Wrap one coordinate into [0, L). */
+static double wrap(double x, double L)
+{
+    x -= L * floor(x / L);
+    if (x >= L) x = 0.0;
+    return x;
+}
+
+/* Advance the state by nsteps velocity-Verlet steps.
+ *   x, v   [nv][3], updated in place;
+ *   a      [nv][3], acceleration at the current x; if have_a == 0 it is
+ *          computed first (a(0) before step 1), and on return it holds the
+ *          acceleration at the final x;
+ *   energies, if not NULL, receives rows (ke, pe_vv, pe_vw) for step 0 and
+ *          for every step that is a multiple of every_k, then the last step
+ *          if not already recorded; the number of rows is returned.
+ * One step is:
+ *   F2: r(t+dt) = r(t) + v(t) dt + a(t) dt^2 / 2,  v(t+dt/2) = v(t) + a(t) dt/2,
+ *       then r is wrapped into the periodic box;
+ *   F1: a(t+dt) = f(r(t+dt)) / m;
+ *   F3: v(t+dt) = v(t+dt/2) + a(t+dt) dt/2. */
+int64_t orc_run(int64_t nv, double *x, double *v, double *a, int have_a,
+                int64_t nw, const double *xw, const orc_params *p,
+                int64_t nsteps, int64_t every_k, double *energies)
+{
+    double dt = p->dt, m = p->mass, evv = 0.0, evw = 0.0;
+    double *F = (double *)malloc(sizeof(double) * 3 * (size_t)(nv > 0 ? nv : 1));
+    int64_t rows = 0;
+    if (!have_a || energies) {
+        orc_forces(nv, x, nw, xw, p, F, &evv, &evw, NULL);
+        if (!have_a)
+            for (int64_t q = 0; q < 3 * nv; ++q) a[q] = F[q] / m;
+    }
+    if (energies) {
+        energies[0] = kinetic(nv, v, m);
+        energies[1] = evv;
+        energies[2] = evw;
+        rows = 1;
+    }
+    for (int64_t n = 1; n <= nsteps; ++n) {
+        for (int64_t i = 0; i < nv; ++i)
+            for (int k = 0; k < 3; ++k) {
+                int64_t q = 3 * i + k;
+                x[q] = x[q] + v[q] * dt + 0.5 * a[q] * dt * dt;
+                v[q] = v[q] + 0.5 * a[q] * dt;
+                x[q] = wrap(x[q], p->box[k]);
+            }
+        orc_forces(nv, x, nw, xw, p, F, &evv, &evw, NULL);
+        for (int64_t q = 0; q < 3 * nv; ++q) {
+            a[q] = F[q] / m;
+            v[q] = v[q] + 0.5 * a[q] * dt;
+        }
+        int record = energies && ((every_k > 0 && n % every_k == 0) || n == nsteps);
+        if (record) {
+            energies[3 * rows + 0] = kinetic(nv, v, m);
+            energies[3 * rows + 1] = evv;
+            energies[3 * rows + 2] = evw;
+            ++rows;
+        }
+    }
+    free(F);
+    return rows;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Pore-wall lattice                                                       */
+/* ---------------------------------------------------------------------- */
+
+/* Pore radius at a layer whose centre is a height h above the slab's lower
+ * face, for a slab of thickness t. */
+static double pore_radius(const orc_pore *pp, double h, double t)
+{
+    switch (pp->kind) {
+    case 2: /* cylinder */
+        return pp->r0;
+    case 4: /* cone: linear from r0 at the lower face to r1 at the upper */
+        return pp->r0 + (pp->r1 - pp->r0) * (h / t);
+    case 5: /* ink-bottle: neck r0 in the outer quarters, cavity r1 between */
+        return (h < 0.25 * t || h >= 0.75 * t) ? pp->r0 : pp->r1;
+    default: /* plain slab, slit: no hole */
+        return 0.0;
+    }
+}
+
+/* Enumerate one slab's sites on a simple cubic lattice of spacing a:
+ * x = (i + 1/2) a, y = (j + 1/2) a over the whole periodic box, and
+ * z = z_lo + (k + 1/2) a for the layers inside [z_lo, z_lo + t).  A site is
+ * left out when its distance from the pore axis (x = Lx/2, y = Ly/2) is
+ * strictly below the pore radius of its layer.  Order: layer, then y, then
+ * x.  Writes at most cap sites; returns how many there are in total. */
+static int64_t slab_sites(const orc_pore *pp, const double *box, double z_lo,
+                          double t, double *out, int64_t n0, int64_t cap)
+{
+    double a = pp->lattice_a;
+    int64_t nx = (int64_t)floor(box[0] / a + 0.5);
+    int64_t ny = (int64_t)floor(box[1] / a + 0.5);
+    int64_t nz = (int64_t)floor(t / a + 0.5);
+    double cx = 0.5 * box[0], cy = 0.5 * box[1];
+    int64_t n = n0;
+    for (int64_t k = 0; k < nz; ++k) {
+        double h = (k + 0.5) * a;
+        double r = pore_radius(pp, h, t);
+        for (int64_t j = 0; j < ny; ++j)
+            for (int64_t i = 0; i < nx; ++i) {
+                double x = (i + 0.5) * a, y = (j + 0.5) * a;
+                double dx = x - cx, dy = y - cy;
+                if (dx * dx + dy * dy < r * r) continue;
+                if (n < cap) {
+                    out[3 * n + 0] = x;
+                    out[3 * n + 1] = y;
+                    out[3 * n + 2] = z_lo + h;
+                }
+                ++n;
+            }
+    }
+    return n;
+}
+
+/* All wall sites of a pore, in canonical order.  Slab placement:
+ *   plain slab, cylinder, cone, ink-bottle: one slab of thickness t centred
+ *     at slab_center_z;
+ *   slit: two slabs of thickness t whose facing surfaces are slit_gap apart,
+ *     centred at slab_center_z (lower slab first);
+ *   none: no sites. */
+int64_t orc_wall_lattice(const orc_pore *pp, const double *box, double *out,
+                         int64_t cap)
+{
+    double t = pp->slab_thickness, c = pp->slab_center_z;
+    switch (pp->kind) {
+    case 0:
+        return 0;
+    case 3: {
+        int64_t n = slab_sites(pp, box, c - 0.5 * pp->slit_gap - t, t, out, 0, cap);
+        return slab_sites(pp, box, c + 0.5 * pp->slit_gap, t, out, n, cap);
+    }
+    default:
+        return slab_sites(pp, box, c - 0.5 * t, t, out, 0, cap);
+    }
+}
+
+/* ---------------------------------------------------------------------- */
+/* Cell binning and pair sets (integer work, compared bit for bit)         */
+/* ---------------------------------------------------------------------- */
+
+/* Stable counting sort of atoms into a grid of nc[0] x nc[1] x nc[2] cells.
+ * Cell of an atom along axis k: floor(x_k * inv[k]) clamped to [0, nc[k]-1];
+ * linear index cx + nc0 (cy + nc1 cz).  Outputs: cell[n], cell_start
+ * [ncells + 1] (exclusive prefix of the counts) and perm[n] = the atom ids
+ * in cell order, ascending id inside a cell. */
+void orc_cell_sort(int64_t n, const double *x, const double *inv,
+                   const int32_t *nc, int32_t *cell, int32_t *cell_start,
+                   int32_t *perm)
+{
+    int64_t ncell = (int64_t)nc[0] * nc[1] * nc[2];
+    for (int64_t c = 0; c <= ncell; ++c) cell_start[c] = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t ck[3];
+        for (int k = 0; k < 3; ++k) {
+            double q = floor(x[3 * i + k] * inv[k]);
+            int32_t ci = (int32_t)q;
+            if (q < 0.0) ci = 0;
+            if (q > (double)(nc[k] - 1)) ci = nc[k] - 1;
+            ck[k] = ci;
+        }
+        cell[i] = ck[0] + nc[0] * (ck[1] + nc[1] * ck[2]);
+        cell_start[cell[i] + 1] += 1;
+    }
+    for (int64_t c = 0; c < ncell; ++c) cell_start[c + 1] += cell_start[c];
+    int32_t *fill = (int32_t *)calloc((size_t)(ncell > 0 ? ncell : 1), sizeof(int32_t));
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t c = cell[i];
+        perm[cell_start[c] + fill[c]] = (int32_t)i;
+        fill[c] += 1;
+    }
+    free(fill);
+}
+
+/* Every vapour-vapour pair (i < j) and vapour-wall pair (i, w) whose
+ * minimum-image squared distance is strictly below rc^2, in lexicographic
+ * order.  Writes at most cap pairs of each kind; returns both totals. */
+void orc_pairs(int64_t nv, const double *xv, int64_t nw, const double *xw,
+               const double *box, double rc, int64_t cap, int32_t *vv,
+               int64_t *n_vv, int32_t *vw, int64_t *n_vw)
+{
+    int64_t a = 0, b = 0;
+    for (int64_t i = 0; i < nv; ++i) {
+        for (int64_t j = i + 1; j < nv; ++j) {
+            double d[3];
+            min_image(xv + 3 * i, xv + 3 * j, box, d);
+            if (d[0] * d[0] + d[1] * d[1] + d[2] * d[2] < rc * rc) {
+                if (a < cap) {
+                    vv[2 * a] = (int32_t)i;
+                    vv[2 * a + 1] = (int32_t)j;
+                }
+                ++a;
+            }
+        }
+        for (int64_t k = 0; k < nw; ++k) {
+            double d[3];
+            min_image(xv + 3 * i, xw + 3 * k, box, d);
+            if (d[0] * d[0] + d[1] * d[1] + d[2] * d[2] < rc * rc) {
+                if (b < cap) {
+                    vw[2 * b] = (int32_t)i;
+                    vw[2 * b + 1] = (int32_t)k;
+                }
+                ++b;
+            }
+        }
+    }
+    *n_vv = a;
+    *n_vw = b;
+}

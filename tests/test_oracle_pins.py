@@ -1,0 +1,434 @@
+"""Pins of the FP64 oracle against closed forms, invariants and brute force.
+
+Nothing here re-types the oracle's formulas: each test checks a fact that the
+mathematics or the paper fixes (a zero, a minimum, a derivative, a
+conservation law, a symmetry, an exact trajectory, a count derived by hand),
+so that a dropped term, a wrong sign or a wrong index in the oracle fails at
+least one of them.
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1812_07993_amd import synth
+
+RC = 2.5
+R_MIN = 2.0 ** (1.0 / 6.0)
+
+
+def two_body(r, sigma=1.0, eps=1.0, box=40.0):
+    """Force on atom 0 and the energy of a lone pair at distance r along x."""
+    x = np.array([[10.0 + r, 20.0, 20.0], [10.0, 20.0, 20.0]])
+    p = oracle.make_params(box, sigma=sigma, epsilon=eps)
+    F, evv, evw = oracle.forces(x, None, p)
+    return F, evv
+
+
+# --------------------------------------------------------------------------
+# Pair term: properties that pin u(r) = a r^-12 - b r^-6 + c and its force
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("sigma,eps", [(1.0, 1.0), (1.3, 0.7), (0.8, 1.5)])
+def test_pair_minimum_and_depth(sigma, eps):
+    rc = RC * sigma
+    rmin = R_MIN * sigma
+    # force vanishes at the minimum 2^(1/6) sigma
+    u_min, w_min = oracle.pair(rmin, sigma, eps, rc)
+    assert abs(w_min * rmin) < 1e-12 * eps / sigma
+    # the unshifted potential is zero at r = sigma and -eps at the minimum,
+    # so the well is eps deep measured from the r = sigma level
+    u_sig, _ = oracle.pair(sigma, sigma, eps, rc)
+    assert u_min - u_sig == pytest.approx(-eps, rel=1e-13)
+    # shifted energy is continuous at r_c and zero beyond it
+    u_in, _ = oracle.pair(rc * (1 - 1e-12), sigma, eps, rc)
+    assert abs(u_in) < 1e-12 * eps
+    for r in (rc, rc * 1.0000001, 3.7 * sigma):
+        u, w = oracle.pair(r, sigma, eps, rc)
+        assert u == 0.0 and w == 0.0
+
+
+@pytest.mark.parametrize("r", [0.95, 1.0, 1.05, 1.12, 1.3, 1.7, 2.1, 2.45])
+def test_pair_force_is_minus_derivative(r):
+    def central(h):
+        up, _ = oracle.pair(r + h, 1.0, 1.0, RC)
+        um, _ = oracle.pair(r - h, 1.0, 1.0, RC)
+        return (up - um) / (2 * h)
+
+    # Richardson-extrapolated central difference, error O(h^4)
+    h = 1e-3
+    dudr = (4.0 * central(h / 2) - central(h)) / 3.0
+    _, w = oracle.pair(r, 1.0, 1.0, RC)
+    # force along the separation is -du/dr = w * r
+    assert w * r == pytest.approx(-dudr, rel=1e-8, abs=1e-9)
+
+
+def test_pair_repulsive_inside_attractive_outside():
+    for r in (0.9, 1.0, 1.1):
+        assert oracle.pair(r)[1] > 0
+    for r in (1.2, 1.5, 2.0, 2.49):
+        assert oracle.pair(r)[1] < 0
+
+
+def test_pair_exact_rationals():
+    """At r^2 rational and r_c = 5/2 every term is rational; compare with
+    exact values derived from u = 4 eps (r^-12 - r^-6) shifted by its value at
+    r_c, and the force magnitude 24 eps (2 r^-12 - r^-6) / r."""
+    c6 = Fraction(2, 5) ** 6
+    uc = 4 * (c6 * c6 - c6)
+    cases = {Fraction(1): None, Fraction(3, 2): None, Fraction(2): None,
+             Fraction(9, 10): None}
+    for r in cases:
+        s6 = (1 / r) ** 6
+        u = 4 * (s6 * s6 - s6) - uc
+        f = 24 * (2 * s6 * s6 - s6) / r
+        uo, w = oracle.pair(float(r))
+        assert uo == pytest.approx(float(u), rel=1e-14, abs=1e-15)
+        assert w * float(r) == pytest.approx(float(f), rel=1e-14, abs=1e-15)
+    # the survey's hand values for the same points
+    assert oracle.pair(1.0)[0] == pytest.approx(0.016316891136, abs=1e-12)
+    assert oracle.pair(1.0)[1] == pytest.approx(24.0, rel=1e-15)
+    assert oracle.pair(2.0)[1] * 2.0 == pytest.approx(-0.181640625, rel=1e-14)
+    assert oracle.pair(2.5 - 1e-13)[1] * 2.5 == pytest.approx(-0.0389994774528, rel=1e-10)
+
+
+def test_pair_through_force_sum():
+    """The all-pairs sum reproduces the pair term for two atoms: action on 0
+    is +w d along +x (repulsive at r = 1), equal and opposite on 1."""
+    for r in (1.0, 1.5, 2.0):
+        F, e = two_body(r)
+        u, w = oracle.pair(r)
+        assert F[0, 0] == pytest.approx(w * r, rel=1e-14)
+        assert F[1, 0] == pytest.approx(-w * r, rel=1e-14)
+        assert np.all(F[:, 1:] == 0.0)
+        assert e == pytest.approx(u, rel=1e-14)
+
+
+def test_wall_pair_uses_wall_parameters():
+    """A vapour atom next to one wall atom feels (sigma_w, eps_w)."""
+    p = oracle.make_params(40.0, sigma_wall=1.1, epsilon_wall=1.5)
+    for r in (1.0, 1.5, 2.0):
+        x = np.array([[10.0 + r, 20.0, 20.0]])
+        w = np.array([[10.0, 20.0, 20.0]])
+        F, evv, evw = oracle.forces(x, w, p)
+        u, ww = oracle.pair(r, 1.1, 1.5, RC)
+        assert evv == 0.0
+        assert evw == pytest.approx(u, rel=1e-14)
+        assert F[0, 0] == pytest.approx(ww * r, rel=1e-14)
+    # eps_w scales both energy and force linearly
+    p1 = oracle.make_params(40.0, epsilon_wall=1.0)
+    x = np.array([[11.5, 20.0, 20.0]])
+    w = np.array([[10.0, 20.0, 20.0]])
+    F15, _, e15 = oracle.forces(x, w, oracle.make_params(40.0))
+    F10, _, e10 = oracle.forces(x, w, p1)
+    assert e15 == pytest.approx(1.5 * e10, rel=1e-14)
+    assert F15[0, 0] == pytest.approx(1.5 * F10[0, 0], rel=1e-14)
+
+
+# --------------------------------------------------------------------------
+# Sums over many atoms
+# --------------------------------------------------------------------------
+
+def small_system(n=150, L=12.0, with_walls=True, seed=5):
+    rng = np.random.default_rng(seed)
+    pore = synth.Pore("cylinder", 1.0, 6.0, 2.0, 2.0) if with_walls else synth.Pore("none")
+    walls = synth.wall_sites(pore, (L, L, L))
+    x = synth.rsa_place(rng, (L, L, L), n, walls, 0.9)
+    v = synth.maxwell(rng, n, 1.2)
+    return x, v, walls, oracle.make_params(L)
+
+
+def test_newton_third_law_vapour_only():
+    x, _, _, p = small_system(with_walls=False)
+    F, _, _ = oracle.forces(x, None, p)
+    scale = np.abs(F).sum()
+    assert np.all(np.abs(F.sum(axis=0)) <= 1e-12 * scale)
+
+
+def test_newton_third_law_with_walls():
+    x, _, walls, p = small_system()
+    F, _, _, Fw = oracle.forces(x, walls, p, wall_reaction=True)
+    scale = np.abs(F).sum()
+    assert np.any(np.abs(F.sum(axis=0)) > 1e-6 * scale)  # walls push on vapour
+    assert np.all(np.abs(F.sum(axis=0) + Fw.sum(axis=0)) <= 1e-12 * scale)
+
+
+def test_force_is_minus_gradient_of_total_energy():
+    x, _, walls, p = small_system(n=80, L=10.0)
+    F, _, _ = oracle.forces(x, walls, p)
+    h = 1e-6
+    rng = np.random.default_rng(1)
+    for i in rng.choice(x.shape[0], 8, replace=False):
+        for k in range(3):
+            xp, xm = x.copy(), x.copy()
+            xp[i, k] += h
+            xm[i, k] -= h
+            # skip if a pair of atom i sits within 2h of the cutoff (the
+            # shifted energy has a kink there)
+            d = x - x[i]
+            d -= 10.0 * np.rint(d / 10.0)
+            dw = walls - x[i]
+            dw -= 10.0 * np.rint(dw / 10.0)
+            r = np.concatenate([np.linalg.norm(d, axis=1), np.linalg.norm(dw, axis=1)])
+            if np.any(np.abs(r - RC) < 1e-4):
+                continue
+            _, a1, b1 = oracle.forces(xp, walls, p)
+            _, a0, b0 = oracle.forces(xm, walls, p)
+            g = ((a1 + b1) - (a0 + b0)) / (2 * h)
+            assert F[i, k] == pytest.approx(-g, rel=1e-6, abs=1e-6)
+
+
+def test_minimum_image_across_boundary():
+    L = 20.0
+    p = oracle.make_params(L)
+    inside = np.array([[10.0, 10.0, 10.0], [11.3, 10.4, 9.1]])
+    shifted = inside.copy()
+    shifted[:, 0] += 9.5  # atom 1 crosses x = L
+    shifted[:, 2] -= 9.5  # atom 1 crosses z = 0
+    shifted %= L
+    F1, e1, _ = oracle.forces(inside, None, p)
+    F2, e2, _ = oracle.forces(shifted, None, p)
+    assert np.allclose(F1, F2, rtol=1e-12, atol=1e-13)
+    assert e1 == pytest.approx(e2, rel=1e-12)
+
+
+def test_wall_symmetry_on_pore_axis():
+    """An atom on the axis at mid-slab feels no net wall force: the lattice is
+    mirror symmetric about x = L/2, y = L/2 and about the slab's mid-plane
+    (cylinder, ink-bottle); the cone keeps only the x and y mirrors."""
+    L = 16.0
+    p = oracle.make_params(L)
+    x = np.array([[8.0, 8.0, 8.0]])
+    for kind, r0, r1, zero_z in (("cylinder", 2.0, 0.0, True),
+                                 ("inkbottle", 1.5, 2.05, True),
+                                 ("cone", 1.5, 2.5, False)):
+        q = oracle.make_pore(kind, 1.0, 8.0, 4.0, r0, r1)
+        walls = oracle.wall_lattice(q, (L, L, L))
+        F, _, evw = oracle.forces(x, walls, p)
+        assert evw != 0.0  # the pin is not trivial: walls are within r_c
+        mag = np.abs(F).max() + 1.0
+        assert abs(F[0, 0]) < 1e-12 * mag and abs(F[0, 1]) < 1e-12 * mag
+        if zero_z:
+            assert abs(F[0, 2]) < 1e-12 * mag
+        else:
+            assert abs(F[0, 2]) > 1e-6  # the cone widens upward
+    # slit: an atom at mid-gap right above a lattice column
+    q = oracle.make_pore("slit", 1.0, 8.0, 2.0, slit_gap=3.0)
+    walls = oracle.wall_lattice(q, (L, L, L))
+    F, _, evw = oracle.forces(np.array([[8.5, 8.5, 8.0]]), walls, p)
+    assert evw != 0.0
+    assert np.all(np.abs(F) < 1e-12)
+
+
+# --------------------------------------------------------------------------
+# Integrator (F2, F1, F3)
+# --------------------------------------------------------------------------
+
+def test_ballistic_exact():
+    """A lone atom moves in a straight line; with dyadic x0, v, dt every
+    position is exact, including the wrap through x = L."""
+    L = 32.0
+    p = oracle.make_params(L, dt=1.0 / 256.0)
+    x0 = np.array([[31.5, 0.25, 16.0]])
+    v0 = np.array([[1.0, -0.5, 0.0]])
+    for n in (1, 100, 256, 300):
+        x, v, a, _ = oracle.run(x0, v0, None, p, n)
+        want = np.mod(x0 + v0 * n / 256.0, L)
+        assert np.array_equal(x, want), (n, x, want)
+        assert np.array_equal(v, v0)
+        assert np.all(a == 0.0)
+
+
+def test_momentum_conserved_without_walls():
+    x, v, _, p = small_system(n=200, L=14.0, with_walls=False)
+    P0 = v.sum(axis=0)
+    x1, v1, _, E = oracle.run(x, v, None, p, 200, every=50)
+    assert np.all(np.abs(v1.sum(axis=0) - P0) < 1e-11)
+    # and the run really moved and exchanged energy
+    assert np.abs(x1 - x).max() > 0.1
+
+
+def test_dimer_small_oscillation_period():
+    """Two atoms near the LJ minimum oscillate with the harmonic period
+    2 pi / sqrt(k / mu), k = u''(2^(1/6)) = 72 * 2^(-1/3), mu = m / 2."""
+    p = oracle.make_params(40.0)
+    r0 = R_MIN + 0.005
+    x = np.array([[10.0 + r0, 20.0, 20.0], [10.0, 20.0, 20.0]])
+    v = np.zeros_like(x)
+    a = None
+    seps = []
+    for _ in range(1400):
+        x, v, a, _ = oracle.run(x, v, None, p, 1, a=a)
+        seps.append(x[0, 0] - x[1, 0])
+    s = np.array(seps) - R_MIN
+    # times (in steps) of upward zero crossings, linearly interpolated
+    ups = [k + s[k] / (s[k] - s[k + 1]) for k in range(len(s) - 1)
+           if s[k] < 0 <= s[k + 1]]
+    period = (ups[-1] - ups[0]) / (len(ups) - 1) * p.dt
+    k = 72.0 * 2.0 ** (-1.0 / 3.0)
+    assert period == pytest.approx(2 * math.pi / math.sqrt(2 * k), rel=2e-3)
+
+
+def test_time_reversibility():
+    x, v, walls, p = small_system(n=120, L=12.0)
+    x1, v1, _, _ = oracle.run(x, v, walls, p, 100)
+    x2, v2, _, _ = oracle.run(x1, -v1, walls, p, 100)
+    d = x2 - x
+    d -= 12.0 * np.rint(d / 12.0)
+    assert np.abs(d).max() < 1e-9
+    assert np.abs(v2 + v).max() < 1e-8
+
+
+def energy_drift(tot, burn=100, window=1000):
+    """Drift measures used throughout: the least-squares trend of E_n over
+    `window` steps after `burn` steps, times the window, relative to
+    |E_burn|; and the largest deviation from E_burn over the same window."""
+    seg = np.asarray(tot[burn:burn + window + 1], dtype=np.float64)
+    t = np.arange(seg.shape[0], dtype=np.float64)
+    slope = np.polyfit(t, seg, 1)[0]
+    return (abs(slope) * window / abs(seg[0]),
+            float(np.abs(seg - seg[0]).max() / abs(seg[0])))
+
+
+@pytest.mark.slow
+def test_nve_drift_cylinder_slab_1000_steps():
+    """Energy conservation of the plain method on the 32^3 cylinder-slab
+    system over 1000 steps after a 100-step burn-in: trend <= 1e-4 of |E|.
+    (From the very first step the deviation reaches ~3.5e-4 within six steps:
+    the 0.9-sigma contacts of the random start are integrated at dt = 0.005;
+    the error halves twice when dt halves, see the next test.)"""
+    s = synth.cylinder_slab_small()
+    p = oracle.make_params(s.params.box)
+    q = oracle.make_pore("cylinder", 1.0, 16.0, 4.0, 3.0)
+    walls = oracle.wall_lattice(q, s.params.box)
+    _, _, _, E = oracle.run(s.x, s.v, walls, p, 1100, every=1)
+    tot = E.sum(axis=1)
+    ke0 = 0.5 * (3 * s.n - 3) * 1.2
+    assert E[0, 0] == pytest.approx(ke0, rel=1e-12)
+    assert abs(tot[0]) > 0.1 * E[0, 0]
+    trend, maxdev = energy_drift(tot)
+    assert trend <= 1e-4, trend
+    assert maxdev <= 2e-4, maxdev
+
+
+def test_integrator_is_second_order():
+    """Velocity Verlet's energy error scales as dt^2: halving dt divides the
+    largest energy deviation over a fixed time by about 4."""
+    x, v, walls, _ = small_system(n=150, L=12.0)
+    devs = []
+    for dt in (0.004, 0.002):
+        p = oracle.make_params(12.0, dt=dt)
+        _, _, _, E = oracle.run(x, v, walls, p, int(round(0.8 / dt)), every=1)
+        tot = E.sum(axis=1)
+        devs.append(np.abs(tot - tot[0]).max())
+    assert 3.0 < devs[0] / devs[1] < 5.0, devs
+
+
+# --------------------------------------------------------------------------
+# Wall lattice: counts derived by hand
+# --------------------------------------------------------------------------
+
+def test_wall_counts_by_hand():
+    """Half-integer lattice points strictly inside a circle of radius r about
+    a lattice-cell corner: r = 3 -> 32, r = 6 -> 112, r = 10 -> 316 (count
+    per quadrant the points (a, b) in {1/2, 3/2, ...} with a^2 + b^2 < r^2:
+    8, 28, 79).  Hence:
+      32^2 x 4 layers - 4 x 32                     = 3968    (cylinder r = 3)
+      2 slabs x 4 layers x 128^2                   = 131072  (slit)
+      8 x (256^2 - 112)                            = 523392  (cylinder r = 6)
+      8 x 256^2 - 4 x 32 - 4 x 316                 = 522896  (ink-bottle 3/10)
+    and the cone 4 -> 12 sampled at the layer centres r = 4.5, 5.5, ..., 11.5
+    removes 60 + 88 + 124 + 172 + 216 + 276 + 332 + 408 = 1676 sites
+    (r = 4.5: per quadrant 4 + 4 + 4 + 3 = 15 points, so 60):
+      8 x 256^2 - 1676                             = 522612."""
+    cases = [
+        (oracle.make_pore("cylinder", 1.0, 16.0, 4.0, 3.0), (32.0, 32.0, 32.0), 3968),
+        (oracle.make_pore("slit", 1.0, 64.0, 4.0, slit_gap=8.0), (128.0,) * 3, 131072),
+        (oracle.make_pore("cylinder", 1.0, 64.0, 8.0, 6.0), (256.0, 256.0, 128.0), 523392),
+        (oracle.make_pore("inkbottle", 1.0, 64.0, 8.0, 3.0, 10.0), (256.0, 256.0, 128.0), 522896),
+        (oracle.make_pore("cone", 1.0, 64.0, 8.0, 4.0, 12.0), (256.0, 256.0, 128.0), 522612),
+    ]
+    for q, box, n in cases:
+        w = oracle.wall_lattice(q, box)
+        assert w.shape[0] == n
+        # every site is a lattice point inside a slab
+        assert np.all(np.abs(np.mod(w, 1.0) - 0.5) < 1e-12)
+
+
+def test_cone_layer_counts_by_hand():
+    """Removed sites per layer for radii 4.5 .. 11.5 (brute force over a
+    quadrant of half-integer points, independent of the oracle's loop)."""
+    want = []
+    for r in (4.5, 5.5, 6.5, 7.5, 8.5, 9.5, 10.5, 11.5):
+        pts = np.arange(0.5, 12.0, 1.0)
+        A, B = np.meshgrid(pts, pts)
+        want.append(4 * int(np.sum(A * A + B * B < r * r)))
+    assert want == [60, 88, 124, 172, 216, 276, 332, 408]
+    q = oracle.make_pore("cone", 1.0, 64.0, 8.0, 4.0, 12.0)
+    w = oracle.wall_lattice(q, (256.0, 256.0, 128.0))
+    z = np.round(w[:, 2] - 60.5).astype(int)
+    got = [65536 - int(np.sum(z == k)) for k in range(8)]
+    assert got == want
+
+
+def test_wall_lattice_agrees_with_input_generator():
+    for kind, r0, r1 in (("cylinder", 3.0, 0.0), ("cone", 2.5, 7.25),
+                         ("inkbottle", 2.0, 20.0 / 3.0), ("slab", 0, 0)):
+        q = oracle.make_pore(kind, 1.0, 13.0, 4.0, r0, r1)
+        w = oracle.wall_lattice(q, (26.0, 26.0, 26.0))
+        g = synth.wall_sites(synth.Pore(kind, 1.0, 13.0, 4.0, r0, r1), (26.0, 26.0, 26.0))
+        assert np.array_equal(w, g)
+
+
+# --------------------------------------------------------------------------
+# Integer work: cell sort and pair sets vs brute force
+# --------------------------------------------------------------------------
+
+def test_cell_sort_matches_stable_argsort():
+    rng = np.random.default_rng(3)
+    L = np.array([17.0, 23.0, 11.0])
+    x = rng.random((700, 3)) * L
+    x[0] = [0.0, 0.0, 0.0]
+    x[1] = np.nextafter(L, 0)
+    nc = np.array([6, 9, 4], dtype=np.int32)
+    inv = nc / L
+    cell, start, perm = oracle.cell_sort(x, inv, nc)
+    ck = np.clip(np.floor(x * inv).astype(int), 0, nc - 1)
+    lin = ck[:, 0] + nc[0] * (ck[:, 1] + nc[1] * ck[:, 2])
+    assert np.array_equal(cell, lin)
+    assert np.array_equal(perm, np.argsort(lin, kind="stable"))
+    counts = np.bincount(lin, minlength=int(np.prod(nc)))
+    assert np.array_equal(start, np.concatenate([[0], np.cumsum(counts)]))
+
+
+def test_pairs_match_brute_force_loop():
+    rng = np.random.default_rng(11)
+    L = 9.0
+    walls = synth.wall_sites(synth.Pore("cylinder", 1.0, 4.5, 2.0, 1.5), (L, L, L))
+    x = synth.rsa_place(rng, (L, L, L), 60, walls, 0.9)
+    vv, vw = oracle.pairs(x, walls, (L, L, L), RC)
+    want_vv, want_vw = [], []
+    for i in range(len(x)):
+        for j in range(i + 1, len(x)):
+            r2 = sum(((x[i][k] - x[j][k] + L / 2) % L - L / 2) ** 2 for k in range(3))
+            if r2 < RC * RC:
+                want_vv.append((i, j))
+        for w in range(len(walls)):
+            r2 = sum(((x[i][k] - walls[w][k] + L / 2) % L - L / 2) ** 2 for k in range(3))
+            if r2 < RC * RC:
+                want_vw.append((i, w))
+    assert [tuple(p) for p in vv] == want_vv
+    assert [tuple(p) for p in vw] == want_vw
+    assert len(want_vv) > 50 and len(want_vw) > 20
+
+
+def test_forces_subset_matches_full():
+    x, _, walls, p = small_system()
+    F, evv, evw = oracle.forces(x, walls, p)
+    sel = np.array([0, 7, 33, 149])
+    Fs, pe = oracle.forces_subset(x, walls, p, sel)
+    assert np.array_equal(Fs, F[sel])
+    allpe = oracle.forces_subset(x, walls, p, np.arange(x.shape[0]))[1]
+    assert allpe.sum() == pytest.approx(evv + evw, rel=1e-12)
