@@ -1,0 +1,245 @@
+/*
+ * poremd.h -- C interface of the MI355X (gfx950) pore molecular-dynamics
+ * library.
+ *
+ * The library advances systems of vapour molecules interacting with each
+ * other and with the fixed atoms of a pore wall, as in Korenkov, Nikonov,
+ * Popovicova, arXiv:1812.07993:
+ *   - equations of motion m_i d^2 r_i/dt^2 = f_i                (Sec. 2, eq. 1)
+ *   - f_i = -dU/dr_i + f_i^ex: Lennard-Jones pairs between vapour molecules,
+ *     and the field of the wall atoms as f^ex                    (Sec. 2, eq. 2)
+ *   - velocity Verlet: drift and first half-kick (the paper's F2), forces at
+ *     the new positions (F1), second half-kick (F3)             (Sec. 3)
+ *   - periodic boundaries on the outer box (Secs. 4-5).
+ * Model readings the paper leaves open (fixed here and in the tests): 12-6
+ * Lennard-Jones truncated at r_c and energy-shifted (force not shifted);
+ * vapour-wall pairs use (sigma_wall, epsilon_wall) with the same r_c; walls
+ * are simple-cubic lattices that never move; reduced units, k_B = 1.
+ *
+ * Conventions for every function:
+ *   - Return value: PMD_OK (0) or a negative pmd_status.  A message for the
+ *     last failure on the calling thread is available from pmd_last_error().
+ *     No C++ exception crosses this interface.
+ *   - Host arrays are row-major [n][3] doubles, in the caller's particle order
+ *     (index i of the array given to pmd_create_system).  The library copies
+ *     inputs; the caller keeps ownership of every pointer it passes.
+ *   - Positions are returned wrapped into [0, L) on each axis.
+ *   - A handle is not thread-safe; distinct handles may be used from
+ *     different threads.
+ *   - Work is queued on a HIP stream (the one given at creation, or a
+ *     library-owned stream if NULL) and runs asynchronously until a call
+ *     that reads results, or pmd_sync, waits for it.
+ */
+#ifndef POREMD_H
+#define POREMD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PMD_OK = 0,
+    PMD_EINVAL = -1,   /* invalid argument (message says which) */
+    PMD_ENOMEM = -2,   /* device memory or budget exhausted */
+    PMD_EHIP = -3,     /* a HIP runtime call failed */
+    PMD_ENUMERIC = -4, /* a non-finite force, energy or position appeared */
+    PMD_EAGAIN = -5,   /* no room now (batch full or over budget); retry */
+    PMD_ESTATE = -6    /* call not allowed in the handle's current state */
+} pmd_status;
+
+typedef enum { PMD_FP64 = 0, PMD_MIXED = 1 } pmd_precision;
+
+typedef enum {
+    PMD_PORE_NONE = 0,      /* no wall atoms */
+    PMD_PORE_SLAB = 1,      /* one slab, no hole */
+    PMD_PORE_CYLINDER = 2,  /* one slab with a cylindrical hole of radius r0 */
+    PMD_PORE_SLIT = 3,      /* two slabs whose facing surfaces are slit_gap apart */
+    PMD_PORE_CONE = 4,      /* one slab, hole radius linear from r0 (lower face) to r1 (upper face) */
+    PMD_PORE_INKBOTTLE = 5  /* one slab, neck r0 in its outer quarters, cavity r1 in between */
+} pmd_pore_kind;
+
+/* Model parameters, reduced Lennard-Jones units.  box[k] is the periodic
+ * box edge L_k.  Constraints: every L_k >= 3 * (cutoff + skin), sigma,
+ * epsilon, mass, dt > 0, cutoff > 0. */
+typedef struct {
+    double box[3];
+    double sigma, epsilon, mass, cutoff, dt;
+    double sigma_wall, epsilon_wall;
+    int32_t precision;    /* pmd_precision: PMD_FP64 = all arithmetic in FP64;
+                             PMD_MIXED = pair forces in FP32, per-particle
+                             force sums, integration and energies in FP64 */
+    int32_t reserved;
+} pmd_params;
+
+/* Pore geometry.  Wall sites sit on a simple cubic lattice of spacing
+ * lattice_a at x = (i + 1/2) a, y = (j + 1/2) a over the whole box and
+ * z = z_lo + (k + 1/2) a through each slab [z_lo, z_lo + slab_thickness).
+ * A slab is centred at slab_center_z (for a slit, the gap is).  The pore
+ * axis is the line x = L_x/2, y = L_y/2; a site is removed when its distance
+ * from the axis is strictly below the pore radius of its layer (evaluated at
+ * the layer's centre).  Wall sites are numbered layer by layer (lower slab
+ * first), then by y, then by x. */
+typedef struct {
+    int32_t kind;         /* pmd_pore_kind */
+    int32_t reserved;
+    double lattice_a;
+    double slab_center_z;
+    double slab_thickness;
+    double r0, r1;
+    double slit_gap;
+} pmd_pore;
+
+/* Energies at one step (per system).  ke = (m/2) sum |v|^2 at the full
+ * step; pe_vv = sum over vapour pairs i<j; pe_vw = sum over vapour-wall
+ * pairs; temperature = 2 ke / (3 n - 3). */
+typedef struct {
+    int64_t step;
+    double ke, pe_vv, pe_vw, etotal, temperature;
+} pmd_energies;
+
+/* Performance knobs; zero fields take the library default.  skin: extra
+ * radius of the neighbour lists beyond the cutoff; rebin_every: steps
+ * between neighbour-list rebuilds (a rebuild also happens early whenever an
+ * atom has travelled more than skin/2 since the last one); block: threads
+ * per workgroup (64..1024, multiple of 64); list_cap: neighbour-list slots
+ * per atom; energy_every: record energies every k steps (the last step of
+ * every pmd_step call is always recorded). */
+typedef struct {
+    double skin;
+    int32_t rebin_every;
+    int32_t block;
+    int32_t list_cap;
+    int32_t energy_every;
+    int32_t use_graph;    /* 1: replay captured HIP graphs; 0: plain launches */
+    int32_t reserved;
+} pmd_tuning;
+
+typedef struct pmd_system pmd_system;
+typedef struct pmd_batch pmd_batch;
+
+/* Message for the last failure on the calling thread (never NULL). */
+const char *pmd_last_error(void);
+
+/* Library version, major * 10000 + minor * 100 + patch. */
+int pmd_version(void);
+
+/* Number of wall sites a pore would generate in a box (host arithmetic
+ * only; no device work). */
+int pmd_wall_count(const pmd_params *params, const pmd_pore *pore, int64_t *n_wall);
+
+/* Device bytes a system of n_vapor molecules with this pore needs, with the
+ * given tuning (NULL = defaults).  Used for admission by footprint. */
+int pmd_footprint_bytes(const pmd_params *params, const pmd_pore *pore,
+                        int64_t n_vapor, const pmd_tuning *tuning, size_t *out);
+
+/* Create a system (Sec. 2: N particles with positions, velocities and mass
+ * in a pore).  pos, vel: host [n_vapor][3].  Walls: if wall_pos is NULL the
+ * library generates them from pore (n_wall is ignored); otherwise wall_pos
+ * is host [n_wall][3] and pore only describes the geometry.  hip_stream: a
+ * hipStream_t to queue work on, or NULL for a library-owned stream.
+ * tuning: NULL = defaults.  The initial forces and energies are computed
+ * before the call returns.  Fails with PMD_EINVAL on a bad parameter,
+ * non-finite input or a position outside [0, L) after wrapping. */
+int pmd_create_system(const pmd_params *params, const pmd_pore *pore,
+                      int64_t n_vapor, const double *pos, const double *vel,
+                      int64_t n_wall, const double *wall_pos, void *hip_stream,
+                      const pmd_tuning *tuning, pmd_system **out);
+
+/* Queue nsteps velocity-Verlet steps (each: F2 drift and half-kick, F1
+ * forces, F3 half-kick).  Asynchronous; pmd_sync or any readback waits. */
+int pmd_step(pmd_system *sys, int64_t nsteps);
+
+/* Wait until every queued step has been done.  Returns PMD_ENUMERIC if a
+ * non-finite value appeared. */
+int pmd_sync(pmd_system *sys);
+
+/* Readbacks (wait for queued work).  n must equal the system's count. */
+int pmd_get_positions(pmd_system *sys, double *out, int64_t n);
+int pmd_get_velocities(pmd_system *sys, double *out, int64_t n);
+/* Forces on the vapour molecules at the current positions, [n][3]. */
+int pmd_get_forces(pmd_system *sys, double *out, int64_t n);
+/* Energies at the current step. */
+int pmd_get_energies(pmd_system *sys, pmd_energies *out);
+/* Recorded energies, oldest first; at most cap rows; *n_out = rows written. */
+int pmd_get_energy_history(pmd_system *sys, pmd_energies *out, int64_t cap,
+                           int64_t *n_out);
+/* Wall sites in the canonical order of pmd_pore, [n_wall][3]. */
+int pmd_get_wall_positions(pmd_system *sys, double *out, int64_t n_wall);
+int pmd_get_counts(pmd_system *sys, int64_t *n_vapor, int64_t *n_wall);
+int64_t pmd_get_step(pmd_system *sys);
+
+/* Positions into a device buffer dev_out ([n][3] doubles, caller order),
+ * queued on `stream` (NULL = the system's stream) after the system's
+ * queued work.  Does not wait. */
+int pmd_get_positions_device(pmd_system *sys, double *dev_out, int64_t n,
+                             void *stream);
+
+/* Change the performance knobs of an existing system (takes effect at the
+ * next pmd_step). */
+int pmd_set_tuning(pmd_system *sys, const pmd_tuning *tuning);
+int pmd_get_tuning(pmd_system *sys, pmd_tuning *out);
+
+/* Destroy a system (NULL-safe).  Waits for queued work. */
+int pmd_destroy(pmd_system *sys);
+
+/* ---- Kernel timing, for measurement ------------------------------------ */
+
+/* When enabled, every launch of the force-and-integrate kernel is bracketed
+ * by HIP events recorded on the launch stream; pmd_kernel_time returns the
+ * number of launches timed and their mean duration in milliseconds. */
+int pmd_timing_enable(pmd_system *sys, int enable);
+int pmd_kernel_time(pmd_system *sys, int64_t *launches, double *mean_ms);
+
+/* ---- Test-only debug exports (same library; unstable) ------------------- */
+
+/* Cell binning after the last rebuild: cell_of_atom[n] (caller order),
+ * cell_start[n_cells + 1] (offsets into the cell-sorted order), perm[n]
+ * (caller indices in cell-sorted order), and the grid: ncell[3], inv[3]
+ * (cells per unit length, inv_k = ncell_k / L_k).  Positions used are those
+ * at the last rebuild. */
+int pmd_debug_cells(pmd_system *sys, int32_t *cell_of_atom, int64_t n,
+                    int32_t *cell_start, int64_t n_cells_p1, int32_t *perm,
+                    int32_t *ncell, double *inv);
+/* In-cutoff pairs found through the neighbour lists at the current
+ * positions, tested in FP64: vv (i < j) and vw (i, wall index), caller
+ * order, each sorted lexicographically.  Writes at most cap pairs of each
+ * kind; *n_vv and *n_vw receive the totals. */
+int pmd_debug_pairs(pmd_system *sys, int32_t *vv, int64_t cap, int64_t *n_vv,
+                    int32_t *vw, int64_t *n_vw);
+/* Number of neighbour-list rebuilds so far, and the longest list at the
+ * last one. */
+int pmd_debug_lists(pmd_system *sys, int64_t *rebuilds, int64_t *max_len);
+
+/* ---- Batching and serving ------------------------------------------------ */
+
+/* A batch advances many systems together: one launch per phase covers all
+ * resident systems, and the steps are replayed from captured HIP graphs.
+ * hbm_budget bounds the device bytes the batch may hold (0 = no bound);
+ * max_slots bounds the number of resident systems. */
+int pmd_batch_create(size_t hbm_budget, int max_slots, void *hip_stream,
+                     pmd_batch **out);
+/* Move a system into the batch with nsteps steps to run.  Returns
+ * PMD_EAGAIN if no slot or budget is free.  The system handle stays valid
+ * but may not be stepped or read until released. */
+int pmd_batch_admit(pmd_batch *b, pmd_system *sys, int64_t nsteps, int *slot);
+/* Run chunk_steps steps (or fewer where a system finishes) on every resident
+ * system.  Asynchronous. */
+int pmd_batch_advance(pmd_batch *b, int64_t chunk_steps);
+/* Slots whose systems have finished their steps (waits for queued work). */
+int pmd_batch_poll(pmd_batch *b, int *done_slots, int cap, int *n_done);
+/* Non-blocking variant: reports only what is known complete. */
+int pmd_batch_poll_async(pmd_batch *b, int *done_slots, int cap, int *n_done);
+/* Take a system out of the batch; its handle becomes usable again. */
+int pmd_batch_release(pmd_batch *b, int slot, pmd_system **sys_out);
+int pmd_batch_info(pmd_batch *b, int *resident, size_t *bytes_used,
+                   size_t *bytes_budget);
+int pmd_batch_destroy(pmd_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* POREMD_H */

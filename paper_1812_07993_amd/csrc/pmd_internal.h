@@ -1,0 +1,153 @@
+// pmd_internal.h -- device-side data layout of the pore-MD library.
+//
+// A "pool" holds the state of one or more systems in shared device arrays.
+// A stand-alone system is a pool with one resident system; a batch is a pool
+// with many.  Every per-atom array is cell-sorted structure-of-arrays; each
+// system owns a contiguous range of vapour slots padded to a multiple of
+// the workgroup size, so that a workgroup never spans two systems.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pmd {
+
+constexpr int kPad = 256;            // vapour slots per system are padded to this
+constexpr int kMaxBlock = 1024;
+constexpr unsigned kIndexBits = 27;  // neighbour-list entry: index | code << 27
+constexpr unsigned kIndexMask = (1u << kIndexBits) - 1u;
+
+enum Phase : int {
+    PH_INIT = 0,  // forces not yet computed
+    PH_REST = 1,  // full-step state x(t), v(t), a(t)
+    PH_RUN = 2    // leapfrog state inside a run: x(t), v(t - dt/2)
+};
+
+enum Status : int {
+    ST_HALT = 1,       // an atom travelled more than skin/2 since the last rebuild
+    ST_OVERFLOW = 2,   // a neighbour list exceeded its capacity
+    ST_NONFINITE = 4   // a non-finite force or position appeared
+};
+
+// Per-system constants (set on the host at admission).
+struct SysParams {
+    double L[3];        // box edges
+    double invL[3];
+    double h[3];        // cell edges, L / nc
+    double inv_h[3];    // nc / L, used to bin
+    int nc[3];
+    int ncell;          // nc0 * nc1 * nc2
+    int voff, nv, vcap; // vapour slots [voff, voff + vcap), real atoms first nv after sorting
+    int woff, nw;       // wall slots [woff, woff + nw)
+    int coff;           // vapour cell_start base: ncell + 2 entries (cells, padding cell, end)
+    int wcoff;          // wall cell_start base: ncell + 1 entries
+    int boff, nblk;     // logical workgroups [boff, boff + nblk) of this system
+    int pboff;          // energy partials base (one entry per workgroup)
+    int ering_off, ering_cap;
+    int energy_every;
+    int active;         // 1 if the slot holds a system
+    int pad0;
+    double A, B, Aw, Bw;   // 4 eps sig^12, 4 eps sig^6 for vapour-vapour and vapour-wall
+    double uc, ucw;        // energy shift u(r_c) of each pair kind
+    double rc2, rl2;       // cutoff^2, neighbour-list radius^2
+    double dt, mass, inv_mass;
+    float half_skin;       // rebuild threshold on the travelled path
+    float pad1;
+};
+
+// Per-system dynamic state, written by kernels.
+struct SysState {
+    int remaining;    // steps left in the current run
+    int phase;        // Phase
+    int status;       // Status bits seen by the current launch
+    int status_next;  // bits raised during the current launch (merged at its end)
+    int lbuf;         // current local-coordinate buffer (0/1)
+    int sbuf;         // current state buffer (0/1)
+    int sbuf_prev;    // state buffer before the last rebuild
+    int blocks_done;  // finished workgroups of the step kernel (last-block pattern)
+    int nrec;         // energy records written
+    int max_nbr;      // longest neighbour list at the last rebuild
+    int rebins;       // rebuilds so far
+    int steps_since;  // steps since the last rebuild
+    long long step;   // completed steps
+};
+
+struct EnergyRec {
+    long long step;
+    double ke, pe_vv, pe_vw;
+};
+
+struct alignas(16) f4 { float x, y, z, w; };
+struct alignas(32) d4 { double x, y, z, w; };
+
+template <typename T> struct V4;
+template <> struct V4<float> { using type = f4; };
+template <> struct V4<double> { using type = d4; };
+
+// Device pointers of a pool, passed by value to every kernel.
+struct PoolDev {
+    SysParams* sp;
+    SysState* st;
+    const int* blk_sys;   // logical workgroup -> system slot
+    int nlog;             // logical workgroups
+    int block;            // threads per workgroup
+    int vt, wt;           // vapour and wall slot capacity
+    int cap;              // neighbour-list capacity per atom
+    // per-atom state, double buffered by SysState::sbuf; SoA with stride vt
+    double* X[2];
+    double* V[2];
+    int* id[2];
+    double* A;            // accelerations at rest (stride vt)
+    float* travel;        // path length since the last rebuild
+    int* cref;            // packed cell (cx | cy << 10 | cz << 20) at the last rebuild
+    int* cell_lin;        // linear cell index at the last rebuild
+    void* L[2];           // local coordinates (f4 or d4), vt + wt entries; walls at vt + w
+    // binning scratch
+    int* count;           // per cell (all systems' ranges)
+    int* cstart;          // per cell + padding + end
+    int* arr;             // arrival rank within the cell (per slot)
+    int* tmp;             // slots in arrival order
+    int* cell_tmp;        // cell of each old slot
+    // neighbour lists, ELL layout list[k * vt + slot]
+    unsigned* list;
+    int* nlist;
+    // walls
+    double* WX;           // sorted wall positions, SoA stride wt
+    int* wid;             // canonical wall index of each sorted wall slot
+    int* wcstart;         // wall cell_start (global wall slots)
+    // energies
+    double* partial;      // 3 doubles per workgroup
+    EnergyRec* erec;
+};
+
+struct PoreDev {
+    int kind;
+    int nslab;
+    double a;
+    double z_lo[2];
+    double t;
+    double r0, r1;
+    int nx, ny, nz;       // sites per slab: nx * ny * nz
+    int pad;
+};
+
+// ---- launchers (pmd_kernels.hip) -----------------------------------------
+hipError_t launch_wall_generate(const PoreDev& pore, const double* L, double* out_xyz_soa,
+                                int stride, int* block_counts, int* block_offsets,
+                                int* total, hipStream_t s);
+hipError_t launch_wall_bin(const PoolDev& P, int sys, const double* raw_soa, int raw_stride,
+                           int nw, int precision, hipStream_t s);
+hipError_t launch_rebuild(const PoolDev& P, int nslots, int precision, hipStream_t s);
+hipError_t launch_set_run(const PoolDev& P, int slot, int add_steps, int phase_init, hipStream_t s);
+hipError_t launch_step(const PoolDev& P, int precision, hipStream_t s, hipEvent_t ev0,
+                       hipEvent_t ev1);
+hipError_t launch_unpermute(const PoolDev& P, int slot, int which, double* out_aos,
+                            int n, hipStream_t s);
+hipError_t launch_wall_unpermute(const PoolDev& P, int slot, double* out_aos, int n,
+                                 hipStream_t s);
+hipError_t launch_debug_pairs(const PoolDev& P, int slot, int nv, int* out_triples, int cap,
+                              int* counts, hipStream_t s);
+hipError_t launch_copy_in(const PoolDev& P, int slot, const double* pos_aos,
+                          const double* vel_aos, int n, int vcap, hipStream_t s);
+
+}  // namespace pmd

@@ -1,0 +1,1010 @@
+// pmd_kernels.hip -- gfx950 kernels of the pore-MD hot path.
+//
+// One time step is velocity Verlet (arXiv:1812.07993, Sec. 3: F2 drift and
+// first half-kick, F1 forces from the new positions, F3 second half-kick).
+// Inside a run the step kernel fuses F1 and F3 of step n with F2 of step
+// n + 1 (the leapfrog form of the same update), so one launch per step reads
+// and writes each atom's state once.
+//
+// Forces (Sec. 2, eq. 2) are short-ranged Lennard-Jones sums over Verlet
+// neighbour lists of radius r_c + skin, rebuilt from a cell grid (cells of
+// edge >= r_c + skin) at the start of every graph replay and whenever an
+// atom has travelled more than skin/2.  The rebuild is five launches: drift
+// and bin count, per-system scan, arrival scatter, stable placement (atoms
+// ordered by cell, then by caller index), list build.
+//
+// Precision: FP64 keeps every operation in double.  Mixed computes the pair
+// terms in FP32 on cell-local coordinates (|x| <= cell edge, so the FP32
+// rounding of a separation is ~1e-7 of the cell edge) and accumulates each
+// atom's force, the integration and the energies in FP64.  A pair whose FP32
+// r^2 lies within a narrow band of r_c^2 is re-tested in FP64 so that the
+// cutoff decision matches an FP64 evaluation.
+#include <hip/hip_ext.h>
+
+#include "pmd_internal.h"
+
+namespace pmd {
+
+// ---------------------------------------------------------------------------
+// Helpers
+// ---------------------------------------------------------------------------
+
+// Workgroups are dispatched round-robin over the 8 XCDs of the device.  Map
+// the hardware index so each XCD receives a contiguous run of logical
+// workgroups: cell-sorted neighbours then share that XCD's L2.  The grid is
+// padded to a multiple of 8.
+__device__ __forceinline__ int logical_block()
+{
+    const int q = gridDim.x >> 3;
+    const int b = blockIdx.x;
+    return (b & 7) * q + (b >> 3);
+}
+
+__device__ __forceinline__ int wrap_cell(int c, int n)
+{
+    c += (c < 0) ? n : 0;
+    c -= (c >= n) ? n : 0;
+    return c;
+}
+
+__device__ __forceinline__ double wrap_box(double x, double L)
+{
+    x -= L * floor(x / L);
+    return (x >= L) ? 0.0 : x;
+}
+
+__device__ __forceinline__ int cell_axis(double x, double inv, int n)
+{
+    double q = floor(x * inv);
+    int c = (int)q;
+    c = (q < 0.0) ? 0 : c;
+    c = (q > (double)(n - 1)) ? n - 1 : c;
+    return c;
+}
+
+// Minimum-image offset of x from the origin of cell index c along one axis.
+__device__ __forceinline__ double local_axis(double x, int c, double h, double L, double invL)
+{
+    double l = x - (double)c * h;
+    return l - L * rint(l * invL);
+}
+
+template <typename T>
+__device__ __forceinline__ typename V4<T>::type make4(double x, double y, double z)
+{
+    typename V4<T>::type v;
+    v.x = (T)x;
+    v.y = (T)y;
+    v.z = (T)z;
+    v.w = (T)0;
+    return v;
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ int wave_or(int v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ int wave_max(int v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Exclusive scan over the workgroup (any size up to 1024, multiple of 64).
+// Returns the exclusive prefix; *total receives the workgroup sum.
+__device__ int block_exclusive_scan(int v, int* lds /* >= 17 ints */, int* total)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nw = blockDim.x >> 6;
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) lds[wave] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int w = 0; w < nw; ++w) {
+            int t = lds[w];
+            lds[w] = run;
+            run += t;
+        }
+        lds[16] = run;
+    }
+    __syncthreads();
+    int r = lds[wave] + x - v;
+    *total = lds[16];
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ double atomic_load_f64(const double* p)
+{
+    unsigned long long u = __hip_atomic_load((const unsigned long long*)p, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+    return __longlong_as_double((long long)u);
+}
+
+// ---------------------------------------------------------------------------
+// Wall lattice (boundary treatment, part 1: fixed atoms of the pore walls)
+// ---------------------------------------------------------------------------
+
+__device__ double layer_radius(const PoreDev& p, double hz)
+{
+    switch (p.kind) {
+    case 2: return p.r0;
+    case 4: return p.r0 + (p.r1 - p.r0) * (hz / p.t);
+    case 5: return (hz < 0.25 * p.t || hz >= 0.75 * p.t) ? p.r0 : p.r1;
+    default: return 0.0;
+    }
+}
+
+__device__ bool wall_site(const PoreDev& p, const double* L, long long s, double* xyz)
+{
+    const long long per_slab = (long long)p.nx * p.ny * p.nz;
+    const int slab = (int)(s / per_slab);
+    long long r = s - (long long)slab * per_slab;
+    const int k = (int)(r / ((long long)p.nx * p.ny));
+    r -= (long long)k * p.nx * p.ny;
+    const int j = (int)(r / p.nx);
+    const int i = (int)(r - (long long)j * p.nx);
+    const double hz = (k + 0.5) * p.a;
+    const double x = (i + 0.5) * p.a, y = (j + 0.5) * p.a;
+    xyz[0] = x;
+    xyz[1] = y;
+    xyz[2] = p.z_lo[slab] + hz;
+    const double rad = layer_radius(p, hz);
+    const double dx = x - 0.5 * L[0], dy = y - 0.5 * L[1];
+    return !(dx * dx + dy * dy < rad * rad);
+}
+
+struct Box3 { double L[3]; };
+
+__global__ void k_wall_count(PoreDev p, Box3 b, long long nsites, int* block_counts)
+{
+    const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    double xyz[3];
+    const bool keep = s < nsites && wall_site(p, b.L, s, xyz);
+    const int c = __syncthreads_count(keep);
+    if (threadIdx.x == 0) block_counts[blockIdx.x] = c;
+}
+
+__global__ void k_scan_small(const int* in, int n, int* out, int* total)
+{
+    __shared__ int lds[17];
+    const int T = blockDim.x;
+    const int per = (n + T - 1) / T;
+    const int lo = threadIdx.x * per, hi = min(n, lo + per);
+    int sum = 0;
+    for (int c = lo; c < hi; ++c) sum += in[c];
+    int tot;
+    int run = block_exclusive_scan(sum, lds, &tot);
+    for (int c = lo; c < hi; ++c) {
+        int k = in[c];
+        out[c] = run;
+        run += k;
+    }
+    if (threadIdx.x == 0) *total = tot;
+}
+
+__global__ void k_wall_emit(PoreDev p, Box3 b, long long nsites, const int* block_offsets,
+                            double* out, int stride)
+{
+    __shared__ int wave_base[16];
+    const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    double xyz[3];
+    const bool keep = s < nsites && wall_site(p, b.L, s, xyz);
+    const unsigned long long m = __ballot(keep);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) wave_base[wave] = __popcll(m);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+            int t = wave_base[w];
+            wave_base[w] = run;
+            run += t;
+        }
+    }
+    __syncthreads();
+    if (keep) {
+        const int rank = wave_base[wave] + __popcll(m & ((1ull << lane) - 1ull));
+        const int o = block_offsets[blockIdx.x] + rank;
+        out[o] = xyz[0];
+        out[stride + o] = xyz[1];
+        out[2 * stride + o] = xyz[2];
+    }
+}
+
+hipError_t launch_wall_generate(const PoreDev& pore, const double* L, double* out, int stride,
+                                int* block_counts, int* block_offsets, int* total, hipStream_t s)
+{
+    const long long nsites = (long long)pore.nslab * pore.nx * pore.ny * pore.nz;
+    if (nsites <= 0) return hipSuccess;
+    const int B = 256;
+    const int G = (int)((nsites + B - 1) / B);
+    Box3 b;
+    for (int k = 0; k < 3; ++k) b.L[k] = L[k];
+    hipLaunchKernelGGL(k_wall_count, dim3(G), dim3(B), 0, s, pore, b, nsites, block_counts);
+    hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, block_counts, G, block_offsets,
+                       total);
+    hipLaunchKernelGGL(k_wall_emit, dim3(G), dim3(B), 0, s, pore, b, nsites, block_offsets, out,
+                       stride);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Wall binning (once per system): walls sorted by cell, then by canonical
+// index; local coordinates written into both coordinate buffers.
+// ---------------------------------------------------------------------------
+
+__global__ void k_wall_bin_count(PoolDev P, int sys, const double* raw, int rs)
+{
+    const SysParams& sp = P.sp[sys];
+    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= sp.nw) return;
+    const int cx = cell_axis(raw[w], sp.inv_h[0], sp.nc[0]);
+    const int cy = cell_axis(raw[rs + w], sp.inv_h[1], sp.nc[1]);
+    const int cz = cell_axis(raw[2 * rs + w], sp.inv_h[2], sp.nc[2]);
+    const int c = cx + sp.nc[0] * (cy + sp.nc[1] * cz);
+    P.cell_tmp[w] = c;
+    P.arr[w] = atomicAdd(&P.count[sp.coff + c], 1);
+}
+
+__global__ void k_wall_bin_scan(PoolDev P, int sys)
+{
+    __shared__ int lds[17];
+    const SysParams& sp = P.sp[sys];
+    const int M = sp.ncell;
+    int* cnt = P.count + sp.coff;
+    int* cs = P.wcstart + sp.wcoff;
+    const int T = blockDim.x;
+    const int per = (M + T - 1) / T;
+    const int lo = threadIdx.x * per, hi = min(M, lo + per);
+    int sum = 0;
+    for (int c = lo; c < hi; ++c) sum += cnt[c];
+    int tot;
+    int run = sp.woff + block_exclusive_scan(sum, lds, &tot);
+    for (int c = lo; c < hi; ++c) {
+        int k = cnt[c];
+        cs[c] = run;
+        run += k;
+        cnt[c] = 0;
+    }
+    if (threadIdx.x == 0) cs[M] = sp.woff + tot;
+}
+
+__global__ void k_wall_bin_scatter(PoolDev P, int sys)
+{
+    const SysParams& sp = P.sp[sys];
+    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= sp.nw) return;
+    const int c = P.cell_tmp[w];
+    P.tmp[P.wcstart[sp.wcoff + c] - sp.woff + P.arr[w]] = w;
+}
+
+template <typename T>
+__global__ void k_wall_bin_place(PoolDev P, int sys, const double* raw, int rs)
+{
+    using V = typename V4<T>::type;
+    const SysParams& sp = P.sp[sys];
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= sp.nw) return;
+    const int o = P.tmp[p];
+    const int c = P.cell_tmp[o];
+    const int b0 = P.wcstart[sp.wcoff + c] - sp.woff, b1 = P.wcstart[sp.wcoff + c + 1] - sp.woff;
+    int rank = 0;
+    for (int q = b0; q < b1; ++q) rank += (P.tmp[q] < o);
+    const int d = sp.woff + b0 + rank;
+    const double x = raw[o], y = raw[rs + o], z = raw[2 * rs + o];
+    P.WX[d] = x;
+    P.WX[P.wt + d] = y;
+    P.WX[2 * P.wt + d] = z;
+    P.wid[d] = o;
+    const int cx = c % sp.nc[0], cy = (c / sp.nc[0]) % sp.nc[1], cz = c / (sp.nc[0] * sp.nc[1]);
+    const V l = make4<T>(local_axis(x, cx, sp.h[0], sp.L[0], sp.invL[0]),
+                         local_axis(y, cy, sp.h[1], sp.L[1], sp.invL[1]),
+                         local_axis(z, cz, sp.h[2], sp.L[2], sp.invL[2]));
+    ((V*)P.L[0])[P.vt + d] = l;
+    ((V*)P.L[1])[P.vt + d] = l;
+}
+
+hipError_t launch_wall_bin(const PoolDev& P, int sys, const double* raw, int rs, int nw,
+                           int precision, hipStream_t s)
+{
+    if (nw <= 0) {
+        hipLaunchKernelGGL(k_wall_bin_scan, dim3(1), dim3(1024), 0, s, P, sys);
+        return hipGetLastError();
+    }
+    const int B = 256, G = (nw + B - 1) / B;
+    hipLaunchKernelGGL(k_wall_bin_count, dim3(G), dim3(B), 0, s, P, sys, raw, rs);
+    hipLaunchKernelGGL(k_wall_bin_scan, dim3(1), dim3(1024), 0, s, P, sys);
+    hipLaunchKernelGGL(k_wall_bin_scatter, dim3(G), dim3(B), 0, s, P, sys);
+    if (precision == 1)
+        hipLaunchKernelGGL(k_wall_bin_place<float>, dim3(G), dim3(B), 0, s, P, sys, raw, rs);
+    else
+        hipLaunchKernelGGL(k_wall_bin_place<double>, dim3(G), dim3(B), 0, s, P, sys, raw, rs);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Rebuild: drift (run start) + bin count, scan, scatter, place, list build
+// ---------------------------------------------------------------------------
+
+struct SlotCtx {
+    int s, lb, li, i;
+};
+
+// Resolve the calling thread's system and slot; false if the workgroup is
+// padding or its system has nothing to do.
+__device__ __forceinline__ bool rebuild_ctx(const PoolDev& P, SlotCtx& c)
+{
+    const int lb = logical_block();
+    if (lb >= P.nlog) return false;
+    const int s = P.blk_sys[lb];
+    const SysState* st = P.st + s;
+    if (st->remaining <= 0 || (st->status & ST_NONFINITE)) return false;
+    const SysParams* sp = P.sp + s;
+    c.s = s;
+    c.lb = lb;
+    c.li = (lb - sp->boff) * (int)blockDim.x + (int)threadIdx.x;
+    c.i = sp->voff + c.li;
+    return true;
+}
+
+__global__ void k_bin_count(PoolDev P)
+{
+    SlotCtx c;
+    if (!rebuild_ctx(P, c)) return;
+    const SysParams& sp = P.sp[c.s];
+    const SysState& st = P.st[c.s];
+    const int vt = P.vt;
+    int cell;
+    if (c.li < sp.nv) {
+        const int b = st.sbuf;
+        double* X = P.X[b];
+        double x = X[c.i], y = X[vt + c.i], z = X[2 * vt + c.i];
+        if (st.phase == PH_REST) {
+            // first half of the run's first step (F2): v += a dt/2, x += v dt
+            double* Vv = P.V[b];
+            const double hdt = 0.5 * sp.dt;
+            double vx = Vv[c.i] + hdt * P.A[c.i];
+            double vy = Vv[vt + c.i] + hdt * P.A[vt + c.i];
+            double vz = Vv[2 * vt + c.i] + hdt * P.A[2 * vt + c.i];
+            x = wrap_box(x + vx * sp.dt, sp.L[0]);
+            y = wrap_box(y + vy * sp.dt, sp.L[1]);
+            z = wrap_box(z + vz * sp.dt, sp.L[2]);
+            Vv[c.i] = vx;
+            Vv[vt + c.i] = vy;
+            Vv[2 * vt + c.i] = vz;
+            X[c.i] = x;
+            X[vt + c.i] = y;
+            X[2 * vt + c.i] = z;
+        }
+        const int cx = cell_axis(x, sp.inv_h[0], sp.nc[0]);
+        const int cy = cell_axis(y, sp.inv_h[1], sp.nc[1]);
+        const int cz = cell_axis(z, sp.inv_h[2], sp.nc[2]);
+        cell = cx + sp.nc[0] * (cy + sp.nc[1] * cz);
+    } else {
+        cell = sp.ncell;  // padding slots gather in one extra cell
+    }
+    P.cell_tmp[c.i] = cell;
+    P.arr[c.i] = atomicAdd(&P.count[sp.coff + cell], 1);
+}
+
+__global__ void k_bin_scan(PoolDev P, int nslots)
+{
+    __shared__ int lds[17];
+    const int s = blockIdx.x;
+    if (s >= nslots) return;
+    const SysParams& sp = P.sp[s];
+    SysState* st = P.st + s;
+    if (!sp.active || st->remaining <= 0 || (st->status & ST_NONFINITE)) return;
+    const int M = sp.ncell + 1;
+    int* cnt = P.count + sp.coff;
+    int* cs = P.cstart + sp.coff;
+    const int T = blockDim.x;
+    const int per = (M + T - 1) / T;
+    const int lo = threadIdx.x * per, hi = min(M, lo + per);
+    int sum = 0;
+    for (int c = lo; c < hi; ++c) sum += cnt[c];
+    int tot;
+    int run = sp.voff + block_exclusive_scan(sum, lds, &tot);
+    for (int c = lo; c < hi; ++c) {
+        int k = cnt[c];
+        cs[c] = run;
+        run += k;
+        cnt[c] = 0;
+    }
+    if (threadIdx.x == 0) {
+        cs[M] = sp.voff + tot;
+        st->sbuf_prev = st->sbuf;
+        st->sbuf ^= 1;
+        st->status &= ~ST_HALT;
+        st->status &= ~ST_OVERFLOW;
+        if (st->phase == PH_REST) st->phase = PH_RUN;
+        st->rebins += 1;
+        st->max_nbr = 0;
+        st->steps_since = 0;
+    }
+}
+
+__global__ void k_bin_scatter(PoolDev P)
+{
+    SlotCtx c;
+    if (!rebuild_ctx(P, c)) return;
+    const SysParams& sp = P.sp[c.s];
+    const int cell = P.cell_tmp[c.i];
+    P.tmp[P.cstart[sp.coff + cell] + P.arr[c.i]] = c.i;
+}
+
+template <typename T>
+__global__ void k_bin_place(PoolDev P)
+{
+    using V = typename V4<T>::type;
+    SlotCtx c;
+    if (!rebuild_ctx(P, c)) return;
+    const SysParams& sp = P.sp[c.s];
+    const SysState& st = P.st[c.s];
+    const int vt = P.vt;
+    const int src = st.sbuf_prev, dst = st.sbuf;
+    const int o = P.tmp[c.i];
+    const int cell = P.cell_tmp[o];
+    const int b0 = P.cstart[sp.coff + cell], b1 = P.cstart[sp.coff + cell + 1];
+    const int* ids = P.id[src];
+    const int myid = ids[o];
+    int rank = 0;
+    for (int q = b0; q < b1; ++q) rank += (ids[P.tmp[q]] < myid);
+    const int d = b0 + rank;
+    const double* Xs = P.X[src];
+    const double* Vs = P.V[src];
+    double* Xd = P.X[dst];
+    double* Vd = P.V[dst];
+    const double x = Xs[o], y = Xs[vt + o], z = Xs[2 * vt + o];
+    Xd[d] = x;
+    Xd[vt + d] = y;
+    Xd[2 * vt + d] = z;
+    Vd[d] = Vs[o];
+    Vd[vt + d] = Vs[vt + o];
+    Vd[2 * vt + d] = Vs[2 * vt + o];
+    P.id[dst][d] = myid;
+    P.travel[d] = 0.0f;
+    V* Lc = (V*)P.L[st.lbuf];
+    if (cell < sp.ncell) {
+        const int cx = cell % sp.nc[0], cy = (cell / sp.nc[0]) % sp.nc[1],
+                  cz = cell / (sp.nc[0] * sp.nc[1]);
+        P.cref[d] = cx | (cy << 10) | (cz << 20);
+        P.cell_lin[d] = cell;
+        Lc[d] = make4<T>(local_axis(x, cx, sp.h[0], sp.L[0], sp.invL[0]),
+                         local_axis(y, cy, sp.h[1], sp.L[1], sp.invL[1]),
+                         local_axis(z, cz, sp.h[2], sp.L[2], sp.invL[2]));
+    } else {
+        P.cref[d] = 0;
+        P.cell_lin[d] = -1;
+        Lc[d] = make4<T>(0.0, 0.0, 0.0);
+    }
+}
+
+template <typename T>
+__global__ void k_list_build(PoolDev P)
+{
+    using V = typename V4<T>::type;
+    SlotCtx c;
+    if (!rebuild_ctx(P, c)) return;
+    const SysParams& sp = P.sp[c.s];
+    const SysState& st = P.st[c.s];
+    const int vt = P.vt;
+    int cnt = 0;
+    if (c.li < sp.nv) {
+        const V* Lc = (const V*)P.L[st.lbuf];
+        const V me = Lc[c.i];
+        const int cr = P.cref[c.i];
+        const int cx = cr & 1023, cy = (cr >> 10) & 1023, cz = cr >> 20;
+        const T rl2 = (T)sp.rl2;
+        const int* cs = P.cstart + sp.coff;
+        const int* wcs = P.wcstart + sp.wcoff;
+        for (int dz = -1; dz <= 1; ++dz) {
+            const int jz = wrap_cell(cz + dz, sp.nc[2]);
+            const T sz = (T)(-dz * sp.h[2]);
+            for (int dy = -1; dy <= 1; ++dy) {
+                const int jy = wrap_cell(cy + dy, sp.nc[1]);
+                const T sy = (T)(-dy * sp.h[1]);
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const int jx = wrap_cell(cx + dx, sp.nc[0]);
+                    const T sx = (T)(-dx * sp.h[0]);
+                    const unsigned code = (unsigned)((dx + 1) + 3 * (dy + 1) + 9 * (dz + 1));
+                    const int cl = jx + sp.nc[0] * (jy + sp.nc[1] * jz);
+                    const int j1 = cs[cl + 1];
+                    for (int j = cs[cl]; j < j1; ++j) {
+                        if (j == c.i) continue;
+                        const V o = Lc[j];
+                        const T ex = me.x - o.x + sx, ey = me.y - o.y + sy, ez = me.z - o.z + sz;
+                        if (ex * ex + ey * ey + ez * ez < rl2) {
+                            if (cnt < P.cap) P.list[(size_t)cnt * vt + c.i] = (unsigned)j | (code << kIndexBits);
+                            ++cnt;
+                        }
+                    }
+                    const int w1 = wcs[cl + 1];
+                    for (int w = wcs[cl]; w < w1; ++w) {
+                        const V o = Lc[vt + w];
+                        const T ex = me.x - o.x + sx, ey = me.y - o.y + sy, ez = me.z - o.z + sz;
+                        if (ex * ex + ey * ey + ez * ez < rl2) {
+                            if (cnt < P.cap)
+                                P.list[(size_t)cnt * vt + c.i] = (unsigned)(vt + w) | (code << kIndexBits);
+                            ++cnt;
+                        }
+                    }
+                }
+            }
+        }
+        P.nlist[c.i] = min(cnt, P.cap);
+    } else {
+        P.nlist[c.i] = 0;
+    }
+    const int m = wave_max(cnt);
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(&P.st[c.s].max_nbr, m);
+        if (m > P.cap) atomicOr(&P.st[c.s].status, ST_OVERFLOW);
+    }
+}
+
+hipError_t launch_rebuild(const PoolDev& P, int nslots, int precision, hipStream_t s)
+{
+    const int G = ((P.nlog + 7) / 8) * 8;
+    const int B = P.block;
+    hipLaunchKernelGGL(k_bin_count, dim3(G), dim3(B), 0, s, P);
+    hipLaunchKernelGGL(k_bin_scan, dim3(nslots), dim3(1024), 0, s, P, nslots);
+    hipLaunchKernelGGL(k_bin_scatter, dim3(G), dim3(B), 0, s, P);
+    if (precision == 1) {
+        hipLaunchKernelGGL(k_bin_place<float>, dim3(G), dim3(B), 0, s, P);
+        hipLaunchKernelGGL(k_list_build<float>, dim3(G), dim3(B), 0, s, P);
+    } else {
+        hipLaunchKernelGGL(k_bin_place<double>, dim3(G), dim3(B), 0, s, P);
+        hipLaunchKernelGGL(k_list_build<double>, dim3(G), dim3(B), 0, s, P);
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Step: forces (F1) + second half-kick (F3) [+ next drift and half-kick (F2)]
+// ---------------------------------------------------------------------------
+
+// Pair scalars: w such that the force on i is w * d, and the pair energy u.
+template <typename T>
+__device__ __forceinline__ T inv_of(T r2);
+template <>
+__device__ __forceinline__ float inv_of<float>(float r2) { return __builtin_amdgcn_rcpf(r2); }
+template <>
+__device__ __forceinline__ double inv_of<double>(double r2) { return 1.0 / r2; }
+
+template <typename T>
+__global__ void __launch_bounds__(1024) k_step(PoolDev P)
+{
+    using V = typename V4<T>::type;
+    __shared__ V tab[27];
+    __shared__ double red[3][16];
+    __shared__ int flag_or[16];
+    __shared__ int am_last;
+
+    const int lb = logical_block();
+    if (lb >= P.nlog) return;
+    const int s = P.blk_sys[lb];
+    const SysParams& sp = P.sp[s];
+    const SysState st = P.st[s];
+    if (st.remaining <= 0 || (st.status & (ST_HALT | ST_OVERFLOW | ST_NONFINITE))) return;
+
+    const int tid = threadIdx.x;
+    if (tid < 27) {
+        const int dx = tid % 3 - 1, dy = (tid / 3) % 3 - 1, dz = tid / 9 - 1;
+        tab[tid] = make4<T>(-dx * sp.h[0], -dy * sp.h[1], -dz * sp.h[2]);
+    }
+    __syncthreads();
+
+    const bool init = st.phase == PH_INIT;
+    const bool last = !init && st.remaining == 1;
+    const long long kstep = init ? 0 : st.step + 1;
+    const bool doE = init || last || (sp.energy_every > 0 && (kstep % sp.energy_every) == 0);
+    const int vt = P.vt;
+    const int li = (lb - sp.boff) * (int)blockDim.x + tid;
+    const int i = sp.voff + li;
+
+    double ke = 0.0, evv = 0.0, evw = 0.0;
+    int flags = 0;
+    if (li < sp.nv) {
+        const V* Lc = (const V*)P.L[st.lbuf];
+        const V me = Lc[i];
+        double* X = P.X[st.sbuf];
+        double* Vv = P.V[st.sbuf];
+        const double xi = X[i], yi = X[vt + i], zi = X[2 * vt + i];
+        const int n = P.nlist[i];
+        const T rc2 = (T)sp.rc2;
+        const T Av = (T)sp.A, Bv = (T)sp.B, Aw = (T)sp.Aw, Bw = (T)sp.Bw;
+        const T ucv = (T)sp.uc, ucw = (T)sp.ucw;
+        const T band = (T)(4.0e-6 * sp.rc2);
+        double fx = 0.0, fy = 0.0, fz = 0.0;
+        const unsigned* lst = P.list + i;
+        for (int k = 0; k < n; ++k) {
+            const unsigned e = lst[(size_t)k * vt];
+            const int j = (int)(e & kIndexMask);
+            const V o = Lc[j];
+            const V sh = tab[e >> kIndexBits];
+            const T dx = me.x - o.x + sh.x;
+            const T dy = me.y - o.y + sh.y;
+            const T dz = me.z - o.z + sh.z;
+            const T r2 = dx * dx + dy * dy + dz * dz;
+            const bool wall = j >= vt;
+            bool in = r2 < rc2;
+            if (sizeof(T) == 4 && fabs(r2 - rc2) < band) {
+                // FP64 re-test of a pair at the cutoff edge
+                double ox, oy, oz;
+                if (wall) {
+                    const int w = j - vt;
+                    ox = P.WX[w];
+                    oy = P.WX[P.wt + w];
+                    oz = P.WX[2 * P.wt + w];
+                } else {
+                    ox = X[j];
+                    oy = X[vt + j];
+                    oz = X[2 * vt + j];
+                }
+                double ex = xi - ox, ey = yi - oy, ez = zi - oz;
+                ex -= sp.L[0] * rint(ex * sp.invL[0]);
+                ey -= sp.L[1] * rint(ey * sp.invL[1]);
+                ez -= sp.L[2] * rint(ez * sp.invL[2]);
+                in = ex * ex + ey * ey + ez * ez < sp.rc2;
+            }
+            if (in) {
+                const T A = wall ? Aw : Av;
+                const T B = wall ? Bw : Bv;
+                const T sr2 = inv_of<T>(r2);
+                const T sr6 = sr2 * sr2 * sr2;
+                const T w = sr2 * sr6 * ((T)12 * A * sr6 - (T)6 * B);
+                fx += (double)(w * dx);
+                fy += (double)(w * dy);
+                fz += (double)(w * dz);
+                if (doE) {
+                    const T u = sr6 * (A * sr6 - B) - (wall ? ucw : ucv);
+                    if (wall)
+                        evw += (double)u;
+                    else
+                        evv += 0.5 * (double)u;
+                }
+            }
+        }
+        const double ax = fx * sp.inv_mass, ay = fy * sp.inv_mass, az = fz * sp.inv_mass;
+        double vx = Vv[i], vy = Vv[vt + i], vz = Vv[2 * vt + i];
+        if (init) {
+            P.A[i] = ax;
+            P.A[vt + i] = ay;
+            P.A[2 * vt + i] = az;
+        } else {
+            const double hdt = 0.5 * sp.dt;
+            vx += hdt * ax;  // F3: v(t) = v(t - dt/2) + a(t) dt/2
+            vy += hdt * ay;
+            vz += hdt * az;
+        }
+        ke = 0.5 * sp.mass * (vx * vx + vy * vy + vz * vz);
+        if (!init) {
+            if (last) {
+                Vv[i] = vx;
+                Vv[vt + i] = vy;
+                Vv[2 * vt + i] = vz;
+                P.A[i] = ax;
+                P.A[vt + i] = ay;
+                P.A[2 * vt + i] = az;
+            } else {
+                const double hdt = 0.5 * sp.dt;
+                vx += hdt * ax;  // F2 of the next step: v(t + dt/2) = v(t) + a(t) dt/2
+                vy += hdt * ay;
+                vz += hdt * az;
+                const double x = wrap_box(xi + vx * sp.dt, sp.L[0]);
+                const double y = wrap_box(yi + vy * sp.dt, sp.L[1]);
+                const double z = wrap_box(zi + vz * sp.dt, sp.L[2]);
+                Vv[i] = vx;
+                Vv[vt + i] = vy;
+                Vv[2 * vt + i] = vz;
+                X[i] = x;
+                X[vt + i] = y;
+                X[2 * vt + i] = z;
+                const int cr = P.cref[i];
+                const int cx = cr & 1023, cy = (cr >> 10) & 1023, cz = cr >> 20;
+                V* Ln = (V*)P.L[st.lbuf ^ 1];
+                Ln[i] = make4<T>(local_axis(x, cx, sp.h[0], sp.L[0], sp.invL[0]),
+                                 local_axis(y, cy, sp.h[1], sp.L[1], sp.invL[1]),
+                                 local_axis(z, cz, sp.h[2], sp.L[2], sp.invL[2]));
+                const float tr = P.travel[i] + (float)(sqrt(vx * vx + vy * vy + vz * vz) * sp.dt);
+                P.travel[i] = tr;
+                if (tr > sp.half_skin) flags |= ST_HALT;
+            }
+        }
+        if (!isfinite(fx + fy + fz) || !isfinite(ke)) flags |= ST_NONFINITE;
+    }
+
+    // workgroup reductions (fixed order: lane tree, then waves in order)
+    const int lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
+    flags = wave_or(flags);
+    if (lane == 0) flag_or[wave] = flags;
+    if (doE) {
+        ke = wave_sum(ke);
+        evv = wave_sum(evv);
+        evw = wave_sum(evw);
+        if (lane == 0) {
+            red[0][wave] = ke;
+            red[1][wave] = evv;
+            red[2][wave] = evw;
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int f = 0;
+        for (int w = 0; w < nwave; ++w) f |= flag_or[w];
+        if (f) atomicOr(&P.st[s].status_next, f);
+        if (doE) {
+            double a = 0.0, b = 0.0, c = 0.0;
+            for (int w = 0; w < nwave; ++w) {
+                a += red[0][w];
+                b += red[1][w];
+                c += red[2][w];
+            }
+            double* pp = P.partial + 3 * (size_t)(sp.pboff + (lb - sp.boff));
+            pp[0] = a;
+            pp[1] = b;
+            pp[2] = c;
+        }
+        __threadfence();
+        const int prev = atomicAdd(&P.st[s].blocks_done, 1);
+        am_last = (prev == sp.nblk - 1);
+    }
+    __syncthreads();
+    if (!am_last) return;
+
+    // last workgroup of this system: finish the energy sums and the step
+    __threadfence();
+    if (doE) {
+        double a = 0.0, b = 0.0, c = 0.0;
+        const double* pp = P.partial + 3 * (size_t)sp.pboff;
+        for (int q = tid; q < sp.nblk; q += blockDim.x) {
+            a += atomic_load_f64(pp + 3 * q);
+            b += atomic_load_f64(pp + 3 * q + 1);
+            c += atomic_load_f64(pp + 3 * q + 2);
+        }
+        a = wave_sum(a);
+        b = wave_sum(b);
+        c = wave_sum(c);
+        if (lane == 0) {
+            red[0][wave] = a;
+            red[1][wave] = b;
+            red[2][wave] = c;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        SysState* sw = P.st + s;
+        if (doE) {
+            double a = 0.0, b = 0.0, c = 0.0;
+            for (int w = 0; w < nwave; ++w) {
+                a += red[0][w];
+                b += red[1][w];
+                c += red[2][w];
+            }
+            EnergyRec r;
+            r.step = kstep;
+            r.ke = a;
+            r.pe_vv = b;
+            r.pe_vw = c;
+            P.erec[sp.ering_off + (st.nrec % sp.ering_cap)] = r;
+            sw->nrec = st.nrec + 1;
+        }
+        const int f = __hip_atomic_load(&sw->status_next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        sw->status = st.status | f;
+        sw->status_next = 0;
+        sw->blocks_done = 0;
+        if (init) {
+            sw->phase = PH_REST;
+            sw->remaining = 0;
+        } else {
+            sw->step = kstep;
+            sw->remaining = st.remaining - 1;
+            sw->steps_since = st.steps_since + 1;
+            if (last) {
+                sw->phase = PH_REST;
+            } else {
+                sw->lbuf = st.lbuf ^ 1;
+            }
+        }
+    }
+}
+
+hipError_t launch_step(const PoolDev& P, int precision, hipStream_t s, hipEvent_t ev0,
+                       hipEvent_t ev1)
+{
+    const int G = ((P.nlog + 7) / 8) * 8;
+    const int B = P.block;
+    if (ev0 && ev1) {
+        if (precision == 1)
+            hipExtLaunchKernelGGL(k_step<float>, dim3(G), dim3(B), 0, s, ev0, ev1, 0, P);
+        else
+            hipExtLaunchKernelGGL(k_step<double>, dim3(G), dim3(B), 0, s, ev0, ev1, 0, P);
+    } else {
+        if (precision == 1)
+            hipLaunchKernelGGL(k_step<float>, dim3(G), dim3(B), 0, s, P);
+        else
+            hipLaunchKernelGGL(k_step<double>, dim3(G), dim3(B), 0, s, P);
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Host-requested state changes and readbacks
+// ---------------------------------------------------------------------------
+
+__global__ void k_set_run(PoolDev P, int slot, int add_steps, int phase_init)
+{
+    SysState* st = P.st + slot;
+    if (phase_init) {
+        st->phase = PH_INIT;
+        st->remaining = 1;
+    } else {
+        st->remaining += add_steps;
+    }
+}
+
+hipError_t launch_set_run(const PoolDev& P, int slot, int add_steps, int phase_init, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_set_run, dim3(1), dim3(1), 0, s, P, slot, add_steps, phase_init);
+    return hipGetLastError();
+}
+
+// which: 0 positions, 1 velocities, 2 forces (m a)
+__global__ void k_unpermute(PoolDev P, int slot, int which, double* out, int n)
+{
+    const SysParams& sp = P.sp[slot];
+    const SysState& st = P.st[slot];
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= sp.nv || p >= n) return;
+    const int i = sp.voff + p;
+    const int vt = P.vt;
+    const int id = P.id[st.sbuf][i];
+    if (id < 0 || id >= n) return;
+    const double* src = which == 0 ? P.X[st.sbuf] : which == 1 ? P.V[st.sbuf] : P.A;
+    const double m = which == 2 ? sp.mass : 1.0;
+    out[3 * (size_t)id] = m * src[i];
+    out[3 * (size_t)id + 1] = m * src[vt + i];
+    out[3 * (size_t)id + 2] = m * src[2 * vt + i];
+}
+
+hipError_t launch_unpermute(const PoolDev& P, int slot, int which, double* out, int n,
+                            hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_unpermute, dim3((n + 255) / 256), dim3(256), 0, s, P, slot, which, out, n);
+    return hipGetLastError();
+}
+
+__global__ void k_wall_unpermute(PoolDev P, int slot, double* out, int n)
+{
+    const SysParams& sp = P.sp[slot];
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= sp.nw || p >= n) return;
+    const int w = sp.woff + p;
+    const int id = P.wid[w];
+    if (id < 0 || id >= n) return;
+    out[3 * (size_t)id] = P.WX[w];
+    out[3 * (size_t)id + 1] = P.WX[P.wt + w];
+    out[3 * (size_t)id + 2] = P.WX[2 * P.wt + w];
+}
+
+hipError_t launch_wall_unpermute(const PoolDev& P, int slot, double* out, int n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_wall_unpermute, dim3((n + 255) / 256), dim3(256), 0, s, P, slot, out, n);
+    return hipGetLastError();
+}
+
+// Pairs within the cutoff found through the lists, tested in FP64 on the
+// master positions: out_pairs holds (kind, a, b) triples; counts[0] = total.
+__global__ void k_debug_pairs(PoolDev P, int slot, int* out, int cap, int* counts)
+{
+    const SysParams& sp = P.sp[slot];
+    const SysState& st = P.st[slot];
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= sp.nv) return;
+    const int vt = P.vt;
+    const int i = sp.voff + p;
+    const double* X = P.X[st.sbuf];
+    const int* ids = P.id[st.sbuf];
+    const int n = P.nlist[i];
+    const double xi = X[i], yi = X[vt + i], zi = X[2 * vt + i];
+    for (int k = 0; k < n; ++k) {
+        const unsigned e = P.list[(size_t)k * vt + i];
+        const int j = (int)(e & kIndexMask);
+        double ox, oy, oz;
+        int kind, b;
+        if (j >= vt) {
+            const int w = j - vt;
+            ox = P.WX[w];
+            oy = P.WX[P.wt + w];
+            oz = P.WX[2 * P.wt + w];
+            kind = 1;
+            b = P.wid[w];
+        } else {
+            ox = X[j];
+            oy = X[vt + j];
+            oz = X[2 * vt + j];
+            kind = 0;
+            b = ids[j];
+            if (!(ids[i] < b)) continue;
+        }
+        double ex = xi - ox, ey = yi - oy, ez = zi - oz;
+        ex -= sp.L[0] * rint(ex * sp.invL[0]);
+        ey -= sp.L[1] * rint(ey * sp.invL[1]);
+        ez -= sp.L[2] * rint(ez * sp.invL[2]);
+        if (ex * ex + ey * ey + ez * ez < sp.rc2) {
+            const int q = atomicAdd(counts, 1);
+            if (q < cap) {
+                out[3 * q] = kind;
+                out[3 * q + 1] = ids[i];
+                out[3 * q + 2] = b;
+            }
+        }
+    }
+}
+
+hipError_t launch_debug_pairs(const PoolDev& P, int slot, int nv, int* out, int cap, int* counts,
+                              hipStream_t s)
+{
+    if (nv <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_debug_pairs, dim3((nv + 255) / 256), dim3(256), 0, s, P, slot, out, cap,
+                       counts);
+    return hipGetLastError();
+}
+
+// Caller-order AoS positions/velocities -> the system's SoA slots (unsorted;
+// id = caller index); padding slots get ids nv .. vcap-1 and zero state.
+__global__ void k_copy_in(PoolDev P, int slot, const double* pos, const double* vel, int n)
+{
+    const SysParams& sp = P.sp[slot];
+    const SysState& st = P.st[slot];
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= sp.vcap) return;
+    const int i = sp.voff + p;
+    const int vt = P.vt;
+    double* X = P.X[st.sbuf];
+    double* Vv = P.V[st.sbuf];
+    if (p < n) {
+        X[i] = pos[3 * (size_t)p];
+        X[vt + i] = pos[3 * (size_t)p + 1];
+        X[2 * vt + i] = pos[3 * (size_t)p + 2];
+        Vv[i] = vel[3 * (size_t)p];
+        Vv[vt + i] = vel[3 * (size_t)p + 1];
+        Vv[2 * vt + i] = vel[3 * (size_t)p + 2];
+    } else {
+        X[i] = X[vt + i] = X[2 * vt + i] = 0.0;
+        Vv[i] = Vv[vt + i] = Vv[2 * vt + i] = 0.0;
+    }
+    P.A[i] = P.A[vt + i] = P.A[2 * vt + i] = 0.0;
+    P.id[st.sbuf][i] = p;
+    P.travel[i] = 0.0f;
+}
+
+hipError_t launch_copy_in(const PoolDev& P, int slot, const double* pos, const double* vel, int n,
+                          int vcap, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_copy_in, dim3((vcap + 255) / 256), dim3(256), 0, s, P, slot, pos, vel, n);
+    return hipGetLastError();
+}
+
+}  // namespace pmd
