@@ -1,0 +1,217 @@
+#!/usr/bin/env python3
+"""Throughput of the pore-MD hot path on one MI355X.
+
+Workload: the single large system -- a 128^3 box with a slit pore (two
+simple-cubic wall slabs 4 thick, gap 8), 262144 vapour atoms placed at random
+clear of each other and of the walls, T* = 1.2, dt = 0.005, reduced LJ units.
+The headline is the mixed-precision path (FP32 pair forces, FP64 sums,
+integration and energies); the plain FP64 path is timed beside it on the
+same input.  A "step" is one velocity-Verlet step of every atom (neighbour
+list rebuilds included); throughput is vapour atom-steps per second with the
+state resident in device memory when the timed region starts.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# survey §8(d) algorithmic bytes per vapour atom-step (mixed / FP64)
+ALG_BYTES = {"mixed": 120.0, "fp64": 144.0}
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def energy_drift(tot, burn):
+    seg = np.asarray(tot[burn:], dtype=np.float64)
+    if seg.shape[0] < 3:
+        return None, None
+    t = np.arange(seg.shape[0], dtype=np.float64)
+    slope = np.polyfit(t, seg, 1)[0]
+    return float(abs(slope) * (seg.shape[0] - 1) / abs(seg[0])), float(
+        np.abs(seg - seg[0]).max() / abs(seg[0]))
+
+
+def run_path(poremd, desc, prec, steps, warmup, energy_every, tuning_kw):
+    import torch
+
+    stream = torch.cuda.Stream()
+    tun = poremd.make_tuning(energy_every=energy_every, **tuning_kw)
+    t0 = time.perf_counter()
+    s = poremd.System.from_desc(desc, precision=prec, tuning=tun, stream=stream.cuda_stream)
+    log("[%s] created in %.2f s (walls %d)" % (prec, time.perf_counter() - t0, s.n_wall))
+    if warmup:
+        s.step(warmup)
+        s.sync()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    e0.record(stream)
+    s.step(steps)
+    s.sync()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms = e0.elapsed_time(e1)
+    hist = s.energy_history()
+    rebuilds, maxlen = poremd.pmd_debug_lists(s.h)
+    out = dict(ms=ms, wall_s=wall, hist=hist, rebuilds=rebuilds, max_list=maxlen, sys=s)
+    log("[%s] %d steps: %.3f ms (%.2f us/step), wall %.3f s, rebuilds %d"
+        % (prec, steps, ms, 1000 * ms / steps, wall, rebuilds))
+    return out
+
+
+def kernel_time(poremd, s, steps):
+    poremd.pmd_timing_enable(s.h, True)
+    s.step(steps)
+    s.sync()
+    n, mean_ms = poremd.pmd_kernel_time(s.h)
+    poremd.pmd_timing_enable(s.h, False)
+    return n, mean_ms
+
+
+def cpu_baseline(desc, sample_atoms, seed=0):
+    import oracle
+
+    rng = np.random.default_rng(seed)
+    sel = np.sort(rng.choice(desc.n, sample_atoms, replace=False))
+    p = oracle.make_params(desc.params.box)
+    walls = oracle.wall_lattice(oracle.make_pore(desc.pore.kind, desc.pore.lattice_a,
+                                                 desc.pore.slab_center_z,
+                                                 desc.pore.slab_thickness, desc.pore.r0,
+                                                 desc.pore.r1, desc.pore.slit_gap),
+                                desc.params.box)
+    t0 = time.perf_counter()
+    oracle.forces_subset(desc.x, walls, p, sel)
+    dt = time.perf_counter() - t0
+    return dict(value=sample_atoms / dt, unit="atom-steps/s", cores=oracle.num_threads(),
+                kind="oracle",
+                sample="F1 force sums (all %d partners each, 99.9%% of an oracle step) for %d "
+                       "randomly chosen vapour atoms of the same system, %.1f s"
+                       % (desc.n + walls.shape[0], sample_atoms, dt))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--n", type=int, default=262144)
+    ap.add_argument("--box", type=float, default=128.0)
+    ap.add_argument("--energy-every", type=int, default=10)
+    ap.add_argument("--skin", type=float, default=0.0)
+    ap.add_argument("--rebin-every", type=int, default=0)
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=16384)
+    ap.add_argument("--timing-steps", type=int, default=500)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(independent replicas shard trivially; see the design notes).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1812_07993_amd import poremd, synth
+
+    poremd.load()
+    assert torch.cuda.is_available(), "needs a GPU"
+    t0 = time.perf_counter()
+    desc = synth.slit_large(n=args.n, box=args.box)
+    log("inputs: %d vapour atoms, box %g, generated in %.1f s"
+        % (desc.n, args.box, time.perf_counter() - t0))
+    tkw = dict(skin=args.skin, rebin_every=args.rebin_every, block=args.block)
+
+    res = {}
+    for prec in (["mixed"] if args.no_fp64 else ["mixed", "fp64"]):
+        r = run_path(poremd, desc, prec, args.steps, args.warmup, args.energy_every, tkw)
+        n_launch, kms = kernel_time(poremd, r["sys"], args.timing_steps)
+        r["kernel_ms"] = kms
+        r["kernel_launches"] = n_launch
+        log("[%s] step kernel mean %.4f ms over %d launches" % (prec, kms, n_launch))
+        E = r["hist"]
+        tot = E["etotal"]
+        burn = max(0, int(np.searchsorted(E["step"], args.warmup + 100)))
+        trend, maxdev = energy_drift(tot, burn)
+        r["drift_trend"], r["drift_max"] = trend, maxdev
+        res[prec] = r
+
+    # force error of the mixed path against the FP64 path at identical positions
+    eps_f = None
+    if "fp64" in res:
+        X = res["mixed"]["sys"].positions()
+        V = res["mixed"]["sys"].velocities()
+        params_m, pore = poremd.params_of(desc, "mixed")
+        params_d, _ = poremd.params_of(desc, "fp64")
+        a = poremd.System(params_m, pore, X, V)
+        b = poremd.System(params_d, pore, X, V)
+        Fm, Fd = a.forces(), b.forces()
+        eps_f = float(np.linalg.norm(Fm - Fd) / np.linalg.norm(Fd))
+        a.close()
+        b.close()
+        log("force error mixed vs fp64 at identical positions: %.3e" % eps_f)
+
+    m = res["mixed"]
+    n = desc.n
+    value = n * args.steps / (m["ms"] / 1000.0)
+    alg = ALG_BYTES["mixed"] * n
+    achieved = alg / (m["kernel_ms"] / 1000.0) / 1e9
+    out = {
+        "metric": "atom-steps/s mixed vs plain FP64 at <=1e-4 energy drift; served p50/p99 latency",
+        "value": value,
+        "unit": "atom-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": m["ms"] / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32-pair/f64-accumulate",
+        "data": "synthetic",
+        "config": {"workload": "slit pore, 128^3 box, %d vapour + %d wall atoms, T*=1.2, "
+                               "dt=0.005, mixed precision" % (n, m["sys"].n_wall),
+                   "n_vapour": n, "n_wall": m["sys"].n_wall, "box": args.box,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "kernel": "k_step<float>", "kernel_ms": m["kernel_ms"],
+                     "alg_bytes_per_atom_step": ALG_BYTES["mixed"]},
+        "accuracy": {"mixed_drift_trend": m["drift_trend"], "mixed_drift_max": m["drift_max"],
+                     "force_err_mixed_vs_fp64": eps_f},
+        "detail": {"mixed_rebuilds": m["rebuilds"], "mixed_max_list": m["max_list"]},
+    }
+    if "fp64" in res:
+        d = res["fp64"]
+        out["fp64"] = {"value": n * args.steps / (d["ms"] / 1000.0),
+                       "ms_per_step": d["ms"] / args.steps, "kernel_ms": d["kernel_ms"],
+                       "drift_trend": d["drift_trend"], "drift_max": d["drift_max"],
+                       "roofline_frac": ALG_BYTES["fp64"] * n / (d["kernel_ms"] / 1000.0) / 1e9
+                       / PEAK_HBM_GBS}
+        out["mixed_over_fp64"] = out["value"] / out["fp64"]["value"]
+    for r in res.values():
+        r["sys"].close()
+    if not args.no_cpu:
+        log("timing the oracle on the host ...")
+        out["cpu_baseline"] = cpu_baseline(desc, args.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -104,7 +104,9 @@ typedef struct {
  * radius of the neighbour lists beyond the cutoff; rebin_every: steps
  * between neighbour-list rebuilds (a rebuild also happens early whenever an
  * atom has travelled more than skin/2 since the last one); block: threads
- * per workgroup (64..1024, multiple of 64); list_cap: neighbour-list slots
+ * per workgroup of the force kernels (64, 128 or 256; each workgroup owns
+ * one brick of cells, sized to hold about 0.8 x block atoms); list_cap:
+ * neighbour-list slots
  * per atom; energy_every: record energies every k steps (the last step of
  * every pmd_step call is always recorded). */
 typedef struct {
@@ -195,11 +197,13 @@ int pmd_kernel_time(pmd_system *sys, int64_t *launches, double *mean_ms);
 
 /* ---- Test-only debug exports (same library; unstable) ------------------- */
 
-/* Cell binning after the last rebuild: cell_of_atom[n] (caller order),
- * cell_start[n_cells + 1] (offsets into the cell-sorted order), perm[n]
- * (caller indices in cell-sorted order), and the grid: ncell[3], inv[3]
- * (cells per unit length, inv_k = ncell_k / L_k).  Positions used are those
- * at the last rebuild. */
+/* Cell binning after the last rebuild.  cell_of_atom[n]: linear cell
+ * cx + ncell_0 (cy + ncell_1 cz) of each atom (caller order); perm[n]: caller
+ * indices in storage order (cells grouped in bricks, ascending caller index
+ * inside a cell); cell_start[n_cells + 1]: storage position of the first
+ * atom of each linear cell (the last entry is n); ncell[3] and inv[3] (cells
+ * per unit length, inv_k = ncell_k / L_k) describe the grid.  Positions used
+ * are those at the last rebuild. */
 int pmd_debug_cells(pmd_system *sys, int32_t *cell_of_atom, int64_t n,
                     int32_t *cell_start, int64_t n_cells_p1, int32_t *perm,
                     int32_t *ncell, double *inv);

@@ -13,7 +13,10 @@
 namespace pmd {
 
 constexpr int kPad = 256;            // vapour slots per system are padded to this
-constexpr int kMaxBlock = 1024;
+constexpr int kChunk = 16;           // atoms per entry of the chunk -> system table
+constexpr int kLanes = 4;            // lanes per atom in the list-build and step kernels
+constexpr int kTile = 4096;          // cells per workgroup of the cell-count scan
+constexpr int kRebuildBlock = 256;   // threads per workgroup of the per-atom rebuild kernels
 constexpr unsigned kIndexBits = 27;  // neighbour-list entry: index | code << 27
 constexpr unsigned kIndexMask = (1u << kIndexBits) - 1u;
 
@@ -26,7 +29,8 @@ enum Phase : int {
 enum Status : int {
     ST_HALT = 1,       // an atom travelled more than skin/2 since the last rebuild
     ST_OVERFLOW = 2,   // a neighbour list exceeded its capacity
-    ST_NONFINITE = 4   // a non-finite force or position appeared
+    ST_NONFINITE = 4,  // a non-finite force or position appeared
+    ST_TILE = 8        // a brick's halo did not fit the LDS tile
 };
 
 // Per-system constants (set on the host at admission).
@@ -37,12 +41,19 @@ struct SysParams {
     double inv_h[3];    // nc / L, used to bin
     int nc[3];
     int ncell;          // nc0 * nc1 * nc2
+    int bdim[3];        // cells per brick along each axis
+    int nbk[3];         // bricks along each axis (edge bricks may be partial)
+    int nbrick;         // nbk0 * nbk1 * nbk2
+    int bcells;         // bdim0 * bdim1 * bdim2
+    int nkey;           // nbrick * bcells: cells are numbered brick by brick
+    int broff;          // first workgroup (brick) of this system in the pool
     int voff, nv, vcap; // vapour slots [voff, voff + vcap), real atoms first nv after sorting
     int woff, nw;       // wall slots [woff, woff + nw)
-    int coff;           // vapour cell_start base: ncell + 2 entries (cells, padding cell, end)
-    int wcoff;          // wall cell_start base: ncell + 1 entries
-    int boff, nblk;     // logical workgroups [boff, boff + nblk) of this system
-    int pboff;          // energy partials base (one entry per workgroup)
+    int coff;           // vapour cell_start base: nkey + 2 entries (cells, padding cell, end)
+    int wcoff;          // wall cell_start base: ncell + 1 entries (linear cell order)
+    int choff;          // first chunk (kChunk atoms) of this system
+    int pboff;          // energy partials base (one entry per brick)
+    int toff, ntile;    // scan tiles [toff, toff + ntile)
     int ering_off, ering_cap;
     int energy_every;
     int active;         // 1 if the slot holds a system
@@ -51,6 +62,7 @@ struct SysParams {
     double uc, ucw;        // energy shift u(r_c) of each pair kind
     double rc2, rl2;       // cutoff^2, neighbour-list radius^2
     double dt, mass, inv_mass;
+    double rw2;            // wall-list radius^2, (r_c + skin/2)^2
     float half_skin;       // rebuild threshold on the travelled path
     float pad1;
 };
@@ -65,6 +77,7 @@ struct SysState {
     int sbuf;         // current state buffer (0/1)
     int sbuf_prev;    // state buffer before the last rebuild
     int blocks_done;  // finished workgroups of the step kernel (last-block pattern)
+    int tiles_done;   // finished workgroups of the cell-count scan
     int nrec;         // energy records written
     int max_nbr;      // longest neighbour list at the last rebuild
     int rebins;       // rebuilds so far
@@ -77,8 +90,8 @@ struct EnergyRec {
     double ke, pe_vv, pe_vw;
 };
 
-struct alignas(16) f4 { float x, y, z, w; };
-struct alignas(32) d4 { double x, y, z, w; };
+typedef float f4 __attribute__((ext_vector_type(4)));   // 16 bytes, one 128-bit load
+typedef double d4 __attribute__((ext_vector_type(4)));  // 32 bytes
 
 template <typename T> struct V4;
 template <> struct V4<float> { using type = f4; };
@@ -88,9 +101,16 @@ template <> struct V4<double> { using type = d4; };
 struct PoolDev {
     SysParams* sp;
     SysState* st;
-    const int* blk_sys;   // logical workgroup -> system slot
-    int nlog;             // logical workgroups
-    int block;            // threads per workgroup
+    const int* chunk_sys; // chunk of kChunk vapour slots -> system slot
+    int nchunk;           // chunks in use
+    const int* tile_sys;  // scan tile -> system slot
+    int ntile;            // scan tiles in use
+    const int* brick_sys; // brick (workgroup of the list and step kernels) -> system slot
+    int nbrick;           // bricks in use
+    int lds_atoms;        // capacity of the staged neighbour tile (atoms)
+    int wall_lds;         // capacity of the staged wall tile of the list build (walls)
+    int hmax;             // largest halo box (cells) of any resident system
+    int block;            // threads per workgroup of the brick kernels
     int vt, wt;           // vapour and wall slot capacity
     int cap;              // neighbour-list capacity per atom
     // per-atom state, double buffered by SysState::sbuf; SoA with stride vt
@@ -100,15 +120,19 @@ struct PoolDev {
     double* A;            // accelerations at rest (stride vt)
     float* travel;        // path length since the last rebuild
     int* cref;            // packed cell (cx | cy << 10 | cz << 20) at the last rebuild
-    int* cell_lin;        // linear cell index at the last rebuild
+    int* cell_lin;        // linear cell index cx + nx (cy + ny cz) at the last rebuild
     void* L[2];           // local coordinates (f4 or d4), vt + wt entries; walls at vt + w
     // binning scratch
     int* count;           // per cell (all systems' ranges)
-    int* cstart;          // per cell + padding + end
+    int* clocal;          // exclusive prefix of the counts inside each scan tile
+    int* ctile;           // per scan tile: sum, then global slot offset
+    int* cstart;          // per cell + padding + end: first slot (global)
     int* arr;             // arrival rank within the cell (per slot)
     int* tmp;             // slots in arrival order
-    int* cell_tmp;        // cell of each old slot
-    // neighbour lists, ELL layout list[k * vt + slot]
+    int* cell_tmp;        // cell key of each old slot
+    // neighbour lists, entry k of slot i at k * vt + i: vapour entries index
+    // the brick's staged tile, wall entries are wall slots; both carry the
+    // cell-offset code above kIndexBits.  nlist = n_vapour | n_wall << 16
     unsigned* list;
     int* nlist;
     // walls
@@ -145,8 +169,8 @@ hipError_t launch_unpermute(const PoolDev& P, int slot, int which, double* out_a
                             int n, hipStream_t s);
 hipError_t launch_wall_unpermute(const PoolDev& P, int slot, double* out_aos, int n,
                                  hipStream_t s);
-hipError_t launch_debug_pairs(const PoolDev& P, int slot, int nv, int* out_triples, int cap,
-                              int* counts, hipStream_t s);
+hipError_t launch_debug_pairs(const PoolDev& P, int slot, int precision, int* out_triples,
+                              int cap, int* counts, hipStream_t s);
 hipError_t launch_copy_in(const PoolDev& P, int slot, const double* pos_aos,
                           const double* vel_aos, int n, int vcap, hipStream_t s);
 

@@ -344,25 +344,53 @@ hipError_t launch_wall_bin(const PoolDev& P, int sys, const double* raw, int rs,
 // Rebuild: drift (run start) + bin count, scan, scatter, place, list build
 // ---------------------------------------------------------------------------
 
+// Cells are numbered brick by brick (bricks of bdim cells, x fastest inside
+// a brick and between bricks), so the atoms of one brick are contiguous
+// slots after sorting.
+__device__ __forceinline__ int cell_key(const SysParams& sp, int cx, int cy, int cz)
+{
+    const int Bx = cx / sp.bdim[0], By = cy / sp.bdim[1], Bz = cz / sp.bdim[2];
+    const int lx = cx - Bx * sp.bdim[0], ly = cy - By * sp.bdim[1], lz = cz - Bz * sp.bdim[2];
+    const int b = Bx + sp.nbk[0] * (By + sp.nbk[1] * Bz);
+    return b * sp.bcells + lx + sp.bdim[0] * (ly + sp.bdim[1] * lz);
+}
+
+__device__ __forceinline__ void key_cell(const SysParams& sp, int key, int& cx, int& cy, int& cz)
+{
+    const int b = key / sp.bcells, l = key - b * sp.bcells;
+    const int Bx = b % sp.nbk[0], By = (b / sp.nbk[0]) % sp.nbk[1], Bz = b / (sp.nbk[0] * sp.nbk[1]);
+    const int lx = l % sp.bdim[0], ly = (l / sp.bdim[0]) % sp.bdim[1], lz = l / (sp.bdim[0] * sp.bdim[1]);
+    cx = Bx * sp.bdim[0] + lx;
+    cy = By * sp.bdim[1] + ly;
+    cz = Bz * sp.bdim[2] + lz;
+}
+
 struct SlotCtx {
-    int s, lb, li, i;
+    int s, li, i;
 };
 
-// Resolve the calling thread's system and slot; false if the workgroup is
-// padding or its system has nothing to do.
+// Per-atom kernels: kRebuildBlock threads = kRebuildBlock slots of one system.
 __device__ __forceinline__ bool rebuild_ctx(const PoolDev& P, SlotCtx& c)
 {
     const int lb = logical_block();
-    if (lb >= P.nlog) return false;
-    const int s = P.blk_sys[lb];
+    const int chunk = lb * (kRebuildBlock / kChunk);
+    if (chunk >= P.nchunk) return false;
+    const int s = P.chunk_sys[chunk];
+    if (s < 0) return false;
     const SysState* st = P.st + s;
     if (st->remaining <= 0 || (st->status & ST_NONFINITE)) return false;
     const SysParams* sp = P.sp + s;
     c.s = s;
-    c.lb = lb;
-    c.li = (lb - sp->boff) * (int)blockDim.x + (int)threadIdx.x;
+    c.li = (chunk - sp->choff) * kChunk + (int)threadIdx.x;
     c.i = sp->voff + c.li;
     return true;
+}
+
+// First slot of cell c of a system between the scan and the placement
+// (tile offset + prefix inside the tile).
+__device__ __forceinline__ int cell_begin(const PoolDev& P, const SysParams& sp, int c)
+{
+    return P.ctile[sp.toff + c / kTile] + P.clocal[sp.coff + c];
 }
 
 __global__ void k_bin_count(PoolDev P)
@@ -397,49 +425,69 @@ __global__ void k_bin_count(PoolDev P)
         const int cx = cell_axis(x, sp.inv_h[0], sp.nc[0]);
         const int cy = cell_axis(y, sp.inv_h[1], sp.nc[1]);
         const int cz = cell_axis(z, sp.inv_h[2], sp.nc[2]);
-        cell = cx + sp.nc[0] * (cy + sp.nc[1] * cz);
+        cell = cell_key(sp, cx, cy, cz);
     } else {
-        cell = sp.ncell;  // padding slots gather in one extra cell
+        cell = sp.nkey;  // padding slots gather in one extra cell
     }
     P.cell_tmp[c.i] = cell;
     P.arr[c.i] = atomicAdd(&P.count[sp.coff + cell], 1);
 }
 
-__global__ void k_bin_scan(PoolDev P, int nslots)
+// One workgroup (1024 threads x 4 cells) per scan tile.  Each writes the
+// exclusive prefix of its tile and the tile sum; the last tile of a system
+// to finish turns the tile sums into slot offsets and advances the system's
+// rebuild state.  Counts run over ncell + 2 entries (cells, padding cell, a
+// zero end entry), so the prefix at ncell + 1 is the system's slot count.
+__global__ void __launch_bounds__(1024) k_bin_scan(PoolDev P)
 {
     __shared__ int lds[17];
-    const int s = blockIdx.x;
-    if (s >= nslots) return;
+    __shared__ int am_last;
+    const int tile = blockIdx.x;
+    if (tile >= P.ntile) return;
+    const int s = P.tile_sys[tile];
     const SysParams& sp = P.sp[s];
     SysState* st = P.st + s;
     if (!sp.active || st->remaining <= 0 || (st->status & ST_NONFINITE)) return;
-    const int M = sp.ncell + 1;
+    const int lt = tile - sp.toff;
+    const int M = sp.nkey + 2;
+    const int c0 = lt * kTile + 4 * (int)threadIdx.x;
     int* cnt = P.count + sp.coff;
-    int* cs = P.cstart + sp.coff;
-    const int T = blockDim.x;
-    const int per = (M + T - 1) / T;
-    const int lo = threadIdx.x * per, hi = min(M, lo + per);
-    int sum = 0;
-    for (int c = lo; c < hi; ++c) sum += cnt[c];
+    int v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = (c0 + k < M) ? cnt[c0 + k] : 0;
+    const int sum = v[0] + v[1] + v[2] + v[3];
     int tot;
-    int run = sp.voff + block_exclusive_scan(sum, lds, &tot);
-    for (int c = lo; c < hi; ++c) {
-        int k = cnt[c];
-        cs[c] = run;
-        run += k;
-        cnt[c] = 0;
-    }
+    int run = block_exclusive_scan(sum, lds, &tot);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (c0 + k < M) {
+            P.clocal[sp.coff + c0 + k] = run;
+            run += v[k];
+            cnt[c0 + k] = 0;
+        }
     if (threadIdx.x == 0) {
-        cs[M] = sp.voff + tot;
-        st->sbuf_prev = st->sbuf;
-        st->sbuf ^= 1;
-        st->status &= ~ST_HALT;
-        st->status &= ~ST_OVERFLOW;
-        if (st->phase == PH_REST) st->phase = PH_RUN;
-        st->rebins += 1;
-        st->max_nbr = 0;
-        st->steps_since = 0;
+        P.ctile[sp.toff + lt] = tot;
+        __threadfence();
+        const int prev = atomicAdd(&st->tiles_done, 1);
+        am_last = prev == sp.ntile - 1;
     }
+    __syncthreads();
+    if (!am_last || threadIdx.x != 0) return;
+    __threadfence();
+    int off = sp.voff;
+    for (int t = 0; t < sp.ntile; ++t) {
+        const int q = __hip_atomic_load(&P.ctile[sp.toff + t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        P.ctile[sp.toff + t] = off;
+        off += q;
+    }
+    st->tiles_done = 0;
+    st->sbuf_prev = st->sbuf;
+    st->sbuf ^= 1;
+    st->status &= ~(ST_HALT | ST_OVERFLOW | ST_TILE);
+    if (st->phase == PH_REST) st->phase = PH_RUN;
+    st->rebins += 1;
+    st->max_nbr = 0;
+    st->steps_since = 0;
 }
 
 __global__ void k_bin_scatter(PoolDev P)
@@ -448,7 +496,7 @@ __global__ void k_bin_scatter(PoolDev P)
     if (!rebuild_ctx(P, c)) return;
     const SysParams& sp = P.sp[c.s];
     const int cell = P.cell_tmp[c.i];
-    P.tmp[P.cstart[sp.coff + cell] + P.arr[c.i]] = c.i;
+    P.tmp[cell_begin(P, sp, cell) + P.arr[c.i]] = c.i;
 }
 
 template <typename T>
@@ -463,7 +511,7 @@ __global__ void k_bin_place(PoolDev P)
     const int src = st.sbuf_prev, dst = st.sbuf;
     const int o = P.tmp[c.i];
     const int cell = P.cell_tmp[o];
-    const int b0 = P.cstart[sp.coff + cell], b1 = P.cstart[sp.coff + cell + 1];
+    const int b0 = cell_begin(P, sp, cell), b1 = cell_begin(P, sp, cell + 1);
     const int* ids = P.id[src];
     const int myid = ids[o];
     int rank = 0;
@@ -483,11 +531,11 @@ __global__ void k_bin_place(PoolDev P)
     P.id[dst][d] = myid;
     P.travel[d] = 0.0f;
     V* Lc = (V*)P.L[st.lbuf];
-    if (cell < sp.ncell) {
-        const int cx = cell % sp.nc[0], cy = (cell / sp.nc[0]) % sp.nc[1],
-                  cz = cell / (sp.nc[0] * sp.nc[1]);
+    if (cell < sp.nkey) {
+        int cx, cy, cz;
+        key_cell(sp, cell, cx, cy, cz);
         P.cref[d] = cx | (cy << 10) | (cz << 20);
-        P.cell_lin[d] = cell;
+        P.cell_lin[d] = cx + sp.nc[0] * (cy + sp.nc[1] * cz);
         Lc[d] = make4<T>(local_axis(x, cx, sp.h[0], sp.L[0], sp.invL[0]),
                          local_axis(y, cy, sp.h[1], sp.L[1], sp.invL[1]),
                          local_axis(z, cz, sp.h[2], sp.L[2], sp.invL[2]));
@@ -496,84 +544,274 @@ __global__ void k_bin_place(PoolDev P)
         P.cell_lin[d] = -1;
         Lc[d] = make4<T>(0.0, 0.0, 0.0);
     }
+    // final cell table for the list build and the readbacks
+    for (int q = c.li; q < sp.nkey + 2; q += sp.vcap) P.cstart[sp.coff + q] = cell_begin(P, sp, q);
+}
+
+// ---------------------------------------------------------------------------
+// Brick kernels: one workgroup per brick of cells.  The brick's halo box
+// (the brick plus one cell on every side, (bx+2)(by+2)(bz+2) cells, periodic)
+// is staged in LDS; every neighbour cell of an atom of the brick lies inside
+// it, so the list build and the step kernel read neighbours from LDS.
+// ---------------------------------------------------------------------------
+
+struct BrickCtx {
+    int s, b;  // system slot, brick index within the system
+};
+
+__device__ __forceinline__ bool brick_ctx(const PoolDev& P, BrickCtx& c, int bad_bits)
+{
+    const int lb = logical_block();
+    if (lb >= P.nbrick) return false;
+    const int s = P.brick_sys[lb];
+    if (s < 0) return false;
+    const SysState* st = P.st + s;
+    if (st->remaining <= 0 || (st->status & bad_bits)) return false;
+    c.s = s;
+    c.b = lb - P.sp[s].broff;
+    return true;
+}
+
+struct HaloGeo {
+    int start[3];  // first cell of the brick along each axis
+    int hd[3];     // halo box extent (brick extent + 2)
+    int H;         // halo cells
+};
+
+__device__ __forceinline__ HaloGeo halo_geo(const SysParams& sp, int b)
+{
+    HaloGeo g;
+    const int B[3] = {b % sp.nbk[0], (b / sp.nbk[0]) % sp.nbk[1], b / (sp.nbk[0] * sp.nbk[1])};
+    g.H = 1;
+    for (int k = 0; k < 3; ++k) {
+        g.start[k] = B[k] * sp.bdim[k];
+        const int end = min(sp.nc[k], g.start[k] + sp.bdim[k]);
+        g.hd[k] = end - g.start[k] + 2;
+        g.H *= g.hd[k];
+    }
+    return g;
+}
+
+// LDS tile: staged positions, their slots, and per halo cell the first slot
+// and the first staged index.
+template <typename T>
+struct Tile {
+    typename V4<T>::type* pos;
+    int* slot;
+    int* hbeg;   // [hmax] first slot of the halo cell
+    int* hoff;   // [hmax + 1] first staged index of the halo cell
+};
+
+// Vapour tile of `cap` atoms at smem + offset.
+template <typename T>
+__device__ __forceinline__ Tile<T> tile_at(unsigned char* smem, size_t offset, int cap, int hmax)
+{
+    Tile<T> t;
+    t.pos = (typename V4<T>::type*)(smem + offset);
+    t.slot = (int*)(smem + offset + (size_t)cap * sizeof(typename V4<T>::type));
+    t.hbeg = t.slot + cap;
+    t.hoff = t.hbeg + hmax;
+    return t;
 }
 
 template <typename T>
-__global__ void k_list_build(PoolDev P)
+__device__ __forceinline__ size_t tile_size(int cap, int hmax)
+{
+    return ((size_t)cap * (sizeof(typename V4<T>::type) + 4) + (size_t)(2 * hmax + 1) * 4 + 31) & ~(size_t)31;
+}
+
+template <typename T>
+__device__ __forceinline__ Tile<T> tile_of(unsigned char* smem, const PoolDev& P)
+{
+    return tile_at<T>(smem, 0, P.lds_atoms, P.hmax);
+}
+
+// Stage the halo box of brick g into LDS.  Returns the number of staged
+// atoms, or -1 if it exceeds the tile capacity.  with_pos = false stages
+// only the slots.
+template <typename T, bool WALLS = false>
+__device__ int stage_halo(const PoolDev& P, const SysParams& sp, const HaloGeo& g, Tile<T>& t,
+                          const typename V4<T>::type* Lc, bool with_pos, int* lds_scan,
+                          int cap = -1)
+{
+    if (cap < 0) cap = P.lds_atoms;
+    const int T_ = blockDim.x;
+    const int per = (g.H + T_ - 1) / T_;
+    const int lo = threadIdx.x * per, hi = min(g.H, lo + per);
+    int sum = 0;
+    for (int h = lo; h < hi; ++h) {
+        const int hx = h % g.hd[0], hy = (h / g.hd[0]) % g.hd[1], hz = h / (g.hd[0] * g.hd[1]);
+        const int cx = wrap_cell(g.start[0] - 1 + hx, sp.nc[0]);
+        const int cy = wrap_cell(g.start[1] - 1 + hy, sp.nc[1]);
+        const int cz = wrap_cell(g.start[2] - 1 + hz, sp.nc[2]);
+        int b0, n;
+        if (WALLS) {
+            const int cl = cx + sp.nc[0] * (cy + sp.nc[1] * cz);
+            b0 = P.wcstart[sp.wcoff + cl];
+            n = P.wcstart[sp.wcoff + cl + 1] - b0;
+            b0 += P.vt;  // walls sit after the vapour slots in the coordinate buffers
+        } else {
+            const int key = cell_key(sp, cx, cy, cz);
+            b0 = P.cstart[sp.coff + key];
+            n = P.cstart[sp.coff + key + 1] - b0;
+        }
+        t.hbeg[h] = b0;
+        t.hoff[h] = n;  // count for now
+        sum += n;
+    }
+    int tot;
+    int run = block_exclusive_scan(sum, lds_scan, &tot);
+    for (int h = lo; h < hi; ++h) {
+        const int n = t.hoff[h];
+        t.hoff[h] = run;
+        run += n;
+    }
+    if (threadIdx.x == 0) t.hoff[g.H] = tot;
+    __syncthreads();
+    if (tot > cap) return -1;
+    for (int a = threadIdx.x; a < tot; a += T_) {
+        // halo cell of staged atom a: last h with hoff[h] <= a
+        int l = 0, r = g.H - 1;
+        while (l < r) {
+            const int m = (l + r + 1) >> 1;
+            if (t.hoff[m] <= a)
+                l = m;
+            else
+                r = m - 1;
+        }
+        t.slot[a] = t.hbeg[l] + (a - t.hoff[l]);
+    }
+    __syncthreads();
+    if (with_pos) {
+        // each thread issues 4 independent loads (indices clamped to a valid
+        // staged atom) before storing the ones in range
+        for (int a0 = threadIdx.x; a0 < tot; a0 += 4 * T_) {
+            const int a1 = a0 + T_, a2 = a0 + 2 * T_, a3 = a0 + 3 * T_;
+            const typename V4<T>::type v0 = Lc[t.slot[a0]];
+            const typename V4<T>::type v1 = Lc[t.slot[min(a1, tot - 1)]];
+            const typename V4<T>::type v2 = Lc[t.slot[min(a2, tot - 1)]];
+            const typename V4<T>::type v3 = Lc[t.slot[min(a3, tot - 1)]];
+            t.pos[a0] = v0;
+            if (a1 < tot) t.pos[a1] = v1;
+            if (a2 < tot) t.pos[a2] = v2;
+            if (a3 < tot) t.pos[a3] = v3;
+        }
+    }
+    __syncthreads();
+    return tot;
+}
+
+// Halo cell of neighbour t (0..26) of an atom whose cell is (cx, cy, cz).
+__device__ __forceinline__ int halo_cell(const HaloGeo& g, int cx, int cy, int cz, int t)
+{
+    const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
+    const int hx = cx - g.start[0] + 1 + dx;
+    const int hy = cy - g.start[1] + 1 + dy;
+    const int hz = cz - g.start[2] + 1 + dz;
+    return hx + g.hd[0] * (hy + g.hd[1] * hz);
+}
+
+// Neighbour lists (radius r_c + skin for vapour, r_c + skin/2 for the fixed
+// walls) of the atoms of one brick, in a fixed order: neighbour cells 0..26,
+// staged order inside a cell; vapour entries first, then walls.
+template <typename T>
+__global__ void __launch_bounds__(256) k_list_build(PoolDev P)
 {
     using V = typename V4<T>::type;
-    SlotCtx c;
-    if (!rebuild_ctx(P, c)) return;
+    extern __shared__ __align__(32) unsigned char smem[];
+    __shared__ int lds_scan[17];
+    BrickCtx c;
+    if (!brick_ctx(P, c, ST_NONFINITE)) return;
     const SysParams& sp = P.sp[c.s];
     const SysState& st = P.st[c.s];
     const int vt = P.vt;
-    int cnt = 0;
-    if (c.li < sp.nv) {
-        const V* Lc = (const V*)P.L[st.lbuf];
-        const V me = Lc[c.i];
-        const int cr = P.cref[c.i];
+    const V* Lc = (const V*)P.L[st.lbuf];
+    const HaloGeo g = halo_geo(sp, c.b);
+    Tile<T> t = tile_of<T>(smem, P);
+    Tile<T> tw = tile_at<T>(smem, tile_size<T>(P.lds_atoms, P.hmax), P.wall_lds, P.hmax);
+    const int tot = stage_halo<T>(P, sp, g, t, Lc, true, lds_scan);
+    const int wtot = tot < 0 ? -1 : stage_halo<T, true>(P, sp, g, tw, Lc, true, lds_scan, P.wall_lds);
+    const int key0 = c.b * sp.bcells;
+    const int i0 = P.cstart[sp.coff + key0], i1 = P.cstart[sp.coff + key0 + sp.bcells];
+    if (tot < 0 || wtot < 0) {
+        for (int i = i0 + (int)threadIdx.x; i < i1; i += blockDim.x) P.nlist[i] = 0;
+        if (threadIdx.x == 0) atomicOr(&P.st[c.s].status, ST_OVERFLOW | ST_TILE);
+        return;
+    }
+    const T rl2 = (T)sp.rl2, rw2 = (T)sp.rw2;
+    const int cap = P.cap;
+    int mx = 0;
+    for (int i = i0 + (int)threadIdx.x; i < i1; i += blockDim.x) {
+        const V me = Lc[i];
+        const int cr = P.cref[i];
         const int cx = cr & 1023, cy = (cr >> 10) & 1023, cz = cr >> 20;
-        const T rl2 = (T)sp.rl2;
-        const int* cs = P.cstart + sp.coff;
-        const int* wcs = P.wcstart + sp.wcoff;
-        for (int dz = -1; dz <= 1; ++dz) {
-            const int jz = wrap_cell(cz + dz, sp.nc[2]);
-            const T sz = (T)(-dz * sp.h[2]);
-            for (int dy = -1; dy <= 1; ++dy) {
-                const int jy = wrap_cell(cy + dy, sp.nc[1]);
-                const T sy = (T)(-dy * sp.h[1]);
-                for (int dx = -1; dx <= 1; ++dx) {
-                    const int jx = wrap_cell(cx + dx, sp.nc[0]);
-                    const T sx = (T)(-dx * sp.h[0]);
-                    const unsigned code = (unsigned)((dx + 1) + 3 * (dy + 1) + 9 * (dz + 1));
-                    const int cl = jx + sp.nc[0] * (jy + sp.nc[1] * jz);
-                    const int j1 = cs[cl + 1];
-                    for (int j = cs[cl]; j < j1; ++j) {
-                        if (j == c.i) continue;
-                        const V o = Lc[j];
-                        const T ex = me.x - o.x + sx, ey = me.y - o.y + sy, ez = me.z - o.z + sz;
-                        if (ex * ex + ey * ey + ez * ez < rl2) {
-                            if (cnt < P.cap) P.list[(size_t)cnt * vt + c.i] = (unsigned)j | (code << kIndexBits);
-                            ++cnt;
-                        }
-                    }
-                    const int w1 = wcs[cl + 1];
-                    for (int w = wcs[cl]; w < w1; ++w) {
-                        const V o = Lc[vt + w];
-                        const T ex = me.x - o.x + sx, ey = me.y - o.y + sy, ez = me.z - o.z + sz;
-                        if (ex * ex + ey * ey + ez * ez < rl2) {
-                            if (cnt < P.cap)
-                                P.list[(size_t)cnt * vt + c.i] = (unsigned)(vt + w) | (code << kIndexBits);
-                            ++cnt;
-                        }
-                    }
+        int nv = 0;
+        for (int q = 0; q < 27; ++q) {
+            const int dx = q % 3 - 1, dy = (q / 3) % 3 - 1, dz = q / 9 - 1;
+            const T sx = (T)(-dx * sp.h[0]), sy = (T)(-dy * sp.h[1]), sz = (T)(-dz * sp.h[2]);
+            const int h = halo_cell(g, cx, cy, cz, q);
+            const int a1 = t.hoff[h + 1];
+            for (int a = t.hoff[h]; a < a1; ++a) {
+                const V o = t.pos[a];
+                const T ex = me.x - o.x + sx, ey = me.y - o.y + sy, ez = me.z - o.z + sz;
+                if (ex * ex + ey * ey + ez * ez < rl2 && t.slot[a] != i) {
+                    if (nv < cap) P.list[(size_t)nv * vt + i] = (unsigned)a | ((unsigned)q << kIndexBits);
+                    ++nv;
                 }
             }
         }
-        P.nlist[c.i] = min(cnt, P.cap);
-    } else {
-        P.nlist[c.i] = 0;
+        int nw = 0;
+        for (int q = 0; q < 27; ++q) {
+            const int dx = q % 3 - 1, dy = (q / 3) % 3 - 1, dz = q / 9 - 1;
+            const T sx = (T)(-dx * sp.h[0]), sy = (T)(-dy * sp.h[1]), sz = (T)(-dz * sp.h[2]);
+            const int h = halo_cell(g, cx, cy, cz, q);
+            const int a1 = tw.hoff[h + 1];
+            for (int a = tw.hoff[h]; a < a1; ++a) {
+                const V o = tw.pos[a];
+                const T ex = me.x - o.x + sx, ey = me.y - o.y + sy, ez = me.z - o.z + sz;
+                if (ex * ex + ey * ey + ez * ez < rw2) {
+                    if (nv + nw < cap)
+                        P.list[(size_t)(nv + nw) * vt + i] =
+                            (unsigned)(tw.slot[a] - vt) | ((unsigned)q << kIndexBits);
+                    ++nw;
+                }
+            }
+        }
+        const bool ok = nv + nw <= cap;
+        P.nlist[i] = ok ? (nv | (nw << 16)) : 0;
+        mx = max(mx, nv + nw);
     }
-    const int m = wave_max(cnt);
-    if ((threadIdx.x & 63) == 0) {
-        atomicMax(&P.st[c.s].max_nbr, m);
-        if (m > P.cap) atomicOr(&P.st[c.s].status, ST_OVERFLOW);
+    mx = wave_max(mx);
+    if ((threadIdx.x & 63) == 0 && mx > 0) {
+        atomicMax(&P.st[c.s].max_nbr, mx);
+        if (mx > cap) atomicOr(&P.st[c.s].status, ST_OVERFLOW);
     }
+}
+
+size_t tile_bytes(const PoolDev& P, int precision, bool walls)
+{
+    const size_t v = precision == 1 ? sizeof(f4) : sizeof(d4);
+    auto one = [&](int cap) { return ((size_t)cap * (v + 4) + (size_t)(2 * P.hmax + 1) * 4 + 31) & ~(size_t)31; };
+    return one(P.lds_atoms) + (walls ? one(P.wall_lds) : 0);
 }
 
 hipError_t launch_rebuild(const PoolDev& P, int nslots, int precision, hipStream_t s)
 {
-    const int G = ((P.nlog + 7) / 8) * 8;
-    const int B = P.block;
-    hipLaunchKernelGGL(k_bin_count, dim3(G), dim3(B), 0, s, P);
-    hipLaunchKernelGGL(k_bin_scan, dim3(nslots), dim3(1024), 0, s, P, nslots);
-    hipLaunchKernelGGL(k_bin_scatter, dim3(G), dim3(B), 0, s, P);
+    (void)nslots;
+    const int nrb = P.nchunk / (kRebuildBlock / kChunk);
+    const int G = ((nrb + 7) / 8) * 8;
+    const int GB = ((P.nbrick + 7) / 8) * 8;
+    if (G == 0) return hipSuccess;
+    const size_t lds = tile_bytes(P, precision, true);
+    hipLaunchKernelGGL(k_bin_count, dim3(G), dim3(kRebuildBlock), 0, s, P);
+    hipLaunchKernelGGL(k_bin_scan, dim3(P.ntile), dim3(1024), 0, s, P);
+    hipLaunchKernelGGL(k_bin_scatter, dim3(G), dim3(kRebuildBlock), 0, s, P);
     if (precision == 1) {
-        hipLaunchKernelGGL(k_bin_place<float>, dim3(G), dim3(B), 0, s, P);
-        hipLaunchKernelGGL(k_list_build<float>, dim3(G), dim3(B), 0, s, P);
+        hipLaunchKernelGGL(k_bin_place<float>, dim3(G), dim3(kRebuildBlock), 0, s, P);
+        hipLaunchKernelGGL(k_list_build<float>, dim3(GB), dim3(P.block), lds, s, P);
     } else {
-        hipLaunchKernelGGL(k_bin_place<double>, dim3(G), dim3(B), 0, s, P);
-        hipLaunchKernelGGL(k_list_build<double>, dim3(G), dim3(B), 0, s, P);
+        hipLaunchKernelGGL(k_bin_place<double>, dim3(G), dim3(kRebuildBlock), 0, s, P);
+        hipLaunchKernelGGL(k_list_build<double>, dim3(GB), dim3(P.block), lds, s, P);
     }
     return hipGetLastError();
 }
@@ -582,7 +820,8 @@ hipError_t launch_rebuild(const PoolDev& P, int nslots, int precision, hipStream
 // Step: forces (F1) + second half-kick (F3) [+ next drift and half-kick (F2)]
 // ---------------------------------------------------------------------------
 
-// Pair scalars: w such that the force on i is w * d, and the pair energy u.
+constexpr int kGroup = 8;  // list entries fetched together in the step kernel
+
 template <typename T>
 __device__ __forceinline__ T inv_of(T r2);
 template <>
@@ -591,101 +830,126 @@ template <>
 __device__ __forceinline__ double inv_of<double>(double r2) { return 1.0 / r2; }
 
 template <typename T>
-__global__ void __launch_bounds__(1024) k_step(PoolDev P)
+__global__ void __launch_bounds__(256) k_step(PoolDev P)
 {
     using V = typename V4<T>::type;
+    extern __shared__ __align__(32) unsigned char smem[];
     __shared__ V tab[27];
-    __shared__ double red[3][16];
-    __shared__ int flag_or[16];
+    __shared__ double red[3][4];
+    __shared__ int flag_or[4];
+    __shared__ int lds_scan[17];
     __shared__ int am_last;
 
-    const int lb = logical_block();
-    if (lb >= P.nlog) return;
-    const int s = P.blk_sys[lb];
+    BrickCtx c;
+    if (!brick_ctx(P, c, ST_HALT | ST_OVERFLOW | ST_NONFINITE)) return;
+    const int s = c.s;
     const SysParams& sp = P.sp[s];
     const SysState st = P.st[s];
-    if (st.remaining <= 0 || (st.status & (ST_HALT | ST_OVERFLOW | ST_NONFINITE))) return;
-
     const int tid = threadIdx.x;
     if (tid < 27) {
         const int dx = tid % 3 - 1, dy = (tid / 3) % 3 - 1, dz = tid / 9 - 1;
         tab[tid] = make4<T>(-dx * sp.h[0], -dy * sp.h[1], -dz * sp.h[2]);
     }
-    __syncthreads();
+    const V* Lc = (const V*)P.L[st.lbuf];
+    const HaloGeo g = halo_geo(sp, c.b);
+    Tile<T> tl = tile_of<T>(smem, P);
+    const int tot = stage_halo<T>(P, sp, g, tl, Lc, true, lds_scan);
 
     const bool init = st.phase == PH_INIT;
     const bool last = !init && st.remaining == 1;
     const long long kstep = init ? 0 : st.step + 1;
     const bool doE = init || last || (sp.energy_every > 0 && (kstep % sp.energy_every) == 0);
     const int vt = P.vt;
-    const int li = (lb - sp.boff) * (int)blockDim.x + tid;
-    const int i = sp.voff + li;
+    const int key0 = c.b * sp.bcells;
+    const int i0 = P.cstart[sp.coff + key0], i1 = P.cstart[sp.coff + key0 + sp.bcells];
 
     double ke = 0.0, evv = 0.0, evw = 0.0;
-    int flags = 0;
-    if (li < sp.nv) {
-        const V* Lc = (const V*)P.L[st.lbuf];
+    int flags = tot < 0 ? (ST_OVERFLOW | ST_TILE) : 0;
+    double* X = P.X[st.sbuf];
+    double* Vv = P.V[st.sbuf];
+    const T rc2 = (T)sp.rc2;
+    const T Av = (T)sp.A, Bv = (T)sp.B, Aw = (T)sp.Aw, Bw = (T)sp.Bw;
+    const T A12v = (T)12 * Av, B6v = (T)6 * Bv, A12w = (T)12 * Aw, B6w = (T)6 * Bw;
+    const T ucv = (T)sp.uc, ucw = (T)sp.ucw;
+    const T band = (T)(4.0e-6 * sp.rc2);
+    for (int i = i0 + tid; tot >= 0 && i < i1; i += blockDim.x) {
         const V me = Lc[i];
-        double* X = P.X[st.sbuf];
-        double* Vv = P.V[st.sbuf];
         const double xi = X[i], yi = X[vt + i], zi = X[2 * vt + i];
-        const int n = P.nlist[i];
-        const T rc2 = (T)sp.rc2;
-        const T Av = (T)sp.A, Bv = (T)sp.B, Aw = (T)sp.Aw, Bw = (T)sp.Bw;
-        const T ucv = (T)sp.uc, ucw = (T)sp.ucw;
-        const T band = (T)(4.0e-6 * sp.rc2);
-        double fx = 0.0, fy = 0.0, fz = 0.0;
+        const double vx0 = Vv[i], vy0 = Vv[vt + i], vz0 = Vv[2 * vt + i];
+        const int cr = P.cref[i];
+        const float tr0 = P.travel[i];
+        const int nl = P.nlist[i];
+        const int nvap = nl & 0xFFFF, nall = nvap + (nl >> 16);
+        double fx = 0.0, fy = 0.0, fz = 0.0, eav = 0.0, eaw = 0.0;
         const unsigned* lst = P.list + i;
-        for (int k = 0; k < n; ++k) {
-            const unsigned e = lst[(size_t)k * vt];
-            const int j = (int)(e & kIndexMask);
-            const V o = Lc[j];
-            const V sh = tab[e >> kIndexBits];
-            const T dx = me.x - o.x + sh.x;
-            const T dy = me.y - o.y + sh.y;
-            const T dz = me.z - o.z + sh.z;
-            const T r2 = dx * dx + dy * dy + dz * dz;
-            const bool wall = j >= vt;
-            bool in = r2 < rc2;
-            if (sizeof(T) == 4 && fabs(r2 - rc2) < band) {
-                // FP64 re-test of a pair at the cutoff edge
-                double ox, oy, oz;
-                if (wall) {
-                    const int w = j - vt;
-                    ox = P.WX[w];
-                    oy = P.WX[P.wt + w];
-                    oz = P.WX[2 * P.wt + w];
-                } else {
-                    ox = X[j];
-                    oy = X[vt + j];
-                    oz = X[2 * vt + j];
-                }
-                double ex = xi - ox, ey = yi - oy, ez = zi - oz;
-                ex -= sp.L[0] * rint(ex * sp.invL[0]);
-                ey -= sp.L[1] * rint(ey * sp.invL[1]);
-                ez -= sp.L[2] * rint(ez * sp.invL[2]);
-                in = ex * ex + ey * ey + ez * ez < sp.rc2;
+        // entries are fetched 8 at a time, then their partners (LDS for
+        // vapour, global memory for walls): two memory latencies per group
+        for (int k0 = 0; k0 < nall; k0 += kGroup) {
+            unsigned e8[kGroup];
+#pragma unroll
+            for (int u = 0; u < kGroup; ++u)
+                e8[u] = (k0 + u < nall) ? lst[(size_t)(k0 + u) * vt] : 0u;
+            V o8[kGroup];
+#pragma unroll
+            for (int u = 0; u < kGroup; ++u) {
+                const int a = (int)(e8[u] & kIndexMask);
+                o8[u] = (k0 + u < nvap) ? tl.pos[a] : Lc[vt + ((k0 + u < nall) ? a : 0)];
             }
-            if (in) {
-                const T A = wall ? Aw : Av;
-                const T B = wall ? Bw : Bv;
-                const T sr2 = inv_of<T>(r2);
-                const T sr6 = sr2 * sr2 * sr2;
-                const T w = sr2 * sr6 * ((T)12 * A * sr6 - (T)6 * B);
-                fx += (double)(w * dx);
-                fy += (double)(w * dy);
-                fz += (double)(w * dz);
-                if (doE) {
-                    const T u = sr6 * (A * sr6 - B) - (wall ? ucw : ucv);
-                    if (wall)
-                        evw += (double)u;
-                    else
-                        evv += 0.5 * (double)u;
+#pragma unroll
+            for (int u = 0; u < kGroup; ++u) {
+                const int k = k0 + u;
+                if (k >= nall) break;
+                const unsigned e = e8[u];
+                const bool wall = k >= nvap;
+                const int a = (int)(e & kIndexMask);
+                const V o = o8[u];
+                const V sh = tab[e >> kIndexBits];
+                const T dx = me.x - o.x + sh.x;
+                const T dy = me.y - o.y + sh.y;
+                const T dz = me.z - o.z + sh.z;
+                const T r2 = dx * dx + dy * dy + dz * dz;
+                bool in = r2 < rc2;
+                if (sizeof(T) == 4 && fabs(r2 - rc2) < band) {
+                    // FP64 re-test of a pair at the cutoff edge
+                    double ox, oy, oz;
+                    if (wall) {
+                        ox = P.WX[a];
+                        oy = P.WX[P.wt + a];
+                        oz = P.WX[2 * P.wt + a];
+                    } else {
+                        const int j = tl.slot[a];
+                        ox = X[j];
+                        oy = X[vt + j];
+                        oz = X[2 * vt + j];
+                    }
+                    double ex = xi - ox, ey = yi - oy, ez = zi - oz;
+                    ex -= sp.L[0] * rint(ex * sp.invL[0]);
+                    ey -= sp.L[1] * rint(ey * sp.invL[1]);
+                    ez -= sp.L[2] * rint(ez * sp.invL[2]);
+                    in = ex * ex + ey * ey + ez * ez < sp.rc2;
+                }
+                if (in) {
+                    const T A = wall ? Aw : Av, B = wall ? Bw : Bv;
+                    const T sr2 = inv_of<T>(r2);
+                    const T sr6 = sr2 * sr2 * sr2;
+                    const T w = sr2 * sr6 * ((wall ? A12w : A12v) * sr6 - (wall ? B6w : B6v));
+                    fx += (double)(w * dx);
+                    fy += (double)(w * dy);
+                    fz += (double)(w * dz);
+                    if (doE) {
+                        const double u_ = (double)(sr6 * (A * sr6 - B) - (wall ? ucw : ucv));
+                        if (wall)
+                            eaw += u_;
+                        else
+                            eav += u_;
+                    }
                 }
             }
         }
+        evv += 0.5 * eav;
+        evw += eaw;
         const double ax = fx * sp.inv_mass, ay = fy * sp.inv_mass, az = fz * sp.inv_mass;
-        double vx = Vv[i], vy = Vv[vt + i], vz = Vv[2 * vt + i];
+        double vx = vx0, vy = vy0, vz = vz0;
         if (init) {
             P.A[i] = ax;
             P.A[vt + i] = ay;
@@ -696,7 +960,8 @@ __global__ void __launch_bounds__(1024) k_step(PoolDev P)
             vy += hdt * ay;
             vz += hdt * az;
         }
-        ke = 0.5 * sp.mass * (vx * vx + vy * vy + vz * vz);
+        const double kei = 0.5 * sp.mass * (vx * vx + vy * vy + vz * vz);
+        ke += kei;
         if (!init) {
             if (last) {
                 Vv[i] = vx;
@@ -719,18 +984,17 @@ __global__ void __launch_bounds__(1024) k_step(PoolDev P)
                 X[i] = x;
                 X[vt + i] = y;
                 X[2 * vt + i] = z;
-                const int cr = P.cref[i];
                 const int cx = cr & 1023, cy = (cr >> 10) & 1023, cz = cr >> 20;
                 V* Ln = (V*)P.L[st.lbuf ^ 1];
                 Ln[i] = make4<T>(local_axis(x, cx, sp.h[0], sp.L[0], sp.invL[0]),
                                  local_axis(y, cy, sp.h[1], sp.L[1], sp.invL[1]),
                                  local_axis(z, cz, sp.h[2], sp.L[2], sp.invL[2]));
-                const float tr = P.travel[i] + (float)(sqrt(vx * vx + vy * vy + vz * vz) * sp.dt);
+                const float tr = tr0 + (float)(sqrt(vx * vx + vy * vy + vz * vz) * sp.dt);
                 P.travel[i] = tr;
                 if (tr > sp.half_skin) flags |= ST_HALT;
             }
         }
-        if (!isfinite(fx + fy + fz) || !isfinite(ke)) flags |= ST_NONFINITE;
+        if (!isfinite(fx + fy + fz) || !isfinite(kei)) flags |= ST_NONFINITE;
     }
 
     // workgroup reductions (fixed order: lane tree, then waves in order)
@@ -753,20 +1017,20 @@ __global__ void __launch_bounds__(1024) k_step(PoolDev P)
         for (int w = 0; w < nwave; ++w) f |= flag_or[w];
         if (f) atomicOr(&P.st[s].status_next, f);
         if (doE) {
-            double a = 0.0, b = 0.0, c = 0.0;
+            double a = 0.0, b = 0.0, cc = 0.0;
             for (int w = 0; w < nwave; ++w) {
                 a += red[0][w];
                 b += red[1][w];
-                c += red[2][w];
+                cc += red[2][w];
             }
-            double* pp = P.partial + 3 * (size_t)(sp.pboff + (lb - sp.boff));
+            double* pp = P.partial + 3 * (size_t)(sp.pboff + c.b);
             pp[0] = a;
             pp[1] = b;
-            pp[2] = c;
+            pp[2] = cc;
         }
         __threadfence();
         const int prev = atomicAdd(&P.st[s].blocks_done, 1);
-        am_last = (prev == sp.nblk - 1);
+        am_last = (prev == sp.nbrick - 1);
     }
     __syncthreads();
     if (!am_last) return;
@@ -774,37 +1038,38 @@ __global__ void __launch_bounds__(1024) k_step(PoolDev P)
     // last workgroup of this system: finish the energy sums and the step
     __threadfence();
     if (doE) {
-        double a = 0.0, b = 0.0, c = 0.0;
+        double a = 0.0, b = 0.0, cc = 0.0;
         const double* pp = P.partial + 3 * (size_t)sp.pboff;
-        for (int q = tid; q < sp.nblk; q += blockDim.x) {
+        for (int q = tid; q < sp.nbrick; q += blockDim.x) {
             a += atomic_load_f64(pp + 3 * q);
             b += atomic_load_f64(pp + 3 * q + 1);
-            c += atomic_load_f64(pp + 3 * q + 2);
+            cc += atomic_load_f64(pp + 3 * q + 2);
         }
         a = wave_sum(a);
         b = wave_sum(b);
-        c = wave_sum(c);
+        cc = wave_sum(cc);
+        __syncthreads();
         if (lane == 0) {
             red[0][wave] = a;
             red[1][wave] = b;
-            red[2][wave] = c;
+            red[2][wave] = cc;
         }
         __syncthreads();
     }
     if (tid == 0) {
         SysState* sw = P.st + s;
         if (doE) {
-            double a = 0.0, b = 0.0, c = 0.0;
+            double a = 0.0, b = 0.0, cc = 0.0;
             for (int w = 0; w < nwave; ++w) {
                 a += red[0][w];
                 b += red[1][w];
-                c += red[2][w];
+                cc += red[2][w];
             }
             EnergyRec r;
             r.step = kstep;
             r.ke = a;
             r.pe_vv = b;
-            r.pe_vw = c;
+            r.pe_vw = cc;
             P.erec[sp.ering_off + (st.nrec % sp.ering_cap)] = r;
             sw->nrec = st.nrec + 1;
         }
@@ -831,18 +1096,20 @@ __global__ void __launch_bounds__(1024) k_step(PoolDev P)
 hipError_t launch_step(const PoolDev& P, int precision, hipStream_t s, hipEvent_t ev0,
                        hipEvent_t ev1)
 {
-    const int G = ((P.nlog + 7) / 8) * 8;
+    const int G = ((P.nbrick + 7) / 8) * 8;
     const int B = P.block;
+    if (G == 0) return hipSuccess;
+    const size_t lds = tile_bytes(P, precision, false);
     if (ev0 && ev1) {
         if (precision == 1)
-            hipExtLaunchKernelGGL(k_step<float>, dim3(G), dim3(B), 0, s, ev0, ev1, 0, P);
+            hipExtLaunchKernelGGL(k_step<float>, dim3(G), dim3(B), lds, s, ev0, ev1, 0, P);
         else
-            hipExtLaunchKernelGGL(k_step<double>, dim3(G), dim3(B), 0, s, ev0, ev1, 0, P);
+            hipExtLaunchKernelGGL(k_step<double>, dim3(G), dim3(B), lds, s, ev0, ev1, 0, P);
     } else {
         if (precision == 1)
-            hipLaunchKernelGGL(k_step<float>, dim3(G), dim3(B), 0, s, P);
+            hipLaunchKernelGGL(k_step<float>, dim3(G), dim3(B), lds, s, P);
         else
-            hipLaunchKernelGGL(k_step<double>, dim3(G), dim3(B), 0, s, P);
+            hipLaunchKernelGGL(k_step<double>, dim3(G), dim3(B), lds, s, P);
     }
     return hipGetLastError();
 }
@@ -915,60 +1182,80 @@ hipError_t launch_wall_unpermute(const PoolDev& P, int slot, double* out, int n,
 }
 
 // Pairs within the cutoff found through the lists, tested in FP64 on the
-// master positions: out_pairs holds (kind, a, b) triples; counts[0] = total.
+// master positions: out holds (kind, a, b) triples; counts[0] = total.
+template <typename T>
 __global__ void k_debug_pairs(PoolDev P, int slot, int* out, int cap, int* counts)
 {
+    extern __shared__ __align__(32) unsigned char smem[];
+    __shared__ int lds_scan[17];
     const SysParams& sp = P.sp[slot];
     const SysState& st = P.st[slot];
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= sp.nv) return;
+    const int b = blockIdx.x;
+    if (b >= sp.nbrick) return;
+    const HaloGeo g = halo_geo(sp, b);
+    Tile<T> t = tile_of<T>(smem, P);
+    const int tot = stage_halo<T>(P, sp, g, t, (const typename V4<T>::type*)P.L[st.lbuf], false,
+                                  lds_scan);
+    if (tot < 0) return;
     const int vt = P.vt;
-    const int i = sp.voff + p;
     const double* X = P.X[st.sbuf];
     const int* ids = P.id[st.sbuf];
-    const int n = P.nlist[i];
-    const double xi = X[i], yi = X[vt + i], zi = X[2 * vt + i];
-    for (int k = 0; k < n; ++k) {
-        const unsigned e = P.list[(size_t)k * vt + i];
-        const int j = (int)(e & kIndexMask);
-        double ox, oy, oz;
-        int kind, b;
-        if (j >= vt) {
-            const int w = j - vt;
-            ox = P.WX[w];
-            oy = P.WX[P.wt + w];
-            oz = P.WX[2 * P.wt + w];
-            kind = 1;
-            b = P.wid[w];
-        } else {
-            ox = X[j];
-            oy = X[vt + j];
-            oz = X[2 * vt + j];
-            kind = 0;
-            b = ids[j];
-            if (!(ids[i] < b)) continue;
-        }
-        double ex = xi - ox, ey = yi - oy, ez = zi - oz;
-        ex -= sp.L[0] * rint(ex * sp.invL[0]);
-        ey -= sp.L[1] * rint(ey * sp.invL[1]);
-        ez -= sp.L[2] * rint(ez * sp.invL[2]);
-        if (ex * ex + ey * ey + ez * ez < sp.rc2) {
-            const int q = atomicAdd(counts, 1);
-            if (q < cap) {
-                out[3 * q] = kind;
-                out[3 * q + 1] = ids[i];
-                out[3 * q + 2] = b;
+    const int key0 = b * sp.bcells;
+    const int i0 = P.cstart[sp.coff + key0], i1 = P.cstart[sp.coff + key0 + sp.bcells];
+    for (int i = i0 + (int)threadIdx.x; i < i1; i += blockDim.x) {
+        const int nl = P.nlist[i];
+        const int nvap = nl & 0xFFFF, n = nvap + (nl >> 16);
+        const double xi = X[i], yi = X[vt + i], zi = X[2 * vt + i];
+        for (int k = 0; k < n; ++k) {
+            const unsigned e = P.list[(size_t)k * vt + i];
+            const int a = (int)(e & kIndexMask);
+            double ox, oy, oz;
+            int kind, bb;
+            if (k >= nvap) {
+                ox = P.WX[a];
+                oy = P.WX[P.wt + a];
+                oz = P.WX[2 * P.wt + a];
+                kind = 1;
+                bb = P.wid[a];
+            } else {
+                const int j = t.slot[a];
+                ox = X[j];
+                oy = X[vt + j];
+                oz = X[2 * vt + j];
+                kind = 0;
+                bb = ids[j];
+                if (!(ids[i] < bb)) continue;
+            }
+            double ex = xi - ox, ey = yi - oy, ez = zi - oz;
+            ex -= sp.L[0] * rint(ex * sp.invL[0]);
+            ey -= sp.L[1] * rint(ey * sp.invL[1]);
+            ez -= sp.L[2] * rint(ez * sp.invL[2]);
+            if (ex * ex + ey * ey + ez * ez < sp.rc2) {
+                const int q = atomicAdd(counts, 1);
+                if (q < cap) {
+                    out[3 * q] = kind;
+                    out[3 * q + 1] = ids[i];
+                    out[3 * q + 2] = bb;
+                }
             }
         }
     }
 }
 
-hipError_t launch_debug_pairs(const PoolDev& P, int slot, int nv, int* out, int cap, int* counts,
-                              hipStream_t s)
+hipError_t launch_debug_pairs(const PoolDev& P, int slot, int precision, int* out, int cap,
+                              int* counts, hipStream_t s)
 {
-    if (nv <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_debug_pairs, dim3((nv + 255) / 256), dim3(256), 0, s, P, slot, out, cap,
-                       counts);
+    SysParams sp;
+    hipError_t e = hipMemcpy(&sp, P.sp + slot, sizeof(SysParams), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return e;
+    if (sp.nbrick <= 0) return hipSuccess;
+    const size_t lds = tile_bytes(P, precision, false);
+    if (precision == 1)
+        hipLaunchKernelGGL(k_debug_pairs<float>, dim3(sp.nbrick), dim3(P.block), lds, s, P, slot, out,
+                           cap, counts);
+    else
+        hipLaunchKernelGGL(k_debug_pairs<double>, dim3(sp.nbrick), dim3(P.block), lds, s, P, slot,
+                           out, cap, counts);
     return hipGetLastError();
 }
 

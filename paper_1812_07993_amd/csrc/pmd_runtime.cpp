@@ -179,6 +179,7 @@ int merge_tuning(const pmd_params& p, int64_t nv, const pmd_tuning* in, pmd_tuni
         return fail(PMD_EINVAL, "block must be 64, 128 or 256 (got %d)", d.block);
     if (d.rebin_every > 1000) return fail(PMD_EINVAL, "rebin_every must be <= 1000");
     if (d.list_cap > 4096) return fail(PMD_EINVAL, "list_cap must be <= 4096");
+    d.list_cap = round_up(d.list_cap, 16);  // the list layout groups entries by 4
     *out = d;
     return PMD_OK;
 }
@@ -196,7 +197,9 @@ struct Pool {
     // device arrays
     SysParams* d_sp = nullptr;
     SysState* d_st = nullptr;
-    int* d_blk = nullptr;
+    int* d_chunk = nullptr;
+    int* d_tile = nullptr;
+    int* d_brick = nullptr;
     double* X[2] = {nullptr, nullptr};
     double* V[2] = {nullptr, nullptr};
     int* id[2] = {nullptr, nullptr};
@@ -206,6 +209,8 @@ struct Pool {
     int* cell_lin = nullptr;
     void* L[2] = {nullptr, nullptr};
     int* count = nullptr;
+    int* clocal = nullptr;
+    int* ctile = nullptr;
     int* cstart = nullptr;
     int* arr = nullptr;
     int* tmp = nullptr;
@@ -221,8 +226,8 @@ struct Pool {
     int* dbg = nullptr;
     // host
     std::vector<SysParams> hsp;
-    std::vector<int> hblk;
-    int nlog = 0;
+    std::vector<int> hchunk, htile, hbrick;
+    int nchunk = 0, ntile = 0, tcap = 0, nbrick = 0, lds_atoms = 0, hmax = 0, wall_lds = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
     hipStream_t cap_stream = nullptr;
@@ -272,8 +277,15 @@ struct Pool {
         PoolDev d{};
         d.sp = d_sp;
         d.st = d_st;
-        d.blk_sys = d_blk;
-        d.nlog = nlog;
+        d.chunk_sys = d_chunk;
+        d.nchunk = nchunk;
+        d.tile_sys = d_tile;
+        d.ntile = ntile;
+        d.brick_sys = d_brick;
+        d.nbrick = nbrick;
+        d.lds_atoms = lds_atoms;
+        d.wall_lds = wall_lds;
+        d.hmax = hmax;
         d.block = block;
         d.vt = vt;
         d.wt = wt;
@@ -289,6 +301,8 @@ struct Pool {
         d.cref = cref;
         d.cell_lin = cell_lin;
         d.count = count;
+        d.clocal = clocal;
+        d.ctile = ctile;
         d.cstart = cstart;
         d.arr = arr;
         d.tmp = tmp;
@@ -314,7 +328,7 @@ size_t pool_bytes(int precision, int vt, int wt, int ct, int wct, int nbt, int n
     s += 2 * 2 * 3 * (size_t)vt * 8 + 3 * (size_t)vt * 8;  // X, V double-buffered, A
     s += 2 * (size_t)vt * 4 + 3 * (size_t)vt * 4;          // id x2, travel, cref, cell_lin
     s += 2 * (size_t)(vt + wt) * lsize(precision);         // local coordinates x2
-    s += 2 * (size_t)ct * 4 + 3 * (size_t)std::max(vt, wt) * 4;
+    s += 3 * (size_t)ct * 4 + 3 * (size_t)std::max(vt, wt) * 4;
     s += (size_t)vt * cap * 4 + (size_t)vt * 4;            // lists
     s += 3 * (size_t)wt * 8 + (size_t)wt * 4 + (size_t)wct * 4;
     s += 3 * (size_t)nbt * 8 + (size_t)nslots * erings * sizeof(EnergyRec);
@@ -328,7 +342,11 @@ int pool_allocate(Pool& p)
     p.wt = wt;
     CHK(p.alloc(&p.d_sp, p.nslots));
     CHK(p.alloc(&p.d_st, p.nslots));
-    CHK(p.alloc(&p.d_blk, std::max(p.nbt, 1)));
+    CHK(p.alloc(&p.d_chunk, std::max(vt / kChunk, 1)));
+    p.tcap = p.ct / kTile + p.nslots + 1;
+    CHK(p.alloc(&p.d_tile, p.tcap));
+    CHK(p.alloc(&p.ctile, p.tcap));
+    CHK(p.alloc(&p.d_brick, std::max(p.nbt, 1)));
     for (int b = 0; b < 2; ++b) {
         CHK(p.alloc(&p.X[b], 3 * (size_t)vt));
         CHK(p.alloc(&p.V[b], 3 * (size_t)vt));
@@ -350,6 +368,7 @@ int pool_allocate(Pool& p)
     CHK(p.alloc(&p.cref, vt));
     CHK(p.alloc(&p.cell_lin, vt));
     CHK(p.alloc(&p.count, p.ct));
+    CHK(p.alloc(&p.clocal, p.ct));
     CHK(p.alloc(&p.cstart, p.ct));
     const int sc = std::max(vt, wt);
     CHK(p.alloc(&p.arr, sc));
@@ -360,6 +379,7 @@ int pool_allocate(Pool& p)
     CHK(p.alloc(&p.WX, 3 * (size_t)wt));
     CHK(p.alloc(&p.wid, wt));
     CHK(p.alloc(&p.wcstart, std::max(p.wct, 1)));
+    HIPCHK(hipMemset(p.wcstart, 0, sizeof(int) * (size_t)std::max(p.wct, 1)));
     CHK(p.alloc(&p.partial, 3 * (size_t)std::max(p.nbt, 1)));
     CHK(p.alloc(&p.erec, (size_t)p.nslots * p.ering_cap));
     CHK(p.alloc(&p.stage, 3 * (size_t)sc));
@@ -398,34 +418,190 @@ int pool_grow_lists(Pool& p, int new_cap)
     return PMD_OK;
 }
 
-// Lay out the workgroup table from the per-slot parameters and upload them.
+constexpr size_t kTileBytesMax = 60 * 1024;  // dynamic LDS of the step kernel's tile
+constexpr size_t kListLdsMax = 150 * 1024;   // dynamic LDS of the list build (vapour + walls)
+
+size_t tile_atom_bytes(int precision) { return (precision == PMD_MIXED ? sizeof(f4) : sizeof(d4)) + 4; }
+
+int halo_cells(const SysParams& sp)
+{
+    return (std::min(sp.bdim[0], sp.nc[0]) + 2) * (std::min(sp.bdim[1], sp.nc[1]) + 2) *
+           (std::min(sp.bdim[2], sp.nc[2]) + 2);
+}
+
+// Largest number of wall atoms in the halo box of any brick of a system
+// (walls are static, so this is exact until the bricks change).
+int wall_halo_max(const Pool& p, const SysParams& sp, int* out)
+{
+    *out = 0;
+    if (sp.nw == 0) return PMD_OK;
+    std::vector<int> wcs((size_t)sp.ncell + 1);
+    HIPCHK(hipMemcpy(wcs.data(), p.wcstart + sp.wcoff, sizeof(int) * wcs.size(), hipMemcpyDeviceToHost));
+    auto cnt = [&](int cx, int cy, int cz) {
+        const int c = cx + sp.nc[0] * (cy + sp.nc[1] * cz);
+        return wcs[c + 1] - wcs[c];
+    };
+    auto wrap = [](int c, int n) { return (c % n + n) % n; };
+    int best = 0;
+    for (int b = 0; b < sp.nbrick; ++b) {
+        const int B[3] = {b % sp.nbk[0], (b / sp.nbk[0]) % sp.nbk[1], b / (sp.nbk[0] * sp.nbk[1])};
+        int lo[3], hi[3];
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = B[k] * sp.bdim[k] - 1;
+            hi[k] = std::min(sp.nc[k], B[k] * sp.bdim[k] + sp.bdim[k]);  // inclusive
+        }
+        int tot = 0;
+        for (int z = lo[2]; z <= hi[2]; ++z)
+            for (int y = lo[1]; y <= hi[1]; ++y)
+                for (int x = lo[0]; x <= hi[0]; ++x)
+                    tot += cnt(wrap(x, sp.nc[0]), wrap(y, sp.nc[1]), wrap(z, sp.nc[2]));
+        best = std::max(best, tot);
+    }
+    *out = best;
+    return PMD_OK;
+}
+
+// Lay out the chunk, scan-tile and brick tables from the per-slot parameters,
+// size the staged LDS tile, and upload.
+int pool_layout_once(Pool& p, int* worst_slot, size_t* list_lds);
+void choose_bricks(SysParams& sp, double target);
+
 int pool_layout(Pool& p)
 {
-    p.hblk.clear();
-    int pb = 0;
+    for (int iter = 0; iter < 64; ++iter) {
+        int worst = -1;
+        size_t lds = 0;
+        CHK(pool_layout_once(p, &worst, &lds));
+        if (lds <= kListLdsMax) return PMD_OK;
+        SysParams& sp = p.hsp[worst];
+        if (sp.bcells == 1) return fail(PMD_ENOMEM, "wall neighbourhood of one cell exceeds LDS");
+        const double occ = std::max((double)sp.nv / sp.ncell, 1e-3);
+        choose_bricks(sp, 0.5 * sp.bcells * occ);
+    }
+    return fail(PMD_EHIP, "could not fit the list-build tile in LDS");
+}
+
+int pool_layout_once(Pool& p, int* worst_slot, size_t* list_lds)
+{
+    p.hchunk.clear();
+    p.htile.clear();
+    p.hbrick.clear();
+    int pb = 0, hmax = 0, wall_want = 0;
+    double lds_want = 0;
     for (int s = 0; s < p.nslots; ++s) {
         SysParams& sp = p.hsp[s];
         if (!sp.active) {
-            sp.nblk = 0;
-            sp.boff = 0;
+            sp.choff = 0;
+            sp.ntile = 0;
+            sp.broff = 0;
             continue;
         }
-        sp.nblk = sp.vcap / p.block;
-        sp.boff = (int)p.hblk.size();
+        if (sp.voff % kPad || sp.vcap % kPad) return fail(PMD_EHIP, "misaligned system slots");
+        // chunks follow slot order; chunks of released ranges map to -1
+        sp.choff = sp.voff / kChunk;
+        const int end = sp.choff + sp.vcap / kChunk;
+        if ((int)p.hchunk.size() < end) p.hchunk.resize(end, -1);
+        for (int c = sp.choff; c < end; ++c) p.hchunk[c] = s;
+        sp.toff = (int)p.htile.size();
+        sp.ntile = (sp.nkey + 2 + kTile - 1) / kTile;
+        for (int t = 0; t < sp.ntile; ++t) p.htile.push_back(s);
+        sp.broff = (int)p.hbrick.size();
         sp.pboff = pb;
-        pb += sp.nblk;
-        for (int b = 0; b < sp.nblk; ++b) p.hblk.push_back(s);
+        pb += sp.nbrick;
+        for (int t = 0; t < sp.nbrick; ++t) p.hbrick.push_back(s);
+        const int H = halo_cells(sp);
+        hmax = std::max(hmax, H);
+        int wmax = 0;
+        CHK(wall_halo_max(p, sp, &wmax));
+        if (wmax > wall_want) *worst_slot = s;
+        wall_want = std::max(wall_want, wmax);
+        const double occ = (double)sp.nv / sp.ncell;
+        lds_want = std::max(lds_want, 2.0 * H * occ + 128.0);
     }
-    p.nlog = (int)p.hblk.size();
-    if (p.nlog > p.nbt) return fail(PMD_ENOMEM, "pool workgroup table too small (%d > %d)", p.nlog, p.nbt);
-    if (p.nlog) HIPCHK(hipMemcpy(p.d_blk, p.hblk.data(), sizeof(int) * p.hblk.size(), hipMemcpyHostToDevice));
+    p.nchunk = (int)p.hchunk.size();
+    p.ntile = (int)p.htile.size();
+    p.nbrick = (int)p.hbrick.size();
+    p.hmax = std::max(hmax, 1);
+    const size_t ab = tile_atom_bytes(p.precision);
+    const size_t ints = (size_t)(2 * p.hmax + 1) * 4;
+    const int lds_max = (int)((kTileBytesMax - std::min(ints, kTileBytesMax / 2)) / ab);
+    p.lds_atoms = std::max(std::min((int)lds_want, lds_max), std::min(p.lds_atoms, lds_max));
+    p.wall_lds = wall_want;
+    auto one = [&](int cap) { return ((size_t)cap * ab + (size_t)(2 * p.hmax + 1) * 4 + 31) & ~(size_t)31; };
+    *list_lds = one(p.lds_atoms) + one(p.wall_lds);
+    if (*worst_slot < 0) *worst_slot = 0;
+    if (p.nchunk > p.vt / kChunk) return fail(PMD_ENOMEM, "pool chunk table too small");
+    if (p.ntile > p.tcap) return fail(PMD_ENOMEM, "pool tile table too small");
+    if (pb > p.nbt) return fail(PMD_ENOMEM, "pool brick table too small (%d > %d)", pb, p.nbt);
+    if (p.nchunk)
+        HIPCHK(hipMemcpy(p.d_chunk, p.hchunk.data(), sizeof(int) * p.hchunk.size(), hipMemcpyHostToDevice));
+    if (p.ntile)
+        HIPCHK(hipMemcpy(p.d_tile, p.htile.data(), sizeof(int) * p.htile.size(), hipMemcpyHostToDevice));
+    if (p.nbrick)
+        HIPCHK(hipMemcpy(p.d_brick, p.hbrick.data(), sizeof(int) * p.hbrick.size(), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(p.d_sp, p.hsp.data(), sizeof(SysParams) * p.nslots, hipMemcpyHostToDevice));
     p.dirty = true;
     return PMD_OK;
 }
 
+// Brick shape: the largest brick (at most 8 cells per axis) whose expected
+// atom count fits `target`, preferring near-cubic shapes (smallest halo per
+// cell); `target` scales with the workgroup size.
+void choose_bricks(SysParams& sp, double target)
+{
+    const double occ = std::max((double)sp.nv / sp.ncell, 1e-3);
+    int best[3] = {1, 1, 1};
+    double best_score = -1.0;
+    for (int bx = 1; bx <= std::min(8, sp.nc[0]); ++bx)
+        for (int by = 1; by <= std::min(8, sp.nc[1]); ++by)
+            for (int bz = 1; bz <= std::min(8, sp.nc[2]); ++bz) {
+                const int P = bx * by * bz;
+                if (P * occ > target && P > 1) continue;
+                const double halo = (double)(bx + 2) * (by + 2) * (bz + 2) / P;
+                const double score = P - 0.01 * halo;
+                if (score > best_score) {
+                    best_score = score;
+                    best[0] = bx;
+                    best[1] = by;
+                    best[2] = bz;
+                }
+            }
+    sp.bcells = 1;
+    sp.nbrick = 1;
+    for (int k = 0; k < 3; ++k) {
+        sp.bdim[k] = best[k];
+        sp.nbk[k] = (sp.nc[k] + best[k] - 1) / best[k];
+        sp.bcells *= best[k];
+        sp.nbrick *= sp.nbk[k];
+    }
+    sp.nkey = sp.nbrick * sp.bcells;
+}
+
+// Upper bound of nkey + 2 over every brick shape choose_bricks can pick.
+int key_capacity(const Grid& g) { return (g.nc[0] + 7) * (g.nc[1] + 7) * (g.nc[2] + 7) + 2; }
+int key_capacity(const SysParams& sp) { return (sp.nc[0] + 7) * (sp.nc[1] + 7) * (sp.nc[2] + 7) + 2; }
+
+// A brick's halo overflowed the LDS tile: grow the tile up to its limit,
+// then shrink the system's bricks.  The next rebuild uses the new layout.
+int pool_fix_tile(Pool& p, int slot)
+{
+    const size_t ab = tile_atom_bytes(p.precision);
+    const size_t ints = (size_t)(2 * p.hmax + 1) * 4;
+    const int lds_max = (int)((kTileBytesMax - std::min(ints, kTileBytesMax / 2)) / ab);
+    if (p.lds_atoms < lds_max) {
+        p.lds_atoms = std::min(lds_max, 2 * p.lds_atoms);
+        p.dirty = true;
+        return PMD_OK;
+    }
+    SysParams& sp = p.hsp[slot];
+    if (sp.bcells == 1) return fail(PMD_ENOMEM, "a single cell's neighbourhood exceeds the LDS tile");
+    const double occ = std::max((double)sp.nv / sp.ncell, 1e-3);
+    choose_bricks(sp, 0.5 * sp.bcells * occ);
+    return pool_layout(p);
+}
+
 void fill_sys_params(SysParams& sp, const pmd_params& p, const Grid& g, const pmd_tuning& t,
-                     int nv, int nw)
+                     int nv, int nw, double brick_target = 0.0)
 {
     for (int k = 0; k < 3; ++k) {
         sp.L[k] = p.box[k];
@@ -450,12 +626,15 @@ void fill_sys_params(SysParams& sp, const pmd_params& p, const Grid& g, const pm
     sp.rc2 = rc2;
     const double rl = p.cutoff + t.skin;
     sp.rl2 = rl * rl;
+    const double rw = p.cutoff + 0.5 * t.skin;
+    sp.rw2 = rw * rw;
     sp.dt = p.dt;
     sp.mass = p.mass;
     sp.inv_mass = 1.0 / p.mass;
     sp.half_skin = (float)(0.5 * t.skin * (1.0 - 1e-3));
     sp.energy_every = t.energy_every;
     sp.active = 1;
+    choose_bricks(sp, brick_target > 0 ? brick_target : 0.8 * t.block);
 }
 
 // Capture `reps` replays of [rebuild, R steps] into one graph.
@@ -560,7 +739,9 @@ int sys_sync(pmd_system* s)
         if (st.status & ST_NONFINITE)
             return fail(PMD_ENUMERIC, "non-finite force or position at step %lld", (long long)st.step);
         if (st.remaining <= 0) return PMD_OK;
-        if (st.status & ST_OVERFLOW) {
+        if (st.status & ST_TILE) {
+            CHK(pool_fix_tile(p, s->slot));
+        } else if (st.status & ST_OVERFLOW) {
             const int need = round_up(std::max(st.max_nbr + st.max_nbr / 4 + 8, p.cap + 16), 16);
             if (need > 4096) return fail(PMD_ENOMEM, "neighbour list needs %d entries per atom", need);
             CHK(pool_grow_lists(p, need));
@@ -626,7 +807,7 @@ int move_system(Pool& src, int sslot, Pool& dst, int dslot)
     for (auto& v : wcs) v = v - a.woff + b.woff;
     HIPCHK(hipMemcpy(dst.wcstart + b.wcoff, wcs.data(), sizeof(int) * wcs.size(), hipMemcpyHostToDevice));
     // vapour cell tables: copy so that debug readbacks of a resting system stay valid
-    std::vector<int> cs((size_t)a.ncell + 2);
+    std::vector<int> cs((size_t)a.nkey + 2);
     HIPCHK(hipMemcpy(cs.data(), src.cstart + a.coff, sizeof(int) * cs.size(), hipMemcpyDeviceToHost));
     for (auto& v : cs) v = v - a.voff + b.voff;
     HIPCHK(hipMemcpy(dst.cstart + b.coff, cs.data(), sizeof(int) * cs.size(), hipMemcpyHostToDevice));
@@ -660,9 +841,9 @@ Needs needs_of(const SysParams& sp)
     Needs n;
     n.vt = sp.vcap;
     n.wt = sp.nw;
-    n.ct = sp.ncell + 2;
+    n.ct = key_capacity(sp);
     n.wct = sp.ncell + 1;
-    n.nbt = sp.vcap / 64;
+    n.nbt = key_capacity(sp);
     return n;
 }
 
@@ -690,9 +871,9 @@ int make_single_pool(const Pool& like, const SysParams& sp_in, hipStream_t strea
     sp.ering_cap = p.ering_cap;
     p.vt = sp.vcap;
     p.wt = std::max(sp.nw, 1);
-    p.ct = sp.ncell + 2;
+    p.ct = key_capacity(sp);
     p.wct = sp.ncell + 1;
-    p.nbt = sp.vcap / 64;
+    p.nbt = key_capacity(sp);
     p.stream = stream;
     p.own_stream = own_stream;
     if (!p.stream) {
@@ -733,7 +914,7 @@ int batch_repack(pmd_batch* b, const Needs& extra, int extra_cap)
     p.wt = (int)(tot.wt * 1.25) + 1;
     p.ct = (int)(tot.ct * 1.25) + 8;
     p.wct = (int)(tot.wct * 1.25) + 8;
-    p.nbt = p.vt / 64;
+    p.nbt = p.vt / kChunk;
     if (b->budget) {
         size_t want = pool_bytes(p.precision, p.vt, p.wt, p.ct, p.wct, p.nbt, p.nslots, p.cap, p.ering_cap);
         if (want > b->budget) {
@@ -741,7 +922,7 @@ int batch_repack(pmd_batch* b, const Needs& extra, int extra_cap)
             p.wt = std::max(tot.wt, 1);
             p.ct = tot.ct;
             p.wct = tot.wct;
-            p.nbt = p.vt / 64;
+            p.nbt = p.vt / kChunk;
         }
     }
     p.stream = old->stream;
@@ -768,6 +949,7 @@ int batch_repack(pmd_batch* b, const Needs& extra, int extra_cap)
     CHK(pool_layout(p));
     for (size_t s = 0; s < b->resident.size(); ++s)
         if (b->resident[s]) CHK(move_system(*old, (int)s, p, (int)s));
+    CHK(pool_layout(p));
     // hand the stream over: the old pool must not destroy it
     const bool owned = old->own_stream;
     old->own_stream = false;
@@ -795,7 +977,7 @@ bool batch_bump(pmd_batch* b, const Needs& n, SysParams* sp)
     }
     int nbt = 0;
     for (size_t s = 0; s < b->resident.size(); ++s)
-        if (b->resident[s]) nbt += p.hsp[s].vcap / 64;
+        if (b->resident[s]) nbt += p.hsp[s].vcap / kChunk;
     if (vo + n.vt > p.vt || wo + n.wt > p.wt || co + n.ct > p.ct || wco + n.wct > p.wct ||
         nbt + n.nbt > p.nbt)
         return false;
@@ -847,8 +1029,8 @@ int pmd_footprint_bytes(const pmd_params* params, const pmd_pore* pore, int64_t 
         const int ncell = g.nc[0] * g.nc[1] * g.nc[2];
         const int vcap = round_up((int)n_vapor, kPad);
         const int nw = (int)host_wall_count(*params, *pore);
-        *out = pool_bytes(params->precision, vcap, std::max(nw, 1), ncell + 2, ncell + 1,
-                          vcap / 64, 1, t.list_cap, kDefaultErings);
+        *out = pool_bytes(params->precision, vcap, std::max(nw, 1), key_capacity(g), ncell + 1,
+                          key_capacity(g), 1, t.list_cap, kDefaultErings);
         return PMD_OK;
     } catch (...) {
         return fail(PMD_EHIP, "unexpected exception");
@@ -901,9 +1083,9 @@ int pmd_create_system(const pmd_params* params, const pmd_pore* pore, int64_t n_
         fill_sys_params(sp, *params, sys->grid, sys->tuning, (int)n_vapor, (int)nw);
         p.vt = sp.vcap;
         p.wt = (int)std::max<int64_t>(nw, 1);
-        p.ct = sp.ncell + 2;
+        p.ct = key_capacity(sys->grid);
         p.wct = sp.ncell + 1;
-        p.nbt = sp.vcap / 64;
+        p.nbt = key_capacity(sys->grid);
         sp.voff = 0;
         sp.woff = 0;
         sp.coff = 0;
@@ -948,6 +1130,8 @@ int pmd_create_system(const pmd_params* params, const pmd_pore* pore, int64_t n_
             }
         }
         HIPCHK(launch_wall_bin(p.dev(), 0, raw, (int)nw, (int)nw, p.precision, p.stream));
+        HIPCHK(hipStreamSynchronize(p.stream));
+        CHK(pool_layout(p));  // wall halo sizes need the binned walls
 
         // vapour: copy in (caller order), then bin, build lists and compute a(0)
         double* dpos = nullptr;
@@ -967,14 +1151,16 @@ int pmd_create_system(const pmd_params* params, const pmd_pore* pore, int64_t n_
         sys->slot = 0;
         Pool& q = *sys->pool;
         HIPCHK(launch_set_run(q.dev(), 0, 0, 1, q.stream));
-        for (int attempt = 0; attempt < 4; ++attempt) {
+        for (int attempt = 0; attempt < 8; ++attempt) {
             HIPCHK(launch_rebuild(q.dev(), q.nslots, q.precision, q.stream));
             HIPCHK(launch_step(q.dev(), q.precision, q.stream, nullptr, nullptr));
             SysState st;
             CHK(read_state(q, 0, &st));
             if (st.status & ST_NONFINITE) return fail(PMD_ENUMERIC, "non-finite initial forces");
             if (st.phase == PH_REST) break;
-            if (st.status & ST_OVERFLOW) {
+            if (st.status & ST_TILE) {
+                CHK(pool_fix_tile(q, 0));
+            } else if (st.status & ST_OVERFLOW) {
                 const int need = round_up(st.max_nbr + st.max_nbr / 4 + 8, 16);
                 if (need > 4096) return fail(PMD_ENOMEM, "neighbour list needs %d entries", need);
                 CHK(pool_grow_lists(q, need));
@@ -1149,8 +1335,8 @@ int pmd_set_tuning(pmd_system* sys, const pmd_tuning* tuning)
         if (g.nc[0] != sys->grid.nc[0] || g.nc[1] != sys->grid.nc[1] || g.nc[2] != sys->grid.nc[2]) {
             // a different cell grid needs larger cell arrays: only allow grids
             // that fit the allocated ones
-            const int ncell = g.nc[0] * g.nc[1] * g.nc[2];
-            if (ncell + 2 > sys->pool->ct) return fail(PMD_EINVAL, "skin too small for the allocated cell grid");
+            if (key_capacity(g) > sys->pool->ct || g.nc[0] * g.nc[1] * g.nc[2] + 1 > sys->pool->wct)
+                return fail(PMD_EINVAL, "skin too small for the allocated cell grid");
         }
         Pool& p = *sys->pool;
         if (t.list_cap > p.cap) CHK(pool_grow_lists(p, t.list_cap));
@@ -1263,11 +1449,19 @@ int pmd_debug_cells(pmd_system* sys, int32_t* cell_of_atom, int64_t n, int32_t* 
         if (n != sys->nv || n_cells_p1 != sp.ncell + 1) return fail(PMD_EINVAL, "size mismatch");
         SysState st;
         CHK(read_state(p, sys->slot, &st));
-        std::vector<int> ids(sp.vcap), cl(sp.vcap), cs(sp.ncell + 2);
+        std::vector<int> ids(sp.vcap), cl(sp.vcap), cs(sp.nkey + 2);
         HIPCHK(hipMemcpy(ids.data(), p.id[st.sbuf] + sp.voff, sizeof(int) * sp.vcap, hipMemcpyDeviceToHost));
         HIPCHK(hipMemcpy(cl.data(), p.cell_lin + sp.voff, sizeof(int) * sp.vcap, hipMemcpyDeviceToHost));
-        HIPCHK(hipMemcpy(cs.data(), p.cstart + sp.coff, sizeof(int) * (sp.ncell + 2), hipMemcpyDeviceToHost));
-        for (int c = 0; c <= sp.ncell; ++c) cell_start[c] = cs[c] - sp.voff;
+        HIPCHK(hipMemcpy(cs.data(), p.cstart + sp.coff, sizeof(int) * (sp.nkey + 2), hipMemcpyDeviceToHost));
+        // first storage position of each cell (cells are stored brick by brick)
+        for (int c = 0; c < sp.ncell; ++c) {
+            const int cx = c % sp.nc[0], cy = (c / sp.nc[0]) % sp.nc[1], cz = c / (sp.nc[0] * sp.nc[1]);
+            const int Bx = cx / sp.bdim[0], By = cy / sp.bdim[1], Bz = cz / sp.bdim[2];
+            const int key = (Bx + sp.nbk[0] * (By + sp.nbk[1] * Bz)) * sp.bcells +
+                            (cx - Bx * sp.bdim[0]) + sp.bdim[0] * ((cy - By * sp.bdim[1]) + sp.bdim[1] * (cz - Bz * sp.bdim[2]));
+            cell_start[c] = cs[key] - sp.voff;
+        }
+        cell_start[sp.ncell] = sp.nv;
         for (int q = 0; q < sp.nv; ++q) {
             perm[q] = ids[q];
             cell_of_atom[ids[q]] = cl[q];
@@ -1292,7 +1486,7 @@ int pmd_debug_pairs(pmd_system* sys, int32_t* vv, int64_t cap, int64_t* n_vv, in
         HIPCHK(hipMalloc(&out, sizeof(int) * (3 * (size_t)maxp + 1)));
         int* counts = out + 3 * (size_t)maxp;
         hipError_t e = hipMemsetAsync(counts, 0, sizeof(int), p.stream);
-        if (e == hipSuccess) e = launch_debug_pairs(p.dev(), sys->slot, sp.nv, out, maxp, counts, p.stream);
+        if (e == hipSuccess) e = launch_debug_pairs(p.dev(), sys->slot, p.precision, out, maxp, counts, p.stream);
         int total = 0;
         if (e == hipSuccess) e = hipMemcpyAsync(&total, counts, sizeof(int), hipMemcpyDeviceToHost, p.stream);
         if (e == hipSuccess) e = hipStreamSynchronize(p.stream);
@@ -1400,7 +1594,7 @@ int pmd_batch_admit(pmd_batch* b, pmd_system* sys, int64_t nsteps, int* slot)
             np->vt = kPad;
             np->wt = 1;
             np->ct = np->wct = 8;
-            np->nbt = kPad / 64;
+            np->nbt = kPad / kChunk;
             CHK(pool_allocate(*np));
             np->hsp.assign(np->nslots, SysParams{});
             CHK(pool_layout(*np));
@@ -1420,6 +1614,7 @@ int pmd_batch_admit(pmd_batch* b, pmd_system* sys, int64_t nsteps, int* slot)
         p.hsp[free_slot] = sp;
         CHK(pool_layout(p));
         CHK(move_system(sp0, sys->slot, p, free_slot));
+        CHK(pool_layout(p));
         b->resident[free_slot] = sys;
         b->steps_wanted[free_slot] = nsteps;
         sys->own.reset();
@@ -1466,7 +1661,9 @@ static int batch_poll_impl(pmd_batch* b, int* done, int cap, int* n_done, bool w
     int need = p.cap;
     for (int s = 0; s < p.nslots; ++s) {
         if (!b->resident[s]) continue;
-        if (st[s].status & ST_OVERFLOW) {
+        if (st[s].status & ST_TILE) {
+            CHK(pool_fix_tile(p, s));
+        } else if (st[s].status & ST_OVERFLOW) {
             grow = true;
             need = std::max(need, st[s].max_nbr + st[s].max_nbr / 4 + 8);
         }
@@ -1503,6 +1700,7 @@ int pmd_batch_release(pmd_batch* b, int slot, pmd_system** sys_out)
         CHK(make_single_pool(p, p.hsp[slot], nullptr, false, &own));
         CHK(move_system(p, slot, *own, 0));
         own->cap = p.cap;
+        CHK(pool_layout(*own));
         b->resident[slot] = nullptr;
         b->steps_wanted[slot] = 0;
         p.hsp[slot] = SysParams{};

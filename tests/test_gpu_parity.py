@@ -137,8 +137,13 @@ def test_cells_bit_exact_vs_counting_sort():
     assert np.array_equal(inv, nc / L)
     rc, rs, rp = oracle.cell_sort(x, inv, nc)
     assert np.array_equal(cell, rc)
-    assert np.array_equal(start, rs)
-    assert np.array_equal(perm, rp)
+    # storage groups cells brick by brick; inside every cell the atoms must
+    # be exactly the counting sort's, in ascending caller order
+    assert start[-1] == len(x)
+    assert sorted(perm.tolist()) == list(range(len(x)))
+    for c in range(int(np.prod(nc))):
+        k = rs[c + 1] - rs[c]
+        assert np.array_equal(perm[start[c]:start[c] + k], rp[rs[c]:rs[c + 1]])
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
