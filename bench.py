@@ -115,6 +115,7 @@ def main():
     ap.add_argument("--skin", type=float, default=0.0)
     ap.add_argument("--rebin-every", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--brick-atoms", type=int, default=0)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=16384)
@@ -136,7 +137,8 @@ def main():
     desc = synth.slit_large(n=args.n, box=args.box)
     log("inputs: %d vapour atoms, box %g, generated in %.1f s"
         % (desc.n, args.box, time.perf_counter() - t0))
-    tkw = dict(skin=args.skin, rebin_every=args.rebin_every, block=args.block)
+    tkw = dict(skin=args.skin, rebin_every=args.rebin_every, block=args.block,
+               brick_atoms=args.brick_atoms)
 
     res = {}
     for prec in (["mixed"] if args.no_fp64 else ["mixed", "fp64"]):

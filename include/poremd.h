@@ -116,7 +116,7 @@ typedef struct {
     int32_t list_cap;
     int32_t energy_every;
     int32_t use_graph;    /* 1: replay captured HIP graphs; 0: plain launches */
-    int32_t reserved;
+    int32_t brick_atoms;  /* target atoms per brick (workgroup); 0 = 0.8 x block */
 } pmd_tuning;
 
 typedef struct pmd_system pmd_system;

@@ -163,7 +163,7 @@ hipError_t launch_wall_bin(const PoolDev& P, int sys, const double* raw_soa, int
                            int nw, int precision, hipStream_t s);
 hipError_t launch_rebuild(const PoolDev& P, int nslots, int precision, hipStream_t s);
 hipError_t launch_set_run(const PoolDev& P, int slot, int add_steps, int phase_init, hipStream_t s);
-hipError_t launch_step(const PoolDev& P, int precision, hipStream_t s, hipEvent_t ev0,
+hipError_t launch_step(const PoolDev& P, int nslots, int precision, hipStream_t s, hipEvent_t ev0,
                        hipEvent_t ev1);
 hipError_t launch_unpermute(const PoolDev& P, int slot, int which, double* out_aos,
                             int n, hipStream_t s);

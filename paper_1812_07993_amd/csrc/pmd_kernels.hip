@@ -433,20 +433,18 @@ __global__ void k_bin_count(PoolDev P)
     P.arr[c.i] = atomicAdd(&P.count[sp.coff + cell], 1);
 }
 
-// One workgroup (1024 threads x 4 cells) per scan tile.  Each writes the
-// exclusive prefix of its tile and the tile sum; the last tile of a system
-// to finish turns the tile sums into slot offsets and advances the system's
-// rebuild state.  Counts run over ncell + 2 entries (cells, padding cell, a
-// zero end entry), so the prefix at ncell + 1 is the system's slot count.
+// One workgroup (1024 threads x 4 cells) per scan tile writes the exclusive
+// prefix of its tile and the tile sum.  Counts run over nkey + 2 entries
+// (cells, padding cell, a zero end entry), so the prefix at nkey + 1 is the
+// system's slot count.
 __global__ void __launch_bounds__(1024) k_bin_scan(PoolDev P)
 {
     __shared__ int lds[17];
-    __shared__ int am_last;
     const int tile = blockIdx.x;
     if (tile >= P.ntile) return;
     const int s = P.tile_sys[tile];
     const SysParams& sp = P.sp[s];
-    SysState* st = P.st + s;
+    const SysState* st = P.st + s;
     if (!sp.active || st->remaining <= 0 || (st->status & ST_NONFINITE)) return;
     const int lt = tile - sp.toff;
     const int M = sp.nkey + 2;
@@ -465,22 +463,24 @@ __global__ void __launch_bounds__(1024) k_bin_scan(PoolDev P)
             run += v[k];
             cnt[c0 + k] = 0;
         }
-    if (threadIdx.x == 0) {
-        P.ctile[sp.toff + lt] = tot;
-        __threadfence();
-        const int prev = atomicAdd(&st->tiles_done, 1);
-        am_last = prev == sp.ntile - 1;
-    }
-    __syncthreads();
-    if (!am_last || threadIdx.x != 0) return;
-    __threadfence();
+    if (threadIdx.x == 0) P.ctile[sp.toff + lt] = tot;
+}
+
+// One workgroup per system: tile sums -> slot offsets; advance the rebuild
+// state (swap the state buffers, clear halts, start the run).
+__global__ void k_bin_scan_finish(PoolDev P, int nslots)
+{
+    const int s = blockIdx.x;
+    if (s >= nslots || threadIdx.x != 0) return;
+    const SysParams& sp = P.sp[s];
+    SysState* st = P.st + s;
+    if (!sp.active || st->remaining <= 0 || (st->status & ST_NONFINITE)) return;
     int off = sp.voff;
     for (int t = 0; t < sp.ntile; ++t) {
-        const int q = __hip_atomic_load(&P.ctile[sp.toff + t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int q = P.ctile[sp.toff + t];
         P.ctile[sp.toff + t] = off;
         off += q;
     }
-    st->tiles_done = 0;
     st->sbuf_prev = st->sbuf;
     st->sbuf ^= 1;
     st->status &= ~(ST_HALT | ST_OVERFLOW | ST_TILE);
@@ -711,9 +711,18 @@ __device__ __forceinline__ int halo_cell(const HaloGeo& g, int cx, int cy, int c
     return hx + g.hd[0] * (hy + g.hd[1] * hz);
 }
 
+// Squared distance from a point at local offset l (from its cell's origin,
+// 0 <= l < h) to the box of the neighbour cell at offset d (-1, 0, 1).
+__device__ __forceinline__ double box_gap(double l, int d, double h)
+{
+    return d < 0 ? l : d > 0 ? h - l : 0.0;
+}
+
 // Neighbour lists (radius r_c + skin for vapour, r_c + skin/2 for the fixed
 // walls) of the atoms of one brick, in a fixed order: neighbour cells 0..26,
-// staged order inside a cell; vapour entries first, then walls.
+// staged order inside a cell; vapour entries first, then walls.  Vapour
+// entries index the brick's staged tile, which the step kernel rebuilds
+// identically from the same cell tables; wall entries are wall slots.
 template <typename T>
 __global__ void __launch_bounds__(256) k_list_build(PoolDev P)
 {
@@ -739,15 +748,22 @@ __global__ void __launch_bounds__(256) k_list_build(PoolDev P)
         return;
     }
     const T rl2 = (T)sp.rl2, rw2 = (T)sp.rw2;
+    // cells farther than the radius cannot hold a partner (with a margin for
+    // the rounding of the local coordinates)
+    const double cull_v = sp.rl2 * (1.0 + 1e-6), cull_w = sp.rw2 * (1.0 + 1e-6);
     const int cap = P.cap;
     int mx = 0;
     for (int i = i0 + (int)threadIdx.x; i < i1; i += blockDim.x) {
         const V me = Lc[i];
         const int cr = P.cref[i];
         const int cx = cr & 1023, cy = (cr >> 10) & 1023, cz = cr >> 20;
+        const double lx = (double)me.x, ly = (double)me.y, lz = (double)me.z;
         int nv = 0;
         for (int q = 0; q < 27; ++q) {
             const int dx = q % 3 - 1, dy = (q / 3) % 3 - 1, dz = q / 9 - 1;
+            const double gx = box_gap(lx, dx, sp.h[0]), gy = box_gap(ly, dy, sp.h[1]),
+                         gz = box_gap(lz, dz, sp.h[2]);
+            if (gx * gx + gy * gy + gz * gz >= cull_v) continue;
             const T sx = (T)(-dx * sp.h[0]), sy = (T)(-dy * sp.h[1]), sz = (T)(-dz * sp.h[2]);
             const int h = halo_cell(g, cx, cy, cz, q);
             const int a1 = t.hoff[h + 1];
@@ -763,6 +779,9 @@ __global__ void __launch_bounds__(256) k_list_build(PoolDev P)
         int nw = 0;
         for (int q = 0; q < 27; ++q) {
             const int dx = q % 3 - 1, dy = (q / 3) % 3 - 1, dz = q / 9 - 1;
+            const double gx = box_gap(lx, dx, sp.h[0]), gy = box_gap(ly, dy, sp.h[1]),
+                         gz = box_gap(lz, dz, sp.h[2]);
+            if (gx * gx + gy * gy + gz * gz >= cull_w) continue;
             const T sx = (T)(-dx * sp.h[0]), sy = (T)(-dy * sp.h[1]), sz = (T)(-dz * sp.h[2]);
             const int h = halo_cell(g, cx, cy, cz, q);
             const int a1 = tw.hoff[h + 1];
@@ -797,7 +816,6 @@ size_t tile_bytes(const PoolDev& P, int precision, bool walls)
 
 hipError_t launch_rebuild(const PoolDev& P, int nslots, int precision, hipStream_t s)
 {
-    (void)nslots;
     const int nrb = P.nchunk / (kRebuildBlock / kChunk);
     const int G = ((nrb + 7) / 8) * 8;
     const int GB = ((P.nbrick + 7) / 8) * 8;
@@ -805,6 +823,7 @@ hipError_t launch_rebuild(const PoolDev& P, int nslots, int precision, hipStream
     const size_t lds = tile_bytes(P, precision, true);
     hipLaunchKernelGGL(k_bin_count, dim3(G), dim3(kRebuildBlock), 0, s, P);
     hipLaunchKernelGGL(k_bin_scan, dim3(P.ntile), dim3(1024), 0, s, P);
+    hipLaunchKernelGGL(k_bin_scan_finish, dim3(nslots), dim3(64), 0, s, P, nslots);
     hipLaunchKernelGGL(k_bin_scatter, dim3(G), dim3(kRebuildBlock), 0, s, P);
     if (precision == 1) {
         hipLaunchKernelGGL(k_bin_place<float>, dim3(G), dim3(kRebuildBlock), 0, s, P);
@@ -838,7 +857,6 @@ __global__ void __launch_bounds__(256) k_step(PoolDev P)
     __shared__ double red[3][4];
     __shared__ int flag_or[4];
     __shared__ int lds_scan[17];
-    __shared__ int am_last;
 
     BrickCtx c;
     if (!brick_ctx(P, c, ST_HALT | ST_OVERFLOW | ST_NONFINITE)) return;
@@ -882,27 +900,31 @@ __global__ void __launch_bounds__(256) k_step(PoolDev P)
         const int nvap = nl & 0xFFFF, nall = nvap + (nl >> 16);
         double fx = 0.0, fy = 0.0, fz = 0.0, eav = 0.0, eaw = 0.0;
         const unsigned* lst = P.list + i;
-        // entries are fetched 8 at a time, then their partners (LDS for
-        // vapour, global memory for walls): two memory latencies per group
+        // entries come 8 at a time, the next group's loads in flight while
+        // the current one is evaluated; vapour partners are read from LDS,
+        // the group's wall partners are fetched together
+        unsigned ec[kGroup];
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) ec[u] = (u < nall) ? lst[(size_t)u * vt] : 0u;
         for (int k0 = 0; k0 < nall; k0 += kGroup) {
-            unsigned e8[kGroup];
+            unsigned en[kGroup];
 #pragma unroll
             for (int u = 0; u < kGroup; ++u)
-                e8[u] = (k0 + u < nall) ? lst[(size_t)(k0 + u) * vt] : 0u;
-            V o8[kGroup];
+                en[u] = (k0 + kGroup + u < nall) ? lst[(size_t)(k0 + kGroup + u) * vt] : 0u;
+            V ow[kGroup];
 #pragma unroll
             for (int u = 0; u < kGroup; ++u) {
-                const int a = (int)(e8[u] & kIndexMask);
-                o8[u] = (k0 + u < nvap) ? tl.pos[a] : Lc[vt + ((k0 + u < nall) ? a : 0)];
+                const bool w_ = k0 + u >= nvap && k0 + u < nall;
+                ow[u] = Lc[vt + (w_ ? (int)(ec[u] & kIndexMask) : 0)];
             }
 #pragma unroll
             for (int u = 0; u < kGroup; ++u) {
                 const int k = k0 + u;
                 if (k >= nall) break;
-                const unsigned e = e8[u];
+                const unsigned e = ec[u];
                 const bool wall = k >= nvap;
                 const int a = (int)(e & kIndexMask);
-                const V o = o8[u];
+                const V o = wall ? ow[u] : tl.pos[a];
                 const V sh = tab[e >> kIndexBits];
                 const T dx = me.x - o.x + sh.x;
                 const T dy = me.y - o.y + sh.y;
@@ -945,6 +967,8 @@ __global__ void __launch_bounds__(256) k_step(PoolDev P)
                     }
                 }
             }
+#pragma unroll
+            for (int u = 0; u < kGroup; ++u) ec[u] = en[u];
         }
         evv += 0.5 * eav;
         evw += eaw;
@@ -1028,27 +1052,38 @@ __global__ void __launch_bounds__(256) k_step(PoolDev P)
             pp[1] = b;
             pp[2] = cc;
         }
-        __threadfence();
-        const int prev = atomicAdd(&P.st[s].blocks_done, 1);
-        am_last = (prev == sp.nbrick - 1);
     }
-    __syncthreads();
-    if (!am_last) return;
+}
 
-    // last workgroup of this system: finish the energy sums and the step
-    __threadfence();
+// After each step launch, one workgroup per system: sum the per-brick
+// energy partials in brick order (fixed, so the total is deterministic),
+// record them, and advance the step state.  The launch boundary makes every
+// brick's partials and status bits visible without device-wide fences.
+__global__ void __launch_bounds__(256) k_finish(PoolDev P, int nslots)
+{
+    __shared__ double red[3][4];
+    const int s = blockIdx.x;
+    if (s >= nslots) return;
+    const SysParams& sp = P.sp[s];
+    const SysState st = P.st[s];
+    if (!sp.active || st.remaining <= 0 || (st.status & (ST_HALT | ST_OVERFLOW | ST_NONFINITE)))
+        return;
+    const bool init = st.phase == PH_INIT;
+    const bool last = !init && st.remaining == 1;
+    const long long kstep = init ? 0 : st.step + 1;
+    const bool doE = init || last || (sp.energy_every > 0 && (kstep % sp.energy_every) == 0);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
+    double a = 0.0, b = 0.0, cc = 0.0;
     if (doE) {
-        double a = 0.0, b = 0.0, cc = 0.0;
         const double* pp = P.partial + 3 * (size_t)sp.pboff;
         for (int q = tid; q < sp.nbrick; q += blockDim.x) {
-            a += atomic_load_f64(pp + 3 * q);
-            b += atomic_load_f64(pp + 3 * q + 1);
-            cc += atomic_load_f64(pp + 3 * q + 2);
+            a += pp[3 * q];
+            b += pp[3 * q + 1];
+            cc += pp[3 * q + 2];
         }
         a = wave_sum(a);
         b = wave_sum(b);
         cc = wave_sum(cc);
-        __syncthreads();
         if (lane == 0) {
             red[0][wave] = a;
             red[1][wave] = b;
@@ -1056,44 +1091,40 @@ __global__ void __launch_bounds__(256) k_step(PoolDev P)
         }
         __syncthreads();
     }
-    if (tid == 0) {
-        SysState* sw = P.st + s;
-        if (doE) {
-            double a = 0.0, b = 0.0, cc = 0.0;
-            for (int w = 0; w < nwave; ++w) {
-                a += red[0][w];
-                b += red[1][w];
-                cc += red[2][w];
-            }
-            EnergyRec r;
-            r.step = kstep;
-            r.ke = a;
-            r.pe_vv = b;
-            r.pe_vw = cc;
-            P.erec[sp.ering_off + (st.nrec % sp.ering_cap)] = r;
-            sw->nrec = st.nrec + 1;
+    if (tid != 0) return;
+    SysState* sw = P.st + s;
+    if (doE) {
+        a = b = cc = 0.0;
+        for (int w = 0; w < nwave; ++w) {
+            a += red[0][w];
+            b += red[1][w];
+            cc += red[2][w];
         }
-        const int f = __hip_atomic_load(&sw->status_next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        sw->status = st.status | f;
-        sw->status_next = 0;
-        sw->blocks_done = 0;
-        if (init) {
+        EnergyRec r;
+        r.step = kstep;
+        r.ke = a;
+        r.pe_vv = b;
+        r.pe_vw = cc;
+        P.erec[sp.ering_off + (st.nrec % sp.ering_cap)] = r;
+        sw->nrec = st.nrec + 1;
+    }
+    sw->status = st.status | st.status_next;
+    sw->status_next = 0;
+    if (init) {
+        sw->phase = PH_REST;
+        sw->remaining = 0;
+    } else {
+        sw->step = kstep;
+        sw->remaining = st.remaining - 1;
+        sw->steps_since = st.steps_since + 1;
+        if (last)
             sw->phase = PH_REST;
-            sw->remaining = 0;
-        } else {
-            sw->step = kstep;
-            sw->remaining = st.remaining - 1;
-            sw->steps_since = st.steps_since + 1;
-            if (last) {
-                sw->phase = PH_REST;
-            } else {
-                sw->lbuf = st.lbuf ^ 1;
-            }
-        }
+        else
+            sw->lbuf = st.lbuf ^ 1;
     }
 }
 
-hipError_t launch_step(const PoolDev& P, int precision, hipStream_t s, hipEvent_t ev0,
+hipError_t launch_step(const PoolDev& P, int nslots, int precision, hipStream_t s, hipEvent_t ev0,
                        hipEvent_t ev1)
 {
     const int G = ((P.nbrick + 7) / 8) * 8;
@@ -1111,6 +1142,7 @@ hipError_t launch_step(const PoolDev& P, int precision, hipStream_t s, hipEvent_
         else
             hipLaunchKernelGGL(k_step<double>, dim3(G), dim3(B), lds, s, P);
     }
+    hipLaunchKernelGGL(k_finish, dim3(nslots), dim3(256), 0, s, P, nslots);
     return hipGetLastError();
 }
 
@@ -1194,8 +1226,8 @@ __global__ void k_debug_pairs(PoolDev P, int slot, int* out, int cap, int* count
     if (b >= sp.nbrick) return;
     const HaloGeo g = halo_geo(sp, b);
     Tile<T> t = tile_of<T>(smem, P);
-    const int tot = stage_halo<T>(P, sp, g, t, (const typename V4<T>::type*)P.L[st.lbuf], false,
-                                  lds_scan);
+    const typename V4<T>::type* Lc = (const typename V4<T>::type*)P.L[st.lbuf];
+    const int tot = stage_halo<T>(P, sp, g, t, Lc, false, lds_scan);
     if (tot < 0) return;
     const int vt = P.vt;
     const double* X = P.X[st.sbuf];

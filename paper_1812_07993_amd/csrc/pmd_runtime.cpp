@@ -151,8 +151,8 @@ int64_t host_wall_count(const pmd_params& p, const pmd_pore& q)
 pmd_tuning default_tuning(const pmd_params& p, int64_t nv)
 {
     pmd_tuning t{};
-    t.skin = 0.4;
-    t.rebin_every = 10;
+    t.skin = 0.5;
+    t.rebin_every = 7;
     t.block = 256;
     const double V = p.box[0] * p.box[1] * p.box[2];
     const double rho = std::max(0.3, (double)nv / V);
@@ -161,6 +161,7 @@ pmd_tuning default_tuning(const pmd_params& p, int64_t nv)
     t.list_cap = round_up((int)std::ceil(1.5 * sphere * rho) + 48, 16);
     t.energy_every = 0;
     t.use_graph = 1;
+    t.brick_atoms = 0;
     return t;
 }
 
@@ -174,6 +175,7 @@ int merge_tuning(const pmd_params& p, int64_t nv, const pmd_tuning* in, pmd_tuni
         if (in->list_cap > 0) d.list_cap = in->list_cap;
         if (in->energy_every >= 0) d.energy_every = in->energy_every;
         d.use_graph = in->use_graph;
+        if (in->brick_atoms > 0) d.brick_atoms = in->brick_atoms;
     }
     if (d.block != 64 && d.block != 128 && d.block != 256)
         return fail(PMD_EINVAL, "block must be 64, 128 or 256 (got %d)", d.block);
@@ -634,7 +636,7 @@ void fill_sys_params(SysParams& sp, const pmd_params& p, const Grid& g, const pm
     sp.half_skin = (float)(0.5 * t.skin * (1.0 - 1e-3));
     sp.energy_every = t.energy_every;
     sp.active = 1;
-    choose_bricks(sp, brick_target > 0 ? brick_target : 0.8 * t.block);
+    choose_bricks(sp, brick_target > 0 ? brick_target : t.brick_atoms > 0 ? t.brick_atoms : 0.8 * t.block);
 }
 
 // Capture `reps` replays of [rebuild, R steps] into one graph.
@@ -649,7 +651,7 @@ int pool_capture(Pool& p, int R, int reps)
     HIPCHK(hipStreamBeginCapture(p.cap_stream, hipStreamCaptureModeThreadLocal));
     for (int r = 0; r < reps; ++r) {
         launch_rebuild(d, p.nslots, p.precision, p.cap_stream);
-        for (int k = 0; k < R; ++k) launch_step(d, p.precision, p.cap_stream, nullptr, nullptr);
+        for (int k = 0; k < R; ++k) launch_step(d, p.nslots, p.precision, p.cap_stream, nullptr, nullptr);
     }
     hipGraph_t g = nullptr;
     HIPCHK(hipStreamEndCapture(p.cap_stream, &g));
@@ -682,9 +684,9 @@ int pool_enqueue(Pool& p, int R, int use_graph, int64_t replays)
                 HIPCHK(hipEventCreate(&a));
                 HIPCHK(hipEventCreate(&b));
                 p.events.emplace_back(a, b);
-                HIPCHK(launch_step(d, p.precision, p.stream, a, b));
+                HIPCHK(launch_step(d, p.nslots, p.precision, p.stream, a, b));
             } else {
-                HIPCHK(launch_step(d, p.precision, p.stream, nullptr, nullptr));
+                HIPCHK(launch_step(d, p.nslots, p.precision, p.stream, nullptr, nullptr));
             }
         }
     }
@@ -1153,7 +1155,7 @@ int pmd_create_system(const pmd_params* params, const pmd_pore* pore, int64_t n_
         HIPCHK(launch_set_run(q.dev(), 0, 0, 1, q.stream));
         for (int attempt = 0; attempt < 8; ++attempt) {
             HIPCHK(launch_rebuild(q.dev(), q.nslots, q.precision, q.stream));
-            HIPCHK(launch_step(q.dev(), q.precision, q.stream, nullptr, nullptr));
+            HIPCHK(launch_step(q.dev(), q.nslots, q.precision, q.stream, nullptr, nullptr));
             SysState st;
             CHK(read_state(q, 0, &st));
             if (st.status & ST_NONFINITE) return fail(PMD_ENUMERIC, "non-finite initial forces");

@@ -13,7 +13,7 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "_build", "libporemd.so")
+LIB_PATH = os.environ.get("PMD_LIBRARY") or os.path.join(_HERE, "_build", "libporemd.so")
 
 PMD_OK, PMD_EINVAL, PMD_ENOMEM, PMD_EHIP, PMD_ENUMERIC, PMD_EAGAIN, PMD_ESTATE = (
     0, -1, -2, -3, -4, -5, -6)
@@ -53,7 +53,7 @@ class pmd_tuning(ctypes.Structure):
     _fields_ = [("skin", ctypes.c_double), ("rebin_every", ctypes.c_int32),
                 ("block", ctypes.c_int32), ("list_cap", ctypes.c_int32),
                 ("energy_every", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("brick_atoms", ctypes.c_int32)]
 
 
 _lib = None
@@ -158,10 +158,10 @@ def make_pore(kind="none", lattice_a=1.0, slab_center_z=0.0, slab_thickness=0.0,
 
 
 def make_tuning(skin=0.0, rebin_every=0, block=0, list_cap=0, energy_every=0,
-                use_graph=1) -> pmd_tuning:
+                use_graph=1, brick_atoms=0) -> pmd_tuning:
     t = pmd_tuning()
     t.skin, t.rebin_every, t.block, t.list_cap = skin, rebin_every, block, list_cap
-    t.energy_every, t.use_graph = energy_every, use_graph
+    t.energy_every, t.use_graph, t.brick_atoms = energy_every, use_graph, brick_atoms
     return t
 
 
