@@ -104,6 +104,30 @@ def cpu_baseline(desc, sample_atoms, seed=0):
                        % (desc.n + walls.shape[0], sample_atoms, dt))
 
 
+def serve_leg(n_requests, budget_gb, chunk):
+    """Served trace: Poisson arrivals at 200 requests/s, vapour N log-uniform in
+    [2k, 500k], pore from {cylinder, slit, cone, ink-bottle}, 1k-20k steps,
+    mixed or FP64 with probability 1/2; one batch per precision, each bounded
+    by the device budget."""
+    from paper_1812_07993_amd import serve, synth
+
+    t0 = time.perf_counter()
+    specs = synth.request_trace(n_requests)
+    reqs = [serve.Request(s["index"], s["arrival"], s["precision"], s["steps"], s["n"],
+                          synth.request_system(s)) for s in specs]
+    log("serve: %d requests generated in %.1f s (%.2e atom-steps offered)"
+        % (len(reqs), time.perf_counter() - t0, sum(r.n * r.steps for r in reqs)))
+    be = serve.PoremdBackend(hbm_budget=int(budget_gb * 2 ** 30), max_slots=256)
+    res = serve.Server(be, chunk_steps=chunk).run(reqs)
+    s = serve.summarize(res)
+    span_arrivals = max(r.arrival for r in reqs) - min(r.arrival for r in reqs)
+    s["offered_req_per_s"] = (len(reqs) - 1) / span_arrivals if span_arrivals > 0 else None
+    s["budget_gb_per_precision"] = budget_gb
+    log("serve: p50 %.3f s, p99 %.3f s, %.3e atom-steps/s over %.2f s"
+        % (s["p50_s"], s["p99_s"], s["atom_steps_per_s"], s["makespan_s"]))
+    return s
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -118,7 +142,11 @@ def main():
     ap.add_argument("--brick-atoms", type=int, default=0)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=16384)
+    ap.add_argument("--cpu-sample", type=int, default=65536)
+    ap.add_argument("--serve-requests", type=int, default=24,
+                    help="requests of the served trace (0 = skip the serving leg)")
+    ap.add_argument("--serve-budget-gb", type=float, default=2.0)
+    ap.add_argument("--serve-chunk", type=int, default=250)
     ap.add_argument("--timing-steps", type=int, default=500)
     args = ap.parse_args()
 
@@ -209,6 +237,10 @@ def main():
         out["mixed_over_fp64"] = out["value"] / out["fp64"]["value"]
     for r in res.values():
         r["sys"].close()
+    if args.serve_requests > 0:
+        out["serve"] = serve_leg(args.serve_requests, args.serve_budget_gb, args.serve_chunk)
+        out["served_p50_s"] = out["serve"]["p50_s"]
+        out["served_p99_s"] = out["serve"]["p99_s"]
     if not args.no_cpu:
         log("timing the oracle on the host ...")
         out["cpu_baseline"] = cpu_baseline(desc, args.cpu_sample)

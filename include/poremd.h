@@ -132,8 +132,9 @@ int pmd_version(void);
  * only; no device work). */
 int pmd_wall_count(const pmd_params *params, const pmd_pore *pore, int64_t *n_wall);
 
-/* Device bytes a system of n_vapor molecules with this pore needs, with the
- * given tuning (NULL = defaults).  Used for admission by footprint. */
+/* Device bytes a system of n_vapor molecules with this pore occupies in a
+ * batch, with the given tuning (NULL = defaults): the figure pmd_batch_admit
+ * charges against the batch's budget. */
 int pmd_footprint_bytes(const pmd_params *params, const pmd_pore *pore,
                         int64_t n_vapor, const pmd_tuning *tuning, size_t *out);
 

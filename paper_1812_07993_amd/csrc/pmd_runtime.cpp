@@ -1028,11 +1028,10 @@ int pmd_footprint_bytes(const pmd_params* params, const pmd_pore* pore, int64_t 
         CHK(merge_tuning(*params, n_vapor, tuning, &t));
         Grid g;
         CHK(grid_for(*params, t.skin, &g));
-        const int ncell = g.nc[0] * g.nc[1] * g.nc[2];
-        const int vcap = round_up((int)n_vapor, kPad);
-        const int nw = (int)host_wall_count(*params, *pore);
-        *out = pool_bytes(params->precision, vcap, std::max(nw, 1), key_capacity(g), ncell + 1,
-                          key_capacity(g), 1, t.list_cap, kDefaultErings);
+        SysParams sp{};
+        fill_sys_params(sp, *params, g, t, (int)n_vapor, (int)host_wall_count(*params, *pore));
+        // the same accounting a batch uses when it admits the system
+        *out = system_bytes(params->precision, sp, t.list_cap);
         return PMD_OK;
     } catch (...) {
         return fail(PMD_EHIP, "unexpected exception");

@@ -1,0 +1,154 @@
+"""GPU tests at the workloads' real shapes, batching and energy conservation.
+
+Tolerances: relative force error <= 1e-5 (mixed) and <= 1e-12 (FP64) at
+identical positions; energy drift trend <= 1e-4 over 1000 steps after a
+100-step burn-in (the same gate the oracle meets, see its pins); a system
+run inside a batch gives the same positions as when run alone (the per-atom
+summation order does not depend on the batch, so they agree bit for bit;
+the gate is 1e-12).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1812_07993_amd import poremd, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def oracle_walls(desc):
+    q = desc.pore
+    return oracle.wall_lattice(oracle.make_pore(q.kind, q.lattice_a, q.slab_center_z,
+                                                q.slab_thickness, q.r0, q.r1, q.slit_gap),
+                               desc.params.box)
+
+
+def energy_drift(tot, burn=100, window=1000):
+    seg = np.asarray(tot[burn:burn + window + 1], dtype=np.float64)
+    t = np.arange(seg.shape[0], dtype=np.float64)
+    slope = np.polyfit(t, seg, 1)[0]
+    return abs(slope) * window / abs(seg[0]), float(np.abs(seg - seg[0]).max() / abs(seg[0]))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_nve_drift_cylinder_slab(prec):
+    desc = synth.cylinder_slab_small()
+    s = poremd.System.from_desc(desc, precision=prec,
+                                tuning=poremd.make_tuning(energy_every=1))
+    s.step(1100)
+    E = s.energy_history()
+    assert E["step"][0] == 0 and E["step"][-1] == 1100 and len(E) == 1101
+    trend, maxdev = energy_drift(E["etotal"])
+    assert trend <= 1e-4, trend
+    assert maxdev <= 2e-4, maxdev
+    assert np.isclose(E["ke"][0], 0.5 * (3 * desc.n - 3) * 1.2, rtol=1e-12)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_slit_128_sampled_forces(prec):
+    """262144 vapour + 131072 wall atoms: forces of 2048 sampled atoms against
+    the oracle's all-pairs sums, at creation and after 60 steps."""
+    desc = synth.slit_large()
+    s = poremd.System.from_desc(desc, precision=prec)
+    walls = oracle_walls(desc)
+    assert s.n_wall == walls.shape[0] == 131072
+    p = oracle.make_params(desc.params.box)
+    rng = np.random.default_rng(7)
+    sel = np.sort(rng.choice(desc.n, 2048, replace=False))
+    tol = 1e-12 if prec == "fp64" else 1e-5
+    F = s.forces()
+    Fr, _ = oracle.forces_subset(desc.x, walls, p, sel)
+    assert rel(F[sel], Fr) <= tol
+    s.step(60)
+    X = s.positions()
+    F = s.forces()
+    Fr, _ = oracle.forces_subset(X, walls, p, sel)
+    assert rel(F[sel], Fr) <= tol
+
+
+def test_pore_sweep_4m_sampled_forces():
+    """4194304 vapour atoms, 8-thick slab with a conical pore, mixed: sampled
+    forces against the oracle and the wall count derived by hand."""
+    desc = synth.pore_sweep("cone")
+    s = poremd.System.from_desc(desc, precision="mixed")
+    assert s.n_wall == 522612
+    walls = oracle_walls(desc)
+    p = oracle.make_params(desc.params.box)
+    rng = np.random.default_rng(3)
+    sel = np.sort(rng.choice(desc.n, 256, replace=False))
+    F = s.forces()
+    Fr, _ = oracle.forces_subset(desc.x, walls, p, sel)
+    assert rel(F[sel], Fr) <= 1e-5
+    s.step(20)
+    e = s.energies()
+    assert e["step"] == 20 and np.isfinite(e["etotal"])
+
+
+def _small_systems(prec):
+    specs = [dict(index=0, n=900, shape="cylinder", r=3.0, L=22.0),
+             dict(index=1, n=2500, shape="slit", r=2.5, L=30.0),
+             dict(index=2, n=1400, shape="cone", r=2.0, L=25.0),
+             dict(index=3, n=600, shape="cylinder", r=5.0, L=22.0)]
+    return [synth.replica(sp, precision=prec, steps=0, seed=11) for sp in specs]
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_batch_matches_alone(prec):
+    descs = _small_systems(prec)
+    steps = [37, 50, 23, 64]
+    tun = poremd.make_tuning(rebin_every=7)
+    alone = []
+    for d, n in zip(descs, steps):
+        s = poremd.System.from_desc(d, tuning=tun)
+        s.step(n)
+        alone.append((s.positions(), s.velocities(), s.energies()))
+        s.close()
+    b = poremd.pmd_batch_create(0, 8)
+    handles = [poremd.System.from_desc(d, tuning=tun) for d in descs]
+    slots = [poremd.pmd_batch_admit(b, h.h, n) for h, n in zip(handles, steps)]
+    assert sorted(slots) == [0, 1, 2, 3]
+    done = set()
+    for _ in range(200):
+        poremd.pmd_batch_advance(b, 14)
+        done |= set(poremd.pmd_batch_poll(b))
+        if len(done) == 4:
+            break
+    assert done == {0, 1, 2, 3}
+    for h, sl, (X, V, E), n in zip(handles, slots, alone, steps):
+        poremd.pmd_batch_release(b, sl)
+        Xb = h.positions()
+        assert np.abs(Xb - X).max() <= 1e-12
+        assert np.abs(h.velocities() - V).max() <= 1e-12
+        e = h.energies()
+        assert e["step"] == n
+        assert e["etotal"] == pytest.approx(E["etotal"], rel=1e-12)
+        h.close()
+    poremd.pmd_batch_destroy(b)
+
+
+def test_batch_admission_by_budget():
+    descs = _small_systems("mixed")
+    need = [poremd.pmd_footprint_bytes(*poremd.params_of(d), d.n) for d in descs]
+    b = poremd.pmd_batch_create(need[0] + need[3] + need[3] // 2, 8)
+    h0 = poremd.System.from_desc(descs[0])
+    h1 = poremd.System.from_desc(descs[1])
+    h3 = poremd.System.from_desc(descs[3])
+    assert poremd.pmd_batch_admit(b, h0.h, 10) is not None
+    assert poremd.pmd_batch_admit(b, h1.h, 10) is None  # over budget: EAGAIN
+    assert poremd.pmd_batch_admit(b, h3.h, 10) is not None
+    resident, used, budget = poremd.pmd_batch_info(b)
+    assert resident == 2 and used <= budget
+    for _ in range(20):
+        poremd.pmd_batch_advance(b, 7)
+        if len(poremd.pmd_batch_poll(b)) == 2:
+            break
+    poremd.pmd_batch_release(b, 0)
+    resident2, used2, _ = poremd.pmd_batch_info(b)
+    assert resident2 == 1 and used2 < used
+    poremd.pmd_batch_destroy(b)
+    for h in (h0, h1, h3):
+        h.close()
