@@ -44,6 +44,29 @@ def energy_drift(tot, burn):
         np.abs(seg - seg[0]).max() / abs(seg[0]))
 
 
+def autotune(poremd, desc, prec, trial_steps, tuning_kw):
+    """Skin and rebuild period from the library's autotuner (untimed): every
+    candidate of its built-in grid runs trial_steps steps of this workload."""
+    params, pore = poremd.params_of(desc, prec)
+    grid = poremd.pmd_autotune_grid(params, desc.n)
+    for t in grid:
+        if tuning_kw.get("block"):
+            t.block = tuning_kw["block"]
+        if tuning_kw.get("brick_atoms"):
+            t.brick_atoms = tuning_kw["brick_atoms"]
+        if tuning_kw.get("brick_order"):
+            t.brick_order = tuning_kw["brick_order"]
+    t0 = time.perf_counter()
+    best, us = poremd.pmd_autotune(params, pore, desc.x, desc.v, grid, trial_steps)
+    b = grid[best]
+    log("[%s] autotune: %d candidates in %.1f s; best skin %.2f, rebuild every %d: %.2f us/step"
+        % (prec, len(grid), time.perf_counter() - t0, b.skin, b.rebin_every, us[best]))
+    order = np.argsort(us)[:5]
+    log("[%s] autotune top 5: %s" % (prec, ", ".join(
+        "(%.2f, %d) %.2f" % (grid[i].skin, grid[i].rebin_every, us[i]) for i in order)))
+    return dict(skin=float(b.skin), rebin_every=int(b.rebin_every))
+
+
 def run_path(poremd, desc, prec, steps, warmup, energy_every, tuning_kw):
     import torch
 
@@ -140,6 +163,7 @@ def main():
     ap.add_argument("--rebin-every", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--brick-atoms", type=int, default=0)
+    ap.add_argument("--brick-order", type=int, default=0)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=65536)
@@ -148,11 +172,17 @@ def main():
     ap.add_argument("--serve-budget-gb", type=float, default=2.0)
     ap.add_argument("--serve-chunk", type=int, default=250)
     ap.add_argument("--timing-steps", type=int, default=500)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="before the timed run, one plain device-to-device copy of this many "
+                         "MiB (a known-size kernel to scale the hardware byte counters by)")
+    ap.add_argument("--autotune-steps", type=int, default=200,
+                    help="timed steps per autotuner candidate (0 = library defaults); "
+                         "skipped when --skin or --rebin-every is given")
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(independent replicas shard trivially; see the design notes).", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(independent replicas shard trivially across GPUs, one process each).", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -161,16 +191,30 @@ def main():
 
     poremd.load()
     assert torch.cuda.is_available(), "needs a GPU"
+    if args.copy_mib > 0:
+        src = torch.empty(args.copy_mib * 2 ** 20, dtype=torch.uint8, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: %d MiB read + %d MiB written by one copy kernel"
+            % (args.copy_mib, args.copy_mib))
+        del src, dst
     t0 = time.perf_counter()
     desc = synth.slit_large(n=args.n, box=args.box)
     log("inputs: %d vapour atoms, box %g, generated in %.1f s"
         % (desc.n, args.box, time.perf_counter() - t0))
     tkw = dict(skin=args.skin, rebin_every=args.rebin_every, block=args.block,
-               brick_atoms=args.brick_atoms)
+               brick_atoms=args.brick_atoms, brick_order=args.brick_order)
 
     res = {}
+    tuned = {}
     for prec in (["mixed"] if args.no_fp64 else ["mixed", "fp64"]):
-        r = run_path(poremd, desc, prec, args.steps, args.warmup, args.energy_every, tkw)
+        kw = dict(tkw)
+        if args.autotune_steps > 0 and not (args.skin or args.rebin_every):
+            kw.update(autotune(poremd, desc, prec, args.autotune_steps, tkw))
+        tuned[prec] = kw
+        r = run_path(poremd, desc, prec, args.steps, args.warmup, args.energy_every, kw)
         n_launch, kms = kernel_time(poremd, r["sys"], args.timing_steps)
         r["kernel_ms"] = kms
         r["kernel_launches"] = n_launch
@@ -225,7 +269,8 @@ def main():
                      "alg_bytes_per_atom_step": ALG_BYTES["mixed"]},
         "accuracy": {"mixed_drift_trend": m["drift_trend"], "mixed_drift_max": m["drift_max"],
                      "force_err_mixed_vs_fp64": eps_f},
-        "detail": {"mixed_rebuilds": m["rebuilds"], "mixed_max_list": m["max_list"]},
+        "detail": {"mixed_rebuilds": m["rebuilds"], "mixed_max_list": m["max_list"],
+                   "tuning": tuned},
     }
     if "fp64" in res:
         d = res["fp64"]

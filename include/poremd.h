@@ -117,6 +117,9 @@ typedef struct {
     int32_t energy_every;
     int32_t use_graph;    /* 1: replay captured HIP graphs; 0: plain launches */
     int32_t brick_atoms;  /* target atoms per brick (workgroup); 0 = 0.8 x block */
+    int32_t brick_order;  /* workgroup order of the brick kernels: 1 = each XCD
+                           * takes a contiguous run of bricks, 2 = bricks dealt
+                           * round-robin over the XCDs; 0 = library default */
 } pmd_tuning;
 
 typedef struct pmd_system pmd_system;
@@ -184,6 +187,41 @@ int pmd_get_positions_device(pmd_system *sys, double *dev_out, int64_t n,
  * next pmd_step). */
 int pmd_set_tuning(pmd_system *sys, const pmd_tuning *tuning);
 int pmd_get_tuning(pmd_system *sys, pmd_tuning *out);
+
+/* Replace the state of a system (not one resident in a batch) with
+ * caller-order positions and velocities, host [n][3] each, n equal to the
+ * system's vapour count, and set its step counter to `step`: the restart
+ * from a checkpoint taken with pmd_get_positions / pmd_get_velocities /
+ * pmd_get_step.  Forces and energies at the loaded positions are computed
+ * before the call returns, and the energy history restarts at `step`.  The
+ * continued trajectory equals the uninterrupted one to rounding (the force
+ * sums are re-ordered by the fresh cell binning).  Same input checks as
+ * pmd_create_system. */
+int pmd_set_state(pmd_system *sys, const double *pos, const double *vel,
+                  int64_t n, int64_t step);
+
+/* ---- Autotuner (neighbour-list skin, rebuild period, brick size) --------
+ * The skin and the rebuild period trade the cost of a rebuild against the
+ * length of the neighbour lists the force pass walks; the best pair depends
+ * on the density, the temperature and the device.  pmd_autotune times each
+ * candidate on one trial copy of the system described by the same inputs as
+ * pmd_create_system (the caller's arrays are not changed, no caller system
+ * is touched): per candidate it loads the initial state, runs
+ * trial_steps / 4 untimed steps, then times trial_steps steps (wall clock,
+ * including rebuilds and early-rebuild round trips).  us_per_step
+ * [n_candidates] (may be NULL) receives each candidate's microseconds per
+ * step (infinity for a candidate that cannot run, e.g. a skin leaving fewer
+ * than 3 cells per axis); *best the index of the fastest.  Fails if none
+ * runs.  pmd_autotune_grid writes the built-in candidate grid (skin x
+ * rebuild period, other knobs at their defaults) into out[cap]; with
+ * out == NULL it only reports the count in *n_out. */
+int pmd_autotune_grid(const pmd_params *params, int64_t n_vapor, pmd_tuning *out,
+                      int32_t cap, int32_t *n_out);
+int pmd_autotune(const pmd_params *params, const pmd_pore *pore, int64_t n_vapor,
+                 const double *pos, const double *vel, int64_t n_wall,
+                 const double *wall_pos, void *hip_stream,
+                 const pmd_tuning *candidates, int32_t n_candidates,
+                 int64_t trial_steps, double *us_per_step, int32_t *best);
 
 /* Destroy a system (NULL-safe).  Waits for queued work. */
 int pmd_destroy(pmd_system *sys);

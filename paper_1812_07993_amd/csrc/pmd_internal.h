@@ -76,8 +76,6 @@ struct SysState {
     int lbuf;         // current local-coordinate buffer (0/1)
     int sbuf;         // current state buffer (0/1)
     int sbuf_prev;    // state buffer before the last rebuild
-    int blocks_done;  // finished workgroups of the step kernel (last-block pattern)
-    int tiles_done;   // finished workgroups of the cell-count scan
     int nrec;         // energy records written
     int max_nbr;      // longest neighbour list at the last rebuild
     int rebins;       // rebuilds so far
@@ -111,6 +109,7 @@ struct PoolDev {
     int wall_lds;         // capacity of the staged wall tile of the list build (walls)
     int hmax;             // largest halo box (cells) of any resident system
     int block;            // threads per workgroup of the brick kernels
+    int brick_order;      // 1: contiguous runs of bricks per XCD, 2: round-robin over XCDs
     int vt, wt;           // vapour and wall slot capacity
     int cap;              // neighbour-list capacity per atom
     // per-atom state, double buffered by SysState::sbuf; SoA with stride vt
@@ -163,6 +162,7 @@ hipError_t launch_wall_bin(const PoolDev& P, int sys, const double* raw_soa, int
                            int nw, int precision, hipStream_t s);
 hipError_t launch_rebuild(const PoolDev& P, int nslots, int precision, hipStream_t s);
 hipError_t launch_set_run(const PoolDev& P, int slot, int add_steps, int phase_init, hipStream_t s);
+hipError_t launch_reset_state(const PoolDev& P, int slot, long long step, hipStream_t s);
 hipError_t launch_step(const PoolDev& P, int nslots, int precision, hipStream_t s, hipEvent_t ev0,
                        hipEvent_t ev1);
 hipError_t launch_unpermute(const PoolDev& P, int slot, int which, double* out_aos,

@@ -561,7 +561,7 @@ struct BrickCtx {
 
 __device__ __forceinline__ bool brick_ctx(const PoolDev& P, BrickCtx& c, int bad_bits)
 {
-    const int lb = logical_block();
+    const int lb = P.brick_order == 2 ? (int)blockIdx.x : logical_block();
     if (lb >= P.nbrick) return false;
     const int s = P.brick_sys[lb];
     if (s < 0) return false;
@@ -875,7 +875,7 @@ __global__ void __launch_bounds__(256) k_step(PoolDev P)
 
     const bool init = st.phase == PH_INIT;
     const bool last = !init && st.remaining == 1;
-    const long long kstep = init ? 0 : st.step + 1;
+    const long long kstep = init ? st.step : st.step + 1;
     const bool doE = init || last || (sp.energy_every > 0 && (kstep % sp.energy_every) == 0);
     const int vt = P.vt;
     const int key0 = c.b * sp.bcells;
@@ -1070,7 +1070,7 @@ __global__ void __launch_bounds__(256) k_finish(PoolDev P, int nslots)
         return;
     const bool init = st.phase == PH_INIT;
     const bool last = !init && st.remaining == 1;
-    const long long kstep = init ? 0 : st.step + 1;
+    const long long kstep = init ? st.step : st.step + 1;
     const bool doE = init || last || (sp.energy_every > 0 && (kstep % sp.energy_every) == 0);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
     double a = 0.0, b = 0.0, cc = 0.0;
@@ -1164,6 +1164,27 @@ __global__ void k_set_run(PoolDev P, int slot, int add_steps, int phase_init)
 hipError_t launch_set_run(const PoolDev& P, int slot, int add_steps, int phase_init, hipStream_t s)
 {
     hipLaunchKernelGGL(k_set_run, dim3(1), dim3(1), 0, s, P, slot, add_steps, phase_init);
+    return hipGetLastError();
+}
+
+// Start over from freshly loaded positions and velocities at step `step`:
+// the next run is the initial force evaluation, the energy history restarts.
+__global__ void k_reset_state(PoolDev P, int slot, long long step)
+{
+    SysState* st = P.st + slot;
+    st->remaining = 1;
+    st->phase = PH_INIT;
+    st->status = 0;
+    st->status_next = 0;
+    st->nrec = 0;
+    st->max_nbr = 0;
+    st->steps_since = 0;
+    st->step = step;
+}
+
+hipError_t launch_reset_state(const PoolDev& P, int slot, long long step, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reset_state, dim3(1), dim3(1), 0, s, P, slot, step);
     return hipGetLastError();
 }
 

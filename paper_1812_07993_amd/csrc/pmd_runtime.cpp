@@ -4,7 +4,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <limits>
+#include <numeric>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -48,6 +51,11 @@ int fail(int code, const char* fmt, ...)
     } while (0)
 
 int round_up(int a, int b) { return ((a + b - 1) / b) * b; }
+
+// Workgroup order of the brick kernels: 1 = each XCD takes a contiguous run
+// of bricks (spatial neighbours share an L2), 2 = bricks dealt round-robin
+// over the XCDs (a dense region of the box is spread over all of them).
+constexpr int kDefaultBrickOrder = 1;
 
 constexpr int kDefaultErings = 16384;
 
@@ -148,20 +156,29 @@ int64_t host_wall_count(const pmd_params& p, const pmd_pore& q)
     return n;
 }
 
+// Neighbour-list slots per atom for a skin: 1.5 x the mean count in the list
+// sphere (at least at density 0.3, adsorbed layers are denser than the
+// mean), plus room for wall partners.
+int default_list_cap(const pmd_params& p, int64_t nv, double skin)
+{
+    const double V = p.box[0] * p.box[1] * p.box[2];
+    const double rho = std::max(0.3, (double)nv / V);
+    const double rl = p.cutoff + skin;
+    const double sphere = 4.0 / 3.0 * M_PI * rl * rl * rl;
+    return round_up((int)std::ceil(1.5 * sphere * rho) + 48, 16);
+}
+
 pmd_tuning default_tuning(const pmd_params& p, int64_t nv)
 {
     pmd_tuning t{};
     t.skin = 0.5;
     t.rebin_every = 7;
     t.block = 256;
-    const double V = p.box[0] * p.box[1] * p.box[2];
-    const double rho = std::max(0.3, (double)nv / V);
-    const double rl = p.cutoff + t.skin;
-    const double sphere = 4.0 / 3.0 * M_PI * rl * rl * rl;
-    t.list_cap = round_up((int)std::ceil(1.5 * sphere * rho) + 48, 16);
+    t.list_cap = default_list_cap(p, nv, t.skin);
     t.energy_every = 0;
     t.use_graph = 1;
     t.brick_atoms = 0;
+    t.brick_order = kDefaultBrickOrder;
     return t;
 }
 
@@ -169,17 +186,23 @@ int merge_tuning(const pmd_params& p, int64_t nv, const pmd_tuning* in, pmd_tuni
 {
     pmd_tuning d = default_tuning(p, nv);
     if (in) {
-        if (in->skin > 0) d.skin = in->skin;
+        if (in->skin > 0) {
+            d.skin = in->skin;
+            d.list_cap = default_list_cap(p, nv, d.skin);
+        }
         if (in->rebin_every > 0) d.rebin_every = in->rebin_every;
         if (in->block > 0) d.block = in->block;
         if (in->list_cap > 0) d.list_cap = in->list_cap;
         if (in->energy_every >= 0) d.energy_every = in->energy_every;
         d.use_graph = in->use_graph;
         if (in->brick_atoms > 0) d.brick_atoms = in->brick_atoms;
+        if (in->brick_order > 0) d.brick_order = in->brick_order;
     }
     if (d.block != 64 && d.block != 128 && d.block != 256)
         return fail(PMD_EINVAL, "block must be 64, 128 or 256 (got %d)", d.block);
     if (d.rebin_every > 1000) return fail(PMD_EINVAL, "rebin_every must be <= 1000");
+    if (d.brick_order != 1 && d.brick_order != 2)
+        return fail(PMD_EINVAL, "brick_order must be 0, 1 or 2 (got %d)", d.brick_order);
     if (d.list_cap > 4096) return fail(PMD_EINVAL, "list_cap must be <= 4096");
     d.list_cap = round_up(d.list_cap, 16);  // the list layout groups entries by 4
     *out = d;
@@ -193,6 +216,7 @@ int merge_tuning(const pmd_params& p, int64_t nv, const pmd_tuning* in, pmd_tuni
 struct Pool {
     int precision = 0;
     int block = 256;
+    int brick_order = kDefaultBrickOrder;
     int cap = 64;
     int vt = 0, wt = 0, ct = 0, wct = 0, nbt = 0, nslots = 0, ering_cap = kDefaultErings;
     size_t bytes = 0;
@@ -289,6 +313,7 @@ struct Pool {
         d.wall_lds = wall_lds;
         d.hmax = hmax;
         d.block = block;
+        d.brick_order = brick_order;
         d.vt = vt;
         d.wt = wt;
         d.cap = cap;
@@ -755,6 +780,57 @@ int sys_sync(pmd_system* s)
     return fail(PMD_EHIP, "step driver made no progress");
 }
 
+int check_atoms(const pmd_params& p, int64_t n, const double* pos, const double* vel)
+{
+    for (int64_t i = 0; i < 3 * n; ++i) {
+        const int k = (int)(i % 3);
+        if (!std::isfinite(pos[i]) || !std::isfinite(vel[i]))
+            return fail(PMD_EINVAL, "non-finite input at atom %lld", (long long)(i / 3));
+        if (pos[i] < 0.0 || pos[i] >= p.box[k])
+            return fail(PMD_EINVAL, "position of atom %lld outside [0, L)", (long long)(i / 3));
+    }
+    return PMD_OK;
+}
+
+// Load caller-order positions and velocities into the system's slot, reset
+// its step counter and energy history, and evaluate the forces at the loaded
+// positions (bin, build lists, one force pass), growing the neighbour lists or
+// the LDS tile if the first attempt reports that they are too small.
+int load_state(pmd_system* sys, const double* pos, const double* vel, int64_t step)
+{
+    Pool& q = *sys->pool;
+    const int slot = sys->slot;
+    const int64_t n = sys->nv;
+    double* dpos = nullptr;
+    HIPCHK(hipMalloc(&dpos, sizeof(double) * 6 * (size_t)n));
+    hipError_t e = hipMemcpyAsync(dpos, pos, sizeof(double) * 3 * n, hipMemcpyHostToDevice, q.stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(dpos + 3 * n, vel, sizeof(double) * 3 * n, hipMemcpyHostToDevice, q.stream);
+    if (e == hipSuccess)
+        e = launch_copy_in(q.dev(), slot, dpos, dpos + 3 * n, (int)n, q.hsp[slot].vcap, q.stream);
+    if (e == hipSuccess) e = launch_reset_state(q.dev(), slot, (long long)step, q.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(q.stream);
+    hipFree(dpos);
+    HIPCHK(e);
+    for (int attempt = 0; attempt < 8; ++attempt) {
+        HIPCHK(launch_rebuild(q.dev(), q.nslots, q.precision, q.stream));
+        HIPCHK(launch_step(q.dev(), q.nslots, q.precision, q.stream, nullptr, nullptr));
+        SysState st;
+        CHK(read_state(q, slot, &st));
+        if (st.status & ST_NONFINITE) return fail(PMD_ENUMERIC, "non-finite initial forces");
+        if (st.phase == PH_REST) return PMD_OK;
+        if (st.status & ST_TILE) {
+            CHK(pool_fix_tile(q, slot));
+        } else if (st.status & ST_OVERFLOW) {
+            const int need = round_up(std::max(st.max_nbr + st.max_nbr / 4 + 8, q.cap), 16);
+            if (need > 4096) return fail(PMD_ENOMEM, "neighbour list needs %d entries", need);
+            CHK(pool_grow_lists(q, need));
+            sys->tuning.list_cap = need;
+        }
+    }
+    return fail(PMD_EHIP, "initial force evaluation did not complete");
+}
+
 int check_free(pmd_system* s)
 {
     if (!s) return fail(PMD_EINVAL, "NULL system");
@@ -828,7 +904,6 @@ int move_system(Pool& src, int sslot, Pool& dst, int dslot)
     SysState nst = st;
     nst.sbuf = 0;
     nst.sbuf_prev = 0;
-    nst.blocks_done = 0;
     nst.status_next = 0;
     HIPCHK(hipMemcpy(dst.d_st + dslot, &nst, sizeof(SysState), hipMemcpyHostToDevice));
     return PMD_OK;
@@ -865,6 +940,7 @@ int make_single_pool(const Pool& like, const SysParams& sp_in, hipStream_t strea
     Pool& p = *pool;
     p.precision = like.precision;
     p.block = like.block;
+    p.brick_order = like.brick_order;
     p.cap = like.cap;
     p.nslots = 1;
     p.ering_cap = kDefaultErings;
@@ -908,6 +984,7 @@ int batch_repack(pmd_batch* b, const Needs& extra, int extra_cap)
     Pool& p = *np;
     p.precision = old->precision;
     p.block = old->block;
+    p.brick_order = old->brick_order;
     p.cap = std::max(old->cap, extra_cap);
     p.nslots = b->max_slots;
     p.ering_cap = kBatchErings;
@@ -1052,13 +1129,7 @@ int pmd_create_system(const pmd_params* params, const pmd_pore* pore, int64_t n_
         if (nw < 0) return fail(PMD_EINVAL, "n_wall must be >= 0");
         if (n_vapor + nw + 2 * kPad >= (int64_t)kIndexMask)
             return fail(PMD_EINVAL, "too many atoms for one system (%lld)", (long long)(n_vapor + nw));
-        for (int64_t i = 0; i < 3 * n_vapor; ++i) {
-            const int k = (int)(i % 3);
-            if (!std::isfinite(pos[i]) || !std::isfinite(vel[i]))
-                return fail(PMD_EINVAL, "non-finite input at atom %lld", (long long)(i / 3));
-            if (pos[i] < 0.0 || pos[i] >= params->box[k])
-                return fail(PMD_EINVAL, "position of atom %lld outside [0, L)", (long long)(i / 3));
-        }
+        CHK(check_atoms(*params, n_vapor, pos, vel));
         if (wall_pos)
             for (int64_t i = 0; i < 3 * nw; ++i) {
                 const int k = (int)(i % 3);
@@ -1078,6 +1149,7 @@ int pmd_create_system(const pmd_params* params, const pmd_pore* pore, int64_t n_
         Pool& p = *pool;
         p.precision = params->precision;
         p.block = sys->tuning.block;
+        p.brick_order = sys->tuning.brick_order;
         p.cap = sys->tuning.list_cap;
         p.nslots = 1;
         SysParams sp{};
@@ -1135,42 +1207,10 @@ int pmd_create_system(const pmd_params* params, const pmd_pore* pore, int64_t n_
         CHK(pool_layout(p));  // wall halo sizes need the binned walls
 
         // vapour: copy in (caller order), then bin, build lists and compute a(0)
-        double* dpos = nullptr;
-        HIPCHK(hipMalloc(&dpos, sizeof(double) * 6 * (size_t)n_vapor));
-        hipError_t e = hipMemcpyAsync(dpos, pos, sizeof(double) * 3 * n_vapor, hipMemcpyHostToDevice, p.stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(dpos + 3 * n_vapor, vel, sizeof(double) * 3 * n_vapor,
-                               hipMemcpyHostToDevice, p.stream);
-        if (e == hipSuccess)
-            e = launch_copy_in(p.dev(), 0, dpos, dpos + 3 * n_vapor, (int)n_vapor, sp.vcap, p.stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(p.stream);
-        hipFree(dpos);
-        HIPCHK(e);
-
         sys->own = std::move(pool);
         sys->pool = sys->own.get();
         sys->slot = 0;
-        Pool& q = *sys->pool;
-        HIPCHK(launch_set_run(q.dev(), 0, 0, 1, q.stream));
-        for (int attempt = 0; attempt < 8; ++attempt) {
-            HIPCHK(launch_rebuild(q.dev(), q.nslots, q.precision, q.stream));
-            HIPCHK(launch_step(q.dev(), q.nslots, q.precision, q.stream, nullptr, nullptr));
-            SysState st;
-            CHK(read_state(q, 0, &st));
-            if (st.status & ST_NONFINITE) return fail(PMD_ENUMERIC, "non-finite initial forces");
-            if (st.phase == PH_REST) break;
-            if (st.status & ST_TILE) {
-                CHK(pool_fix_tile(q, 0));
-            } else if (st.status & ST_OVERFLOW) {
-                const int need = round_up(st.max_nbr + st.max_nbr / 4 + 8, 16);
-                if (need > 4096) return fail(PMD_ENOMEM, "neighbour list needs %d entries", need);
-                CHK(pool_grow_lists(q, need));
-                sys->tuning.list_cap = need;
-            }
-        }
-        SysState st;
-        CHK(read_state(q, 0, &st));
-        if (st.phase != PH_REST) return fail(PMD_EHIP, "initial force evaluation did not complete");
+        CHK(load_state(sys.get(), pos, vel, 0));
         *out = sys.release();
         return PMD_OK;
     } catch (const std::bad_alloc&) {
@@ -1354,6 +1394,7 @@ int pmd_set_tuning(pmd_system* sys, const pmd_tuning* tuning)
         sp.ering_off = keep.ering_off;
         sp.ering_cap = keep.ering_cap;
         p.block = t.block;
+        p.brick_order = t.brick_order;
         CHK(pool_layout(p));
         if (g.nc[0] != keep.nc[0] || g.nc[1] != keep.nc[1] || g.nc[2] != keep.nc[2]) {
             // re-bin the walls on the new grid from their sorted positions
@@ -1379,6 +1420,109 @@ int pmd_get_tuning(pmd_system* sys, pmd_tuning* out)
     if (!sys || !out) return fail(PMD_EINVAL, "NULL argument");
     *out = sys->tuning;
     return PMD_OK;
+}
+
+int pmd_set_state(pmd_system* sys, const double* pos, const double* vel, int64_t n, int64_t step)
+{
+    try {
+        CHK(check_free(sys));
+        if (!pos || !vel) return fail(PMD_EINVAL, "pos and vel must not be NULL");
+        if (n != sys->nv) return fail(PMD_EINVAL, "n = %lld, system has %lld vapour atoms",
+                                      (long long)n, (long long)sys->nv);
+        if (step < 0) return fail(PMD_EINVAL, "step must be >= 0");
+        CHK(check_atoms(sys->params, n, pos, vel));
+        CHK(sys_sync(sys));
+        return load_state(sys, pos, vel, step);
+    } catch (const std::bad_alloc&) {
+        return fail(PMD_ENOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(PMD_EHIP, "unexpected exception");
+    }
+}
+
+int pmd_autotune_grid(const pmd_params* params, int64_t n_vapor, pmd_tuning* out, int32_t cap,
+                      int32_t* n_out)
+{
+    try {
+        if (!params || !n_out) return fail(PMD_EINVAL, "NULL argument");
+        static const double skins[] = {0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 1.0};
+        static const int periods[] = {4, 6, 8, 10, 12, 15, 20};
+        const int total = (int)(sizeof(skins) / sizeof(skins[0]) * sizeof(periods) / sizeof(periods[0]));
+        *n_out = total;
+        if (!out) return PMD_OK;
+        if (cap < total) return fail(PMD_EINVAL, "need room for %d candidates", total);
+        const pmd_tuning base = default_tuning(*params, n_vapor);
+        int k = 0;
+        for (double sk : skins)
+            for (int R : periods) {
+                pmd_tuning t = base;
+                t.skin = sk;
+                t.rebin_every = R;
+                t.list_cap = 0;  // sized from the density at the new skin
+                out[k++] = t;
+            }
+        return PMD_OK;
+    } catch (...) {
+        return fail(PMD_EHIP, "unexpected exception");
+    }
+}
+
+int pmd_autotune(const pmd_params* params, const pmd_pore* pore, int64_t n_vapor, const double* pos,
+                 const double* vel, int64_t n_wall, const double* wall_pos, void* hip_stream,
+                 const pmd_tuning* candidates, int32_t n_candidates, int64_t trial_steps,
+                 double* us_per_step, int32_t* best)
+{
+    try {
+        if (!candidates || n_candidates < 1 || !best)
+            return fail(PMD_EINVAL, "need candidates and best");
+        if (trial_steps < 1 || trial_steps > 100000) return fail(PMD_EINVAL, "trial_steps out of range");
+        for (int32_t c = 0; c < n_candidates; ++c) {
+            pmd_tuning t;
+            CHK(merge_tuning(*params, n_vapor, candidates + c, &t));
+        }
+        // one trial system, created at the smallest skin so that its cell
+        // arrays also hold every coarser grid the later candidates use
+        std::vector<int32_t> order(n_candidates);
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+            return candidates[a].skin < candidates[b].skin;
+        });
+        pmd_system* trial = nullptr;
+        CHK(pmd_create_system(params, pore, n_vapor, pos, vel, n_wall, wall_pos, hip_stream,
+                              candidates + order[0], &trial));
+        std::unique_ptr<pmd_system, int (*)(pmd_system*)> guard(trial, pmd_destroy);
+        const int64_t warm = std::max<int64_t>(trial_steps / 4, 1);
+        double best_us = std::numeric_limits<double>::infinity();
+        *best = -1;
+        for (int32_t c : order) {
+            double us = std::numeric_limits<double>::infinity();
+            int rc = pmd_set_tuning(trial, candidates + c);
+            if (rc == PMD_OK) rc = load_state(trial, pos, vel, 0);
+            if (rc == PMD_OK) rc = pmd_step(trial, warm);
+            if (rc == PMD_OK) rc = sys_sync(trial);
+            if (rc == PMD_OK) {
+                const auto t0 = std::chrono::steady_clock::now();
+                rc = pmd_step(trial, trial_steps);
+                if (rc == PMD_OK) rc = sys_sync(trial);
+                const auto t1 = std::chrono::steady_clock::now();
+                if (rc == PMD_OK)
+                    us = std::chrono::duration<double, std::micro>(t1 - t0).count() / (double)trial_steps;
+            }
+            // a failing candidate (numerics aside) is only a slow one
+            if (rc == PMD_ENUMERIC) return rc;
+            if (us_per_step) us_per_step[c] = us;
+            if (us < best_us) {
+                best_us = us;
+                *best = c;
+            }
+        }
+        if (*best < 0) return fail(PMD_EHIP, "no candidate tuning completed its trial");
+        return PMD_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(PMD_ENOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(PMD_EHIP, "unexpected exception");
+    }
 }
 
 int pmd_destroy(pmd_system* sys)
@@ -1583,6 +1727,7 @@ int pmd_batch_admit(pmd_batch* b, pmd_system* sys, int64_t nsteps, int* slot)
             auto np = std::make_unique<Pool>();
             np->precision = sp0.precision;
             np->block = sys->tuning.block;
+            np->brick_order = sys->tuning.brick_order;
             np->cap = sp0.cap;
             np->nslots = b->max_slots;
             np->ering_cap = kBatchErings;

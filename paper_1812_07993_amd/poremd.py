@@ -53,7 +53,7 @@ class pmd_tuning(ctypes.Structure):
     _fields_ = [("skin", ctypes.c_double), ("rebin_every", ctypes.c_int32),
                 ("block", ctypes.c_int32), ("list_cap", ctypes.c_int32),
                 ("energy_every", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("brick_atoms", ctypes.c_int32)]
+                ("brick_atoms", ctypes.c_int32), ("brick_order", ctypes.c_int32)]
 
 
 _lib = None
@@ -81,6 +81,10 @@ _SIGS = {
     "pmd_get_positions_device": (ctypes.c_int, [_vp, _vp, _i64, _vp]),
     "pmd_set_tuning": (ctypes.c_int, [_vp, _P(pmd_tuning)]),
     "pmd_get_tuning": (ctypes.c_int, [_vp, _P(pmd_tuning)]),
+    "pmd_set_state": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i64]),
+    "pmd_autotune_grid": (ctypes.c_int, [_P(pmd_params), _i64, _vp, _i32, _P(_i32)]),
+    "pmd_autotune": (ctypes.c_int, [_P(pmd_params), _P(pmd_pore), _i64, _vp, _vp, _i64, _vp, _vp,
+                                    _vp, _i32, _i64, _vp, _P(_i32)]),
     "pmd_destroy": (ctypes.c_int, [_vp]),
     "pmd_timing_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
     "pmd_kernel_time": (ctypes.c_int, [_vp, _P(_i64), _P(_d)]),
@@ -158,10 +162,11 @@ def make_pore(kind="none", lattice_a=1.0, slab_center_z=0.0, slab_thickness=0.0,
 
 
 def make_tuning(skin=0.0, rebin_every=0, block=0, list_cap=0, energy_every=0,
-                use_graph=1, brick_atoms=0) -> pmd_tuning:
+                use_graph=1, brick_atoms=0, brick_order=0) -> pmd_tuning:
     t = pmd_tuning()
     t.skin, t.rebin_every, t.block, t.list_cap = skin, rebin_every, block, list_cap
     t.energy_every, t.use_graph, t.brick_atoms = energy_every, use_graph, brick_atoms
+    t.brick_order = brick_order
     return t
 
 
@@ -279,6 +284,36 @@ def pmd_get_tuning(h):
     t = pmd_tuning()
     _check(load().pmd_get_tuning(h, ctypes.byref(t)))
     return t
+
+
+def pmd_set_state(h, pos, vel, step=0):
+    pos = _f64(pos, -1)
+    vel = _f64(vel, -1)
+    _check(load().pmd_set_state(h, _ptr(pos), _ptr(vel), pos.shape[0], int(step)))
+
+
+def pmd_autotune_grid(params, n_vapor):
+    n = ctypes.c_int32()
+    _check(load().pmd_autotune_grid(ctypes.byref(params), int(n_vapor), None, 0, ctypes.byref(n)))
+    out = (pmd_tuning * n.value)()
+    _check(load().pmd_autotune_grid(ctypes.byref(params), int(n_vapor), out, n.value,
+                                    ctypes.byref(n)))
+    return list(out)
+
+
+def pmd_autotune(params, pore, pos, vel, candidates, trial_steps=200, wall_pos=None, stream=None):
+    """Returns (index of the fastest candidate, microseconds per step of each)."""
+    pos = _f64(pos, -1)
+    vel = _f64(vel, -1)
+    w = _f64(wall_pos, -1) if wall_pos is not None else None
+    cand = (pmd_tuning * len(candidates))(*candidates)
+    us = np.zeros(len(candidates), dtype=np.float64)
+    best = ctypes.c_int32()
+    _check(load().pmd_autotune(ctypes.byref(params), ctypes.byref(pore), pos.shape[0], _ptr(pos),
+                               _ptr(vel), 0 if w is None else w.shape[0], _ptr(w),
+                               ctypes.c_void_p(stream) if stream else None, cand, len(candidates),
+                               int(trial_steps), _ptr(us), ctypes.byref(best)))
+    return best.value, us
 
 
 def pmd_destroy(h):
@@ -430,6 +465,12 @@ class System:
 
     def energy_history(self):
         return pmd_get_energy_history(self.h)
+
+    def step_count(self):
+        return pmd_get_step(self.h)
+
+    def set_state(self, pos, vel, step=0):
+        pmd_set_state(self.h, pos, vel, step)
 
     def close(self):
         if self.h:

@@ -51,3 +51,14 @@ def test_host_only_calls():
         poremd.pmd_wall_count(bad, q)
     assert e.value.code == poremd.PMD_EINVAL
     assert "dt" in poremd.pmd_last_error()
+
+
+def test_autotune_grid_is_host_only():
+    p = poremd.make_params(128.0, "mixed")
+    grid = poremd.pmd_autotune_grid(p, 262144)
+    assert len(grid) == 49
+    skins = sorted({round(t.skin, 6) for t in grid})
+    periods = sorted({t.rebin_every for t in grid})
+    assert skins == [0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 1.0]
+    assert periods == [4, 6, 8, 10, 12, 15, 20]
+    assert all(t.block in (64, 128, 256) and t.list_cap == 0 for t in grid)
