@@ -106,7 +106,6 @@ struct PoolDev {
     const int* brick_sys; // brick (workgroup of the list and step kernels) -> system slot
     int nbrick;           // bricks in use
     int lds_atoms;        // capacity of the staged neighbour tile (atoms)
-    int wall_lds;         // capacity of the staged wall tile of the list build (walls)
     int hmax;             // largest halo box (cells) of any resident system
     int block;            // threads per workgroup of the brick kernels
     int brick_order;      // 1: contiguous runs of bricks per XCD, 2: round-robin over XCDs

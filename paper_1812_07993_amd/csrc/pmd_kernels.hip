@@ -629,7 +629,7 @@ __device__ __forceinline__ Tile<T> tile_of(unsigned char* smem, const PoolDev& P
 // Stage the halo box of brick g into LDS.  Returns the number of staged
 // atoms, or -1 if it exceeds the tile capacity.  with_pos = false stages
 // only the slots.
-template <typename T, bool WALLS = false>
+template <typename T>
 __device__ int stage_halo(const PoolDev& P, const SysParams& sp, const HaloGeo& g, Tile<T>& t,
                           const typename V4<T>::type* Lc, bool with_pos, int* lds_scan,
                           int cap = -1)
@@ -644,17 +644,9 @@ __device__ int stage_halo(const PoolDev& P, const SysParams& sp, const HaloGeo& 
         const int cx = wrap_cell(g.start[0] - 1 + hx, sp.nc[0]);
         const int cy = wrap_cell(g.start[1] - 1 + hy, sp.nc[1]);
         const int cz = wrap_cell(g.start[2] - 1 + hz, sp.nc[2]);
-        int b0, n;
-        if (WALLS) {
-            const int cl = cx + sp.nc[0] * (cy + sp.nc[1] * cz);
-            b0 = P.wcstart[sp.wcoff + cl];
-            n = P.wcstart[sp.wcoff + cl + 1] - b0;
-            b0 += P.vt;  // walls sit after the vapour slots in the coordinate buffers
-        } else {
-            const int key = cell_key(sp, cx, cy, cz);
-            b0 = P.cstart[sp.coff + key];
-            n = P.cstart[sp.coff + key + 1] - b0;
-        }
+        const int key = cell_key(sp, cx, cy, cz);
+        const int b0 = P.cstart[sp.coff + key];
+        const int n = P.cstart[sp.coff + key + 1] - b0;
         t.hbeg[h] = b0;
         t.hoff[h] = n;  // count for now
         sum += n;
@@ -669,17 +661,14 @@ __device__ int stage_halo(const PoolDev& P, const SysParams& sp, const HaloGeo& 
     if (threadIdx.x == 0) t.hoff[g.H] = tot;
     __syncthreads();
     if (tot > cap) return -1;
+    // each staged atom learns its halo cell from the thread owning the cell
+    // (written into slot[] first), then turns it into its storage slot
+    for (int h = lo; h < hi; ++h)
+        for (int a = t.hoff[h], a1 = t.hoff[h + 1]; a < a1; ++a) t.slot[a] = h;
+    __syncthreads();
     for (int a = threadIdx.x; a < tot; a += T_) {
-        // halo cell of staged atom a: last h with hoff[h] <= a
-        int l = 0, r = g.H - 1;
-        while (l < r) {
-            const int m = (l + r + 1) >> 1;
-            if (t.hoff[m] <= a)
-                l = m;
-            else
-                r = m - 1;
-        }
-        t.slot[a] = t.hbeg[l] + (a - t.hoff[l]);
+        const int h = t.slot[a];
+        t.slot[a] = t.hbeg[h] + (a - t.hoff[h]);
     }
     __syncthreads();
     if (with_pos) {
@@ -722,7 +711,10 @@ __device__ __forceinline__ double box_gap(double l, int d, double h)
 // walls) of the atoms of one brick, in a fixed order: neighbour cells 0..26,
 // staged order inside a cell; vapour entries first, then walls.  Vapour
 // entries index the brick's staged tile, which the step kernel rebuilds
-// identically from the same cell tables; wall entries are wall slots.
+// identically from the same cell tables; wall entries are wall slots.  Wall
+// candidates are read from global memory (the static wall coordinates stay
+// in L2): staging them would size every brick's LDS for the densest wall
+// halo and leave one workgroup per CU.
 template <typename T>
 __global__ void __launch_bounds__(256) k_list_build(PoolDev P)
 {
@@ -737,12 +729,12 @@ __global__ void __launch_bounds__(256) k_list_build(PoolDev P)
     const V* Lc = (const V*)P.L[st.lbuf];
     const HaloGeo g = halo_geo(sp, c.b);
     Tile<T> t = tile_of<T>(smem, P);
-    Tile<T> tw = tile_at<T>(smem, tile_size<T>(P.lds_atoms, P.hmax), P.wall_lds, P.hmax);
     const int tot = stage_halo<T>(P, sp, g, t, Lc, true, lds_scan);
-    const int wtot = tot < 0 ? -1 : stage_halo<T, true>(P, sp, g, tw, Lc, true, lds_scan, P.wall_lds);
     const int key0 = c.b * sp.bcells;
     const int i0 = P.cstart[sp.coff + key0], i1 = P.cstart[sp.coff + key0 + sp.bcells];
-    if (tot < 0 || wtot < 0) {
+    const int* wcs = P.wcstart + sp.wcoff;
+    const V* Lw = Lc + vt;
+    if (tot < 0) {
         for (int i = i0 + (int)threadIdx.x; i < i1; i += blockDim.x) P.nlist[i] = 0;
         if (threadIdx.x == 0) atomicOr(&P.st[c.s].status, ST_OVERFLOW | ST_TILE);
         return;
@@ -767,12 +759,22 @@ __global__ void __launch_bounds__(256) k_list_build(PoolDev P)
             const T sx = (T)(-dx * sp.h[0]), sy = (T)(-dy * sp.h[1]), sz = (T)(-dz * sp.h[2]);
             const int h = halo_cell(g, cx, cy, cz, q);
             const int a1 = t.hoff[h + 1];
-            for (int a = t.hoff[h]; a < a1; ++a) {
-                const V o = t.pos[a];
-                const T ex = me.x - o.x + sx, ey = me.y - o.y + sy, ez = me.z - o.z + sz;
-                if (ex * ex + ey * ey + ez * ez < rl2 && t.slot[a] != i) {
-                    if (nv < cap) P.list[(size_t)nv * vt + i] = (unsigned)a | ((unsigned)q << kIndexBits);
-                    ++nv;
+            for (int a = t.hoff[h]; a < a1; a += 4) {
+                V o[4];
+                int sl[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    o[u] = t.pos[min(a + u, a1 - 1)];
+                    sl[u] = t.slot[min(a + u, a1 - 1)];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const T ex = me.x - o[u].x + sx, ey = me.y - o[u].y + sy, ez = me.z - o[u].z + sz;
+                    if (a + u < a1 && ex * ex + ey * ey + ez * ez < rl2 && sl[u] != i) {
+                        if (nv < cap)
+                            P.list[(size_t)nv * vt + i] = (unsigned)(a + u) | ((unsigned)q << kIndexBits);
+                        ++nv;
+                    }
                 }
             }
         }
@@ -782,17 +784,26 @@ __global__ void __launch_bounds__(256) k_list_build(PoolDev P)
             const double gx = box_gap(lx, dx, sp.h[0]), gy = box_gap(ly, dy, sp.h[1]),
                          gz = box_gap(lz, dz, sp.h[2]);
             if (gx * gx + gy * gy + gz * gz >= cull_w) continue;
+            const int cl = wrap_cell(cx + dx, sp.nc[0]) +
+                           sp.nc[0] * (wrap_cell(cy + dy, sp.nc[1]) + sp.nc[1] * wrap_cell(cz + dz, sp.nc[2]));
+            const int w0 = wcs[cl], w1 = wcs[cl + 1];
+            if (w0 >= w1) continue;
             const T sx = (T)(-dx * sp.h[0]), sy = (T)(-dy * sp.h[1]), sz = (T)(-dz * sp.h[2]);
-            const int h = halo_cell(g, cx, cy, cz, q);
-            const int a1 = tw.hoff[h + 1];
-            for (int a = tw.hoff[h]; a < a1; ++a) {
-                const V o = tw.pos[a];
-                const T ex = me.x - o.x + sx, ey = me.y - o.y + sy, ez = me.z - o.z + sz;
-                if (ex * ex + ey * ey + ez * ez < rw2) {
-                    if (nv + nw < cap)
-                        P.list[(size_t)(nv + nw) * vt + i] =
-                            (unsigned)(tw.slot[a] - vt) | ((unsigned)q << kIndexBits);
-                    ++nw;
+            // four candidates per round, loads issued together (indices
+            // clamped to the cell's last wall)
+            for (int w = w0; w < w1; w += 4) {
+                V o[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) o[u] = Lw[min(w + u, w1 - 1)];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const T ex = me.x - o[u].x + sx, ey = me.y - o[u].y + sy, ez = me.z - o[u].z + sz;
+                    if (w + u < w1 && ex * ex + ey * ey + ez * ez < rw2) {
+                        if (nv + nw < cap)
+                            P.list[(size_t)(nv + nw) * vt + i] =
+                                (unsigned)(w + u) | ((unsigned)q << kIndexBits);
+                        ++nw;
+                    }
                 }
             }
         }
@@ -807,11 +818,10 @@ __global__ void __launch_bounds__(256) k_list_build(PoolDev P)
     }
 }
 
-size_t tile_bytes(const PoolDev& P, int precision, bool walls)
+size_t tile_bytes(const PoolDev& P, int precision)
 {
     const size_t v = precision == 1 ? sizeof(f4) : sizeof(d4);
-    auto one = [&](int cap) { return ((size_t)cap * (v + 4) + (size_t)(2 * P.hmax + 1) * 4 + 31) & ~(size_t)31; };
-    return one(P.lds_atoms) + (walls ? one(P.wall_lds) : 0);
+    return ((size_t)P.lds_atoms * (v + 4) + (size_t)(2 * P.hmax + 1) * 4 + 31) & ~(size_t)31;
 }
 
 hipError_t launch_rebuild(const PoolDev& P, int nslots, int precision, hipStream_t s)
@@ -820,7 +830,7 @@ hipError_t launch_rebuild(const PoolDev& P, int nslots, int precision, hipStream
     const int G = ((nrb + 7) / 8) * 8;
     const int GB = ((P.nbrick + 7) / 8) * 8;
     if (G == 0) return hipSuccess;
-    const size_t lds = tile_bytes(P, precision, true);
+    const size_t lds = tile_bytes(P, precision);
     hipLaunchKernelGGL(k_bin_count, dim3(G), dim3(kRebuildBlock), 0, s, P);
     hipLaunchKernelGGL(k_bin_scan, dim3(P.ntile), dim3(1024), 0, s, P);
     hipLaunchKernelGGL(k_bin_scan_finish, dim3(nslots), dim3(64), 0, s, P, nslots);
@@ -1130,7 +1140,7 @@ hipError_t launch_step(const PoolDev& P, int nslots, int precision, hipStream_t 
     const int G = ((P.nbrick + 7) / 8) * 8;
     const int B = P.block;
     if (G == 0) return hipSuccess;
-    const size_t lds = tile_bytes(P, precision, false);
+    const size_t lds = tile_bytes(P, precision);
     if (ev0 && ev1) {
         if (precision == 1)
             hipExtLaunchKernelGGL(k_step<float>, dim3(G), dim3(B), lds, s, ev0, ev1, 0, P);
@@ -1302,7 +1312,7 @@ hipError_t launch_debug_pairs(const PoolDev& P, int slot, int precision, int* ou
     hipError_t e = hipMemcpy(&sp, P.sp + slot, sizeof(SysParams), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return e;
     if (sp.nbrick <= 0) return hipSuccess;
-    const size_t lds = tile_bytes(P, precision, false);
+    const size_t lds = tile_bytes(P, precision);
     if (precision == 1)
         hipLaunchKernelGGL(k_debug_pairs<float>, dim3(sp.nbrick), dim3(P.block), lds, s, P, slot, out,
                            cap, counts);

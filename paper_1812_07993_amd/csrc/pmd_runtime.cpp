@@ -55,7 +55,7 @@ int round_up(int a, int b) { return ((a + b - 1) / b) * b; }
 // Workgroup order of the brick kernels: 1 = each XCD takes a contiguous run
 // of bricks (spatial neighbours share an L2), 2 = bricks dealt round-robin
 // over the XCDs (a dense region of the box is spread over all of them).
-constexpr int kDefaultBrickOrder = 1;
+constexpr int kDefaultBrickOrder = 2;
 
 constexpr int kDefaultErings = 16384;
 
@@ -253,7 +253,7 @@ struct Pool {
     // host
     std::vector<SysParams> hsp;
     std::vector<int> hchunk, htile, hbrick;
-    int nchunk = 0, ntile = 0, tcap = 0, nbrick = 0, lds_atoms = 0, hmax = 0, wall_lds = 0;
+    int nchunk = 0, ntile = 0, tcap = 0, nbrick = 0, lds_atoms = 0, hmax = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
     hipStream_t cap_stream = nullptr;
@@ -310,7 +310,6 @@ struct Pool {
         d.brick_sys = d_brick;
         d.nbrick = nbrick;
         d.lds_atoms = lds_atoms;
-        d.wall_lds = wall_lds;
         d.hmax = hmax;
         d.block = block;
         d.brick_order = brick_order;
@@ -445,8 +444,7 @@ int pool_grow_lists(Pool& p, int new_cap)
     return PMD_OK;
 }
 
-constexpr size_t kTileBytesMax = 60 * 1024;  // dynamic LDS of the step kernel's tile
-constexpr size_t kListLdsMax = 150 * 1024;   // dynamic LDS of the list build (vapour + walls)
+constexpr size_t kTileBytesMax = 60 * 1024;  // dynamic LDS of the staged halo tile
 
 size_t tile_atom_bytes(int precision) { return (precision == PMD_MIXED ? sizeof(f4) : sizeof(d4)) + 4; }
 
@@ -456,64 +454,14 @@ int halo_cells(const SysParams& sp)
            (std::min(sp.bdim[2], sp.nc[2]) + 2);
 }
 
-// Largest number of wall atoms in the halo box of any brick of a system
-// (walls are static, so this is exact until the bricks change).
-int wall_halo_max(const Pool& p, const SysParams& sp, int* out)
-{
-    *out = 0;
-    if (sp.nw == 0) return PMD_OK;
-    std::vector<int> wcs((size_t)sp.ncell + 1);
-    HIPCHK(hipMemcpy(wcs.data(), p.wcstart + sp.wcoff, sizeof(int) * wcs.size(), hipMemcpyDeviceToHost));
-    auto cnt = [&](int cx, int cy, int cz) {
-        const int c = cx + sp.nc[0] * (cy + sp.nc[1] * cz);
-        return wcs[c + 1] - wcs[c];
-    };
-    auto wrap = [](int c, int n) { return (c % n + n) % n; };
-    int best = 0;
-    for (int b = 0; b < sp.nbrick; ++b) {
-        const int B[3] = {b % sp.nbk[0], (b / sp.nbk[0]) % sp.nbk[1], b / (sp.nbk[0] * sp.nbk[1])};
-        int lo[3], hi[3];
-        for (int k = 0; k < 3; ++k) {
-            lo[k] = B[k] * sp.bdim[k] - 1;
-            hi[k] = std::min(sp.nc[k], B[k] * sp.bdim[k] + sp.bdim[k]);  // inclusive
-        }
-        int tot = 0;
-        for (int z = lo[2]; z <= hi[2]; ++z)
-            for (int y = lo[1]; y <= hi[1]; ++y)
-                for (int x = lo[0]; x <= hi[0]; ++x)
-                    tot += cnt(wrap(x, sp.nc[0]), wrap(y, sp.nc[1]), wrap(z, sp.nc[2]));
-        best = std::max(best, tot);
-    }
-    *out = best;
-    return PMD_OK;
-}
-
 // Lay out the chunk, scan-tile and brick tables from the per-slot parameters,
 // size the staged LDS tile, and upload.
-int pool_layout_once(Pool& p, int* worst_slot, size_t* list_lds);
-void choose_bricks(SysParams& sp, double target);
-
 int pool_layout(Pool& p)
-{
-    for (int iter = 0; iter < 64; ++iter) {
-        int worst = -1;
-        size_t lds = 0;
-        CHK(pool_layout_once(p, &worst, &lds));
-        if (lds <= kListLdsMax) return PMD_OK;
-        SysParams& sp = p.hsp[worst];
-        if (sp.bcells == 1) return fail(PMD_ENOMEM, "wall neighbourhood of one cell exceeds LDS");
-        const double occ = std::max((double)sp.nv / sp.ncell, 1e-3);
-        choose_bricks(sp, 0.5 * sp.bcells * occ);
-    }
-    return fail(PMD_EHIP, "could not fit the list-build tile in LDS");
-}
-
-int pool_layout_once(Pool& p, int* worst_slot, size_t* list_lds)
 {
     p.hchunk.clear();
     p.htile.clear();
     p.hbrick.clear();
-    int pb = 0, hmax = 0, wall_want = 0;
+    int pb = 0, hmax = 0;
     double lds_want = 0;
     for (int s = 0; s < p.nslots; ++s) {
         SysParams& sp = p.hsp[s];
@@ -538,10 +486,6 @@ int pool_layout_once(Pool& p, int* worst_slot, size_t* list_lds)
         for (int t = 0; t < sp.nbrick; ++t) p.hbrick.push_back(s);
         const int H = halo_cells(sp);
         hmax = std::max(hmax, H);
-        int wmax = 0;
-        CHK(wall_halo_max(p, sp, &wmax));
-        if (wmax > wall_want) *worst_slot = s;
-        wall_want = std::max(wall_want, wmax);
         const double occ = (double)sp.nv / sp.ncell;
         lds_want = std::max(lds_want, 2.0 * H * occ + 128.0);
     }
@@ -553,10 +497,6 @@ int pool_layout_once(Pool& p, int* worst_slot, size_t* list_lds)
     const size_t ints = (size_t)(2 * p.hmax + 1) * 4;
     const int lds_max = (int)((kTileBytesMax - std::min(ints, kTileBytesMax / 2)) / ab);
     p.lds_atoms = std::max(std::min((int)lds_want, lds_max), std::min(p.lds_atoms, lds_max));
-    p.wall_lds = wall_want;
-    auto one = [&](int cap) { return ((size_t)cap * ab + (size_t)(2 * p.hmax + 1) * 4 + 31) & ~(size_t)31; };
-    *list_lds = one(p.lds_atoms) + one(p.wall_lds);
-    if (*worst_slot < 0) *worst_slot = 0;
     if (p.nchunk > p.vt / kChunk) return fail(PMD_ENOMEM, "pool chunk table too small");
     if (p.ntile > p.tcap) return fail(PMD_ENOMEM, "pool tile table too small");
     if (pb > p.nbt) return fail(PMD_ENOMEM, "pool brick table too small (%d > %d)", pb, p.nbt);
@@ -993,7 +933,7 @@ int batch_repack(pmd_batch* b, const Needs& extra, int extra_cap)
     p.wt = (int)(tot.wt * 1.25) + 1;
     p.ct = (int)(tot.ct * 1.25) + 8;
     p.wct = (int)(tot.wct * 1.25) + 8;
-    p.nbt = p.vt / kChunk;
+    p.nbt = (int)(tot.nbt * 1.25) + 8;
     if (b->budget) {
         size_t want = pool_bytes(p.precision, p.vt, p.wt, p.ct, p.wct, p.nbt, p.nslots, p.cap, p.ering_cap);
         if (want > b->budget) {
@@ -1001,7 +941,7 @@ int batch_repack(pmd_batch* b, const Needs& extra, int extra_cap)
             p.wt = std::max(tot.wt, 1);
             p.ct = tot.ct;
             p.wct = tot.wct;
-            p.nbt = p.vt / kChunk;
+            p.nbt = tot.nbt;
         }
     }
     p.stream = old->stream;
@@ -1056,7 +996,7 @@ bool batch_bump(pmd_batch* b, const Needs& n, SysParams* sp)
     }
     int nbt = 0;
     for (size_t s = 0; s < b->resident.size(); ++s)
-        if (b->resident[s]) nbt += p.hsp[s].vcap / kChunk;
+        if (b->resident[s]) nbt += needs_of(p.hsp[s]).nbt;
     if (vo + n.vt > p.vt || wo + n.wt > p.wt || co + n.ct > p.ct || wco + n.wct > p.wct ||
         nbt + n.nbt > p.nbt)
         return false;
@@ -1204,7 +1144,6 @@ int pmd_create_system(const pmd_params* params, const pmd_pore* pore, int64_t n_
         }
         HIPCHK(launch_wall_bin(p.dev(), 0, raw, (int)nw, (int)nw, p.precision, p.stream));
         HIPCHK(hipStreamSynchronize(p.stream));
-        CHK(pool_layout(p));  // wall halo sizes need the binned walls
 
         // vapour: copy in (caller order), then bin, build lists and compute a(0)
         sys->own = std::move(pool);

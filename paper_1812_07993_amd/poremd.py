@@ -110,6 +110,13 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError("libporemd.so not built at %s; run __graft_entry__.build()" % LIB_PATH)
+    # One HIP runtime per process: PyTorch ships its own copy of the HIP
+    # runtime under the same soname; loading it first makes the library bind
+    # to that copy, so streams and device pointers from torch are valid here.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     for name, (res, args) in _SIGS.items():
         fn = getattr(lib, name)
