@@ -151,6 +151,91 @@ def serve_leg(n_requests, budget_gb, chunk):
     return s
 
 
+def batch_leg(poremd, count, steps, alone_steps, tuning_kw):
+    """Replica batch: `count` independent systems (vapour N log-uniform in
+    [1k, 64k], pore from {cylinder, slit, cone}, box at density 0.1) resident
+    in one batch and advanced together, against the same systems stepped one
+    at a time.  Both in vapour atom-steps per second, mixed precision."""
+    import torch
+
+    from paper_1812_07993_amd import synth
+
+    t0 = time.perf_counter()
+    descs = [synth.replica(sp, "mixed", steps) for sp in synth.replica_specs(count)]
+    tun = poremd.make_tuning(**{k: v for k, v in tuning_kw.items() if k != "brick_atoms"})
+    stream = torch.cuda.Stream()
+    handles = [poremd.System.from_desc(d, tuning=tun, stream=stream.cuda_stream) for d in descs]
+    natoms = sum(d.n for d in descs)
+    log("batch: %d systems, %d vapour atoms, created in %.1f s"
+        % (count, natoms, time.perf_counter() - t0))
+    # one at a time (each system on its own, the same stream)
+    for h in handles:
+        h.step(alone_steps // 4)
+        h.sync()
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for h in handles:
+        h.step(alone_steps)
+        h.sync()
+    torch.cuda.synchronize()
+    alone = natoms * alone_steps / (time.perf_counter() - w0)
+    # all in one batch: every system runs exactly `steps` steps; the timed
+    # region spans the first advance to the last system finishing (one graph
+    # capture and the replays re-queued after early rebuilds included)
+    b = poremd.pmd_batch_create(0, count, stream.cuda_stream)
+    slots = [poremd.pmd_batch_admit(b, h.h, steps) for h in handles]
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    poremd.pmd_batch_advance(b, steps)
+    while len(poremd.pmd_batch_poll(b)) < count:
+        poremd.pmd_batch_advance(b, max(steps // 10, 1))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    batched = natoms * steps / wall
+    for sl in slots:
+        poremd.pmd_batch_release(b, sl)
+    E = [h.energies() for h in handles]
+    poremd.pmd_batch_destroy(b)
+    for h in handles:
+        h.close()
+    bad = sum(not np.isfinite(e["etotal"]) for e in E)
+    log("batch: %.3e atom-steps/s batched (%d steps, %.3f s), %.3e one at a time"
+        % (batched, steps, wall, alone))
+    return {"systems": count, "vapour_atoms": natoms, "steps": steps, "value": batched,
+            "unit": "atom-steps/s", "one_at_a_time": alone, "one_at_a_time_steps": alone_steps,
+            "speedup": batched / alone, "nonfinite_systems": bad}
+
+
+def pore_sweep_leg(poremd, kinds, steps, autotune_steps, tuning_kw):
+    """The dense workload: 256 x 256 x 128 box, one 8-thick wall slab with a
+    pore (cylinder r = 6, cone 4 -> 12, ink-bottle 3 / 10), 4194304 vapour
+    atoms (density 0.5), mixed precision."""
+    import torch
+
+    from paper_1812_07993_amd import synth
+
+    out = {}
+    for kind in kinds:
+        t0 = time.perf_counter()
+        desc = synth.pore_sweep(kind)
+        log("[sweep %s] %d vapour atoms generated in %.1f s" % (kind, desc.n, time.perf_counter() - t0))
+        kw = dict(tuning_kw)
+        if autotune_steps > 0:
+            kw.update(autotune(poremd, desc, "mixed", autotune_steps, tuning_kw))
+        r = run_path(poremd, desc, "mixed", steps, max(steps // 10, 10), 10, kw)
+        n_launch, kms = kernel_time(poremd, r["sys"], min(steps, 100))
+        n = desc.n
+        out[kind] = {"value": n * steps / (r["ms"] / 1000.0), "unit": "atom-steps/s",
+                     "ms_per_step": r["ms"] / steps, "steps": steps, "n_vapour": n,
+                     "n_wall": r["sys"].n_wall, "kernel_ms": kms,
+                     "roofline_frac": ALG_BYTES["mixed"] * n / (kms / 1000.0) / 1e9 / PEAK_HBM_GBS,
+                     "rebuilds": r["rebuilds"], "max_list": r["max_list"], "tuning": kw}
+        log("[sweep %s] %.3e atom-steps/s, step kernel %.3f ms" % (kind, out[kind]["value"], kms))
+        r["sys"].close()
+        torch.cuda.synchronize()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -170,6 +255,13 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=24,
                     help="requests of the served trace (0 = skip the serving leg)")
     ap.add_argument("--serve-budget-gb", type=float, default=2.0)
+    ap.add_argument("--batch-systems", type=int, default=256,
+                    help="replica systems of the batched leg (0 = skip it)")
+    ap.add_argument("--batch-steps", type=int, default=1000)
+    ap.add_argument("--sweep", default="cylinder",
+                    help="pores of the 4M-atom leg, comma separated (cylinder,cone,inkbottle); "
+                         "'none' skips it")
+    ap.add_argument("--sweep-steps", type=int, default=500)
     ap.add_argument("--serve-chunk", type=int, default=250)
     ap.add_argument("--timing-steps", type=int, default=500)
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -192,12 +284,14 @@ def main():
     poremd.load()
     assert torch.cuda.is_available(), "needs a GPU"
     if args.copy_mib > 0:
-        src = torch.empty(args.copy_mib * 2 ** 20, dtype=torch.uint8, device="cuda").fill_(1)
+        # an elementwise kernel (not a DMA copy) that reads and writes exactly
+        # copy_mib MiB each
+        src = torch.ones(args.copy_mib * 2 ** 18, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
-        dst.copy_(src)
+        torch.mul(src, 2.0, out=dst)
         torch.cuda.synchronize()
-        log("copy calibration: %d MiB read + %d MiB written by one copy kernel"
+        log("copy calibration: %d MiB read + %d MiB written by one elementwise kernel"
             % (args.copy_mib, args.copy_mib))
         del src, dst
     t0 = time.perf_counter()
@@ -282,6 +376,13 @@ def main():
         out["mixed_over_fp64"] = out["value"] / out["fp64"]["value"]
     for r in res.values():
         r["sys"].close()
+    if args.sweep != "none":
+        out["pore_sweep"] = pore_sweep_leg(poremd, args.sweep.split(","), args.sweep_steps,
+                                           0 if (args.skin or args.rebin_every)
+                                           else min(args.autotune_steps, 50), tkw)
+    if args.batch_systems > 0:
+        out["batched"] = batch_leg(poremd, args.batch_systems, args.batch_steps, 40,
+                                   tuned["mixed"])
     if args.serve_requests > 0:
         out["serve"] = serve_leg(args.serve_requests, args.serve_budget_gb, args.serve_chunk)
         out["served_p50_s"] = out["serve"]["p50_s"]
