@@ -849,7 +849,7 @@ hipError_t launch_rebuild(const PoolDev& P, int nslots, int precision, hipStream
 // Step: forces (F1) + second half-kick (F3) [+ next drift and half-kick (F2)]
 // ---------------------------------------------------------------------------
 
-constexpr int kGroup = 8;  // list entries fetched together in the step kernel
+constexpr int kGroup = 6;  // list entries fetched together in the step kernel
 
 template <typename T>
 __device__ __forceinline__ T inv_of(T r2);
@@ -909,10 +909,31 @@ __global__ void __launch_bounds__(256) k_step(PoolDev P)
         const int nl = P.nlist[i];
         const int nvap = nl & 0xFFFF, nall = nvap + (nl >> 16);
         double fx = 0.0, fy = 0.0, fz = 0.0, eav = 0.0, eaw = 0.0;
+        // one in-cutoff pair: FP32 (mixed) or FP64 LJ, FP64 sums
+        auto pair = [&](T dx, T dy, T dz, T r2, bool wall) {
+            const T A = wall ? Aw : Av, B = wall ? Bw : Bv;
+            const T sr2 = inv_of<T>(r2);
+            const T sr6 = sr2 * sr2 * sr2;
+            const T w = sr2 * sr6 * ((wall ? A12w : A12v) * sr6 - (wall ? B6w : B6v));
+            fx += (double)(w * dx);
+            fy += (double)(w * dy);
+            fz += (double)(w * dz);
+            if (doE) {
+                const double u_ = (double)(sr6 * (A * sr6 - B) - (wall ? ucw : ucv));
+                if (wall)
+                    eaw += u_;
+                else
+                    eav += u_;
+            }
+        };
         const unsigned* lst = P.list + i;
-        // entries come 8 at a time, the next group's loads in flight while
+        // entries come kGroup at a time, the next group's loads in flight while
         // the current one is evaluated; vapour partners are read from LDS,
         // the group's wall partners are fetched together
+        // pairs whose FP32 r^2 lies within a narrow band around the cutoff
+        // are left out here and decided in FP64 after the whole list (a rare
+        // slow path: a few atoms per step), so the per-pair code has no branch
+        bool edge = false;
         unsigned ec[kGroup];
 #pragma unroll
         for (int u = 0; u < kGroup; ++u) ec[u] = (u < nall) ? lst[(size_t)u * vt] : 0u;
@@ -933,52 +954,48 @@ __global__ void __launch_bounds__(256) k_step(PoolDev P)
                 if (k >= nall) break;
                 const unsigned e = ec[u];
                 const bool wall = k >= nvap;
-                const int a = (int)(e & kIndexMask);
-                const V o = wall ? ow[u] : tl.pos[a];
+                const V o = wall ? ow[u] : tl.pos[e & kIndexMask];
                 const V sh = tab[e >> kIndexBits];
                 const T dx = me.x - o.x + sh.x;
                 const T dy = me.y - o.y + sh.y;
                 const T dz = me.z - o.z + sh.z;
                 const T r2 = dx * dx + dy * dy + dz * dz;
-                bool in = r2 < rc2;
-                if (sizeof(T) == 4 && fabs(r2 - rc2) < band) {
-                    // FP64 re-test of a pair at the cutoff edge
-                    double ox, oy, oz;
-                    if (wall) {
-                        ox = P.WX[a];
-                        oy = P.WX[P.wt + a];
-                        oz = P.WX[2 * P.wt + a];
-                    } else {
-                        const int j = tl.slot[a];
-                        ox = X[j];
-                        oy = X[vt + j];
-                        oz = X[2 * vt + j];
-                    }
-                    double ex = xi - ox, ey = yi - oy, ez = zi - oz;
-                    ex -= sp.L[0] * rint(ex * sp.invL[0]);
-                    ey -= sp.L[1] * rint(ey * sp.invL[1]);
-                    ez -= sp.L[2] * rint(ez * sp.invL[2]);
-                    in = ex * ex + ey * ey + ez * ez < sp.rc2;
-                }
-                if (in) {
-                    const T A = wall ? Aw : Av, B = wall ? Bw : Bv;
-                    const T sr2 = inv_of<T>(r2);
-                    const T sr6 = sr2 * sr2 * sr2;
-                    const T w = sr2 * sr6 * ((wall ? A12w : A12v) * sr6 - (wall ? B6w : B6v));
-                    fx += (double)(w * dx);
-                    fy += (double)(w * dy);
-                    fz += (double)(w * dz);
-                    if (doE) {
-                        const double u_ = (double)(sr6 * (A * sr6 - B) - (wall ? ucw : ucv));
-                        if (wall)
-                            eaw += u_;
-                        else
-                            eav += u_;
-                    }
-                }
+                const bool near = sizeof(T) == 4 && fabs(r2 - rc2) < band;
+                edge |= near;
+                if (r2 < rc2 && !near) pair(dx, dy, dz, r2, wall);
             }
 #pragma unroll
             for (int u = 0; u < kGroup; ++u) ec[u] = en[u];
+        }
+        if (edge) {
+            for (int k = 0; k < nall; ++k) {
+                const unsigned e = lst[(size_t)k * vt];
+                const bool wall = k >= nvap;
+                const int a = (int)(e & kIndexMask);
+                const V o = wall ? Lc[vt + a] : tl.pos[a];
+                const V sh = tab[e >> kIndexBits];
+                const T dx = me.x - o.x + sh.x;
+                const T dy = me.y - o.y + sh.y;
+                const T dz = me.z - o.z + sh.z;
+                const T r2 = dx * dx + dy * dy + dz * dz;
+                if (!(fabs(r2 - rc2) < band)) continue;
+                double ox, oy, oz;
+                if (wall) {
+                    ox = P.WX[a];
+                    oy = P.WX[P.wt + a];
+                    oz = P.WX[2 * P.wt + a];
+                } else {
+                    const int j = tl.slot[a];
+                    ox = X[j];
+                    oy = X[vt + j];
+                    oz = X[2 * vt + j];
+                }
+                double ex = xi - ox, ey = yi - oy, ez = zi - oz;
+                ex -= sp.L[0] * rint(ex * sp.invL[0]);
+                ey -= sp.L[1] * rint(ey * sp.invL[1]);
+                ez -= sp.L[2] * rint(ez * sp.invL[2]);
+                if (ex * ex + ey * ey + ez * ez < sp.rc2) pair(dx, dy, dz, r2, wall);
+            }
         }
         evv += 0.5 * eav;
         evw += eaw;
