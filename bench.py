@@ -25,9 +25,26 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# survey §8(d) algorithmic bytes per vapour atom-step (mixed / FP64)
+# algorithmic bytes per vapour atom-step (mixed / FP64): FP64 x and v read and
+# written once, plus the FP32 (FP64) neighbour copy written once and read once
 ALG_BYTES = {"mixed": 120.0, "fp64": 144.0}
 PEAK_HBM_GBS = 8000.0
+
+# HBM bytes per k_step<float> launch from the FETCH_SIZE / WRITE_SIZE counter
+# passes summarised in profiles/k_step_slit128_mixed.md, keyed by the hash of
+# the kernel source they were taken on and the tuning they were taken at; any
+# other kernel source or tuning reports null.
+MEASURED_TRAFFIC = {
+    ("5325eec8ad4fd86b", 262144, 0.7, 12, 256, 0): 95.8e6,
+}
+
+
+def kernel_source_hash():
+    import hashlib
+
+    path = os.path.join(ROOT, "paper_1812_07993_amd", "csrc", "pmd_kernels.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
 def log(*a):
@@ -64,7 +81,18 @@ def autotune(poremd, desc, prec, trial_steps, tuning_kw):
     order = np.argsort(us)[:5]
     log("[%s] autotune top 5: %s" % (prec, ", ".join(
         "(%.2f, %d) %.2f" % (grid[i].skin, grid[i].rebin_every, us[i]) for i in order)))
-    return dict(skin=float(b.skin), rebin_every=int(b.rebin_every))
+    out = dict(skin=float(b.skin), rebin_every=int(b.rebin_every))
+    if tuning_kw.get("block") or tuning_kw.get("brick_atoms"):
+        return out
+    # second stage: workgroup size and atoms per brick at the chosen skin and period
+    shapes = [(256, 0), (256, 256), (256, 160), (128, 0)]
+    cands = [poremd.make_tuning(skin=b.skin, rebin_every=b.rebin_every, block=bl, brick_atoms=ba)
+             for bl, ba in shapes]
+    best2, us2 = poremd.pmd_autotune(params, pore, desc.x, desc.v, cands, trial_steps)
+    log("[%s] autotune shapes: %s" % (prec, ", ".join(
+        "(%d, %d) %.2f" % (bl, ba, u) for (bl, ba), u in zip(shapes, us2))))
+    out.update(block=shapes[best2][0], brick_atoms=shapes[best2][1])
+    return out
 
 
 def run_path(poremd, desc, prec, steps, warmup, energy_every, tuning_kw):
@@ -98,12 +126,16 @@ def run_path(poremd, desc, prec, steps, warmup, energy_every, tuning_kw):
 
 
 def kernel_time(poremd, s, steps):
+    """Mean duration of the step kernel over the launches that did a step
+    (launches shorter than a quarter of the median are the ones that
+    returned at once after an early-rebuild halt)."""
     poremd.pmd_timing_enable(s.h, True)
     s.step(steps)
     s.sync()
-    n, mean_ms = poremd.pmd_kernel_time(s.h)
+    t = poremd.pmd_kernel_times(s.h)
     poremd.pmd_timing_enable(s.h, False)
-    return n, mean_ms
+    full = t[t >= 0.25 * np.median(t)]
+    return len(full), float(full.mean())
 
 
 def cpu_baseline(desc, sample_atoms, seed=0):
@@ -358,7 +390,13 @@ def main():
                    "n_vapour": n, "n_wall": m["sys"].n_wall, "box": args.box,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "frac": achieved / PEAK_HBM_GBS,
+                     "traffic": MEASURED_TRAFFIC.get((kernel_source_hash(), n,
+                                                      round(tuned["mixed"].get("skin", 0.0), 3),
+                                                      tuned["mixed"].get("rebin_every", 0),
+                                                      tuned["mixed"].get("block") or 256,
+                                                      tuned["mixed"].get("brick_atoms") or 0)),
+                     "traffic_unit": "bytes per launch",
                      "kernel": "k_step<float>", "kernel_ms": m["kernel_ms"],
                      "alg_bytes_per_atom_step": ALG_BYTES["mixed"]},
         "accuracy": {"mixed_drift_trend": m["drift_trend"], "mixed_drift_max": m["drift_max"],

@@ -206,13 +206,17 @@ int pmd_set_state(pmd_system *sys, const double *pos, const double *vel,
  * on the density, the temperature and the device.  pmd_autotune times each
  * candidate on one trial copy of the system described by the same inputs as
  * pmd_create_system (the caller's arrays are not changed, no caller system
- * is touched): per candidate it loads the initial state, runs
- * trial_steps / 4 untimed steps, then times trial_steps steps (wall clock,
- * including rebuilds and early-rebuild round trips).  us_per_step
- * [n_candidates] (may be NULL) receives each candidate's microseconds per
- * step (infinity for a candidate that cannot run, e.g. a skin leaving fewer
- * than 3 cells per axis); *best the index of the fastest.  Fails if none
- * runs.  pmd_autotune_grid writes the built-in candidate grid (skin x
+ * is touched): the trial copy first runs max(2 x trial_steps, 1000) steps
+ * (a fresh placement is not typical of a run: adsorption onto the walls
+ * changes local densities and speeds); per candidate it then reloads that
+ * state, runs trial_steps / 4 untimed steps and times trial_steps steps
+ * (wall clock, including rebuilds and early-rebuild round trips).
+ * us_per_step [n_candidates] (may be NULL) receives each candidate's
+ * microseconds per step (infinity for a candidate that cannot run, e.g. a
+ * skin leaving fewer than 3 cells per axis); *best the index of the fastest,
+ * or, when us_per_step is given, of the candidate with the largest skin
+ * (then longest period) within 2% of the fastest, since early rebuilds grow
+ * more frequent as a run goes on.  Fails if none runs.  pmd_autotune_grid writes the built-in candidate grid (skin x
  * rebuild period, other knobs at their defaults) into out[cap]; with
  * out == NULL it only reports the count in *n_out. */
 int pmd_autotune_grid(const pmd_params *params, int64_t n_vapor, pmd_tuning *out,
@@ -233,6 +237,11 @@ int pmd_destroy(pmd_system *sys);
  * number of launches timed and their mean duration in milliseconds. */
 int pmd_timing_enable(pmd_system *sys, int enable);
 int pmd_kernel_time(pmd_system *sys, int64_t *launches, double *mean_ms);
+/* The duration of every timed launch, oldest first, in milliseconds; at most
+ * cap values are written, *n_out receives the number timed.  Launches that
+ * return at once (the steps of a replay after an early-rebuild halt) are
+ * included; callers separate them by duration. */
+int pmd_kernel_times(pmd_system *sys, double *out_ms, int64_t cap, int64_t *n_out);
 
 /* ---- Test-only debug exports (same library; unstable) ------------------- */
 

@@ -17,7 +17,7 @@ constexpr int kChunk = 16;           // atoms per entry of the chunk -> system t
 constexpr int kLanes = 4;            // lanes per atom in the list-build and step kernels
 constexpr int kTile = 4096;          // cells per workgroup of the cell-count scan
 constexpr int kRebuildBlock = 256;   // threads per workgroup of the per-atom rebuild kernels
-constexpr unsigned kIndexBits = 27;  // neighbour-list entry: index | code << 27
+constexpr unsigned kIndexBits = 26;  // neighbour-list entry: index | cell-offset code << 26
 constexpr unsigned kIndexMask = (1u << kIndexBits) - 1u;
 
 enum Phase : int {

@@ -40,6 +40,22 @@ __device__ __forceinline__ int logical_block()
     return (b & 7) * q + (b >> 3);
 }
 
+// Cell-offset code of a list entry: 2 bits per axis above kIndexBits, the
+// neighbour cell's offset d in {-1, 0, 1} stored as d + 1.
+__device__ __forceinline__ unsigned offset_code(int q)
+{
+    return (unsigned)(q % 3) | ((unsigned)((q / 3) % 3) << 2) | ((unsigned)(q / 9) << 4);
+}
+
+// Shift -d h that moves the neighbour's cell-local coordinate into the frame
+// of the atom's cell along one axis (exactly h, 0 or -h).
+template <typename T>
+__device__ __forceinline__ T shift_of(unsigned e, int bit, T h)
+{
+    const T b = (T)((e >> (kIndexBits + bit)) & 3u);
+    return fma(-b, h, h);
+}
+
 __device__ __forceinline__ int wrap_cell(int c, int n)
 {
     c += (c < 0) ? n : 0;
@@ -772,7 +788,7 @@ __global__ void __launch_bounds__(256) k_list_build(PoolDev P)
                     const T ex = me.x - o[u].x + sx, ey = me.y - o[u].y + sy, ez = me.z - o[u].z + sz;
                     if (a + u < a1 && ex * ex + ey * ey + ez * ez < rl2 && sl[u] != i) {
                         if (nv < cap)
-                            P.list[(size_t)nv * vt + i] = (unsigned)(a + u) | ((unsigned)q << kIndexBits);
+                            P.list[(size_t)nv * vt + i] = (unsigned)(a + u) | (offset_code(q) << kIndexBits);
                         ++nv;
                     }
                 }
@@ -801,7 +817,7 @@ __global__ void __launch_bounds__(256) k_list_build(PoolDev P)
                     if (w + u < w1 && ex * ex + ey * ey + ez * ez < rw2) {
                         if (nv + nw < cap)
                             P.list[(size_t)(nv + nw) * vt + i] =
-                                (unsigned)(w + u) | ((unsigned)q << kIndexBits);
+                                (unsigned)(w + u) | (offset_code(q) << kIndexBits);
                         ++nw;
                     }
                 }
@@ -851,6 +867,8 @@ hipError_t launch_rebuild(const PoolDev& P, int nslots, int precision, hipStream
 
 constexpr int kGroup = 6;  // list entries fetched together in the step kernel
 
+
+
 template <typename T>
 __device__ __forceinline__ T inv_of(T r2);
 template <>
@@ -863,7 +881,6 @@ __global__ void __launch_bounds__(256) k_step(PoolDev P)
 {
     using V = typename V4<T>::type;
     extern __shared__ __align__(32) unsigned char smem[];
-    __shared__ V tab[27];
     __shared__ double red[3][4];
     __shared__ int flag_or[4];
     __shared__ int lds_scan[17];
@@ -874,10 +891,6 @@ __global__ void __launch_bounds__(256) k_step(PoolDev P)
     const SysParams& sp = P.sp[s];
     const SysState st = P.st[s];
     const int tid = threadIdx.x;
-    if (tid < 27) {
-        const int dx = tid % 3 - 1, dy = (tid / 3) % 3 - 1, dz = tid / 9 - 1;
-        tab[tid] = make4<T>(-dx * sp.h[0], -dy * sp.h[1], -dz * sp.h[2]);
-    }
     const V* Lc = (const V*)P.L[st.lbuf];
     const HaloGeo g = halo_geo(sp, c.b);
     Tile<T> tl = tile_of<T>(smem, P);
@@ -900,6 +913,7 @@ __global__ void __launch_bounds__(256) k_step(PoolDev P)
     const T A12v = (T)12 * Av, B6v = (T)6 * Bv, A12w = (T)12 * Aw, B6w = (T)6 * Bw;
     const T ucv = (T)sp.uc, ucw = (T)sp.ucw;
     const T band = (T)(4.0e-6 * sp.rc2);
+    const T hx = (T)sp.h[0], hy = (T)sp.h[1], hz = (T)sp.h[2];
     for (int i = i0 + tid; tot >= 0 && i < i1; i += blockDim.x) {
         const V me = Lc[i];
         const double xi = X[i], yi = X[vt + i], zi = X[2 * vt + i];
@@ -934,35 +948,62 @@ __global__ void __launch_bounds__(256) k_step(PoolDev P)
         // are left out here and decided in FP64 after the whole list (a rare
         // slow path: a few atoms per step), so the per-pair code has no branch
         bool edge = false;
+        // every load below is unconditional, with indices clamped to valid
+        // memory (list rows past the end of this atom's list exist up to the
+        // capacity; their values are not used), so the code is straight-line
+        // and each wait covers only the loads it needs
+        const int lastrow = P.cap - 1;
         unsigned ec[kGroup];
+        // vapour partners (the first nvap entries), positions from LDS
 #pragma unroll
-        for (int u = 0; u < kGroup; ++u) ec[u] = (u < nall) ? lst[(size_t)u * vt] : 0u;
-        for (int k0 = 0; k0 < nall; k0 += kGroup) {
+        for (int u = 0; u < kGroup; ++u) ec[u] = lst[(size_t)min(u, lastrow) * vt];
+        for (int k0 = 0; k0 < nvap; k0 += kGroup) {
             unsigned en[kGroup];
 #pragma unroll
             for (int u = 0; u < kGroup; ++u)
-                en[u] = (k0 + kGroup + u < nall) ? lst[(size_t)(k0 + kGroup + u) * vt] : 0u;
-            V ow[kGroup];
+                en[u] = lst[(size_t)min(k0 + kGroup + u, lastrow) * vt];
 #pragma unroll
             for (int u = 0; u < kGroup; ++u) {
-                const bool w_ = k0 + u >= nvap && k0 + u < nall;
-                ow[u] = Lc[vt + (w_ ? (int)(ec[u] & kIndexMask) : 0)];
+                const bool live = k0 + u < nvap;
+                const unsigned e = ec[u];
+                const V o = tl.pos[live ? (int)(e & kIndexMask) : 0];
+                const T dx = me.x - o.x + shift_of<T>(e, 0, hx);
+                const T dy = me.y - o.y + shift_of<T>(e, 2, hy);
+                const T dz = me.z - o.z + shift_of<T>(e, 4, hz);
+                const T r2 = dx * dx + dy * dy + dz * dz;
+                const bool near = live && sizeof(T) == 4 && fabs(r2 - rc2) < band;
+                edge |= near;
+                if (live && r2 < rc2 && !near) pair(dx, dy, dz, r2, false);
             }
 #pragma unroll
+            for (int u = 0; u < kGroup; ++u) ec[u] = en[u];
+        }
+        // wall partners (entries nvap .. nall), positions from global memory
+        if (nall > nvap) {
+#pragma unroll
+            for (int u = 0; u < kGroup; ++u) ec[u] = lst[(size_t)min(nvap + u, lastrow) * vt];
+        }
+        for (int k0 = nvap; k0 < nall; k0 += kGroup) {
+            V ow[kGroup];
+#pragma unroll
+            for (int u = 0; u < kGroup; ++u)
+                ow[u] = Lc[vt + (k0 + u < nall ? (int)(ec[u] & kIndexMask) : 0)];
+            unsigned en[kGroup];
+#pragma unroll
+            for (int u = 0; u < kGroup; ++u)
+                en[u] = lst[(size_t)min(k0 + kGroup + u, lastrow) * vt];
+#pragma unroll
             for (int u = 0; u < kGroup; ++u) {
-                const int k = k0 + u;
-                if (k >= nall) break;
+                const bool live = k0 + u < nall;
                 const unsigned e = ec[u];
-                const bool wall = k >= nvap;
-                const V o = wall ? ow[u] : tl.pos[e & kIndexMask];
-                const V sh = tab[e >> kIndexBits];
-                const T dx = me.x - o.x + sh.x;
-                const T dy = me.y - o.y + sh.y;
-                const T dz = me.z - o.z + sh.z;
+                const V o = ow[u];
+                const T dx = me.x - o.x + shift_of<T>(e, 0, hx);
+                const T dy = me.y - o.y + shift_of<T>(e, 2, hy);
+                const T dz = me.z - o.z + shift_of<T>(e, 4, hz);
                 const T r2 = dx * dx + dy * dy + dz * dz;
-                const bool near = sizeof(T) == 4 && fabs(r2 - rc2) < band;
+                const bool near = live && sizeof(T) == 4 && fabs(r2 - rc2) < band;
                 edge |= near;
-                if (r2 < rc2 && !near) pair(dx, dy, dz, r2, wall);
+                if (live && r2 < rc2 && !near) pair(dx, dy, dz, r2, true);
             }
 #pragma unroll
             for (int u = 0; u < kGroup; ++u) ec[u] = en[u];
@@ -973,10 +1014,9 @@ __global__ void __launch_bounds__(256) k_step(PoolDev P)
                 const bool wall = k >= nvap;
                 const int a = (int)(e & kIndexMask);
                 const V o = wall ? Lc[vt + a] : tl.pos[a];
-                const V sh = tab[e >> kIndexBits];
-                const T dx = me.x - o.x + sh.x;
-                const T dy = me.y - o.y + sh.y;
-                const T dz = me.z - o.z + sh.z;
+                const T dx = me.x - o.x + shift_of<T>(e, 0, hx);
+                const T dy = me.y - o.y + shift_of<T>(e, 2, hy);
+                const T dz = me.z - o.z + shift_of<T>(e, 4, hz);
                 const T r2 = dx * dx + dy * dy + dz * dz;
                 if (!(fabs(r2 - rc2) < band)) continue;
                 double ox, oy, oz;

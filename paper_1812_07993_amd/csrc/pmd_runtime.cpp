@@ -646,8 +646,10 @@ int pool_enqueue(Pool& p, int R, int use_graph, int64_t replays)
         for (int k = 0; k < R; ++k) {
             if (p.timing) {
                 hipEvent_t a, b;
-                HIPCHK(hipEventCreate(&a));
-                HIPCHK(hipEventCreate(&b));
+                // no system-scope fence on the timing events: the kernel's
+                // duration is wanted, not that of a cache flush behind it
+                HIPCHK(hipEventCreateWithFlags(&a, hipEventDisableSystemFence));
+                HIPCHK(hipEventCreateWithFlags(&b, hipEventDisableSystemFence));
                 p.events.emplace_back(a, b);
                 HIPCHK(launch_step(d, p.nslots, p.precision, p.stream, a, b));
             } else {
@@ -1430,13 +1432,21 @@ int pmd_autotune(const pmd_params* params, const pmd_pore* pore, int64_t n_vapor
         CHK(pmd_create_system(params, pore, n_vapor, pos, vel, n_wall, wall_pos, hip_stream,
                               candidates + order[0], &trial));
         std::unique_ptr<pmd_system, int (*)(pmd_system*)> guard(trial, pmd_destroy);
+        // the first steps of a freshly placed system are not typical of a
+        // run (adsorption onto the walls changes densities and speeds), so
+        // every candidate starts from the state 2 x trial_steps steps later
+        CHK(pmd_step(trial, std::max<int64_t>(2 * trial_steps, 1000)));
+        CHK(sys_sync(trial));
+        std::vector<double> x0(3 * (size_t)n_vapor), v0(3 * (size_t)n_vapor);
+        CHK(pmd_get_positions(trial, x0.data(), n_vapor));
+        CHK(pmd_get_velocities(trial, v0.data(), n_vapor));
         const int64_t warm = std::max<int64_t>(trial_steps / 4, 1);
         double best_us = std::numeric_limits<double>::infinity();
         *best = -1;
         for (int32_t c : order) {
             double us = std::numeric_limits<double>::infinity();
             int rc = pmd_set_tuning(trial, candidates + c);
-            if (rc == PMD_OK) rc = load_state(trial, pos, vel, 0);
+            if (rc == PMD_OK) rc = load_state(trial, x0.data(), v0.data(), 0);
             if (rc == PMD_OK) rc = pmd_step(trial, warm);
             if (rc == PMD_OK) rc = sys_sync(trial);
             if (rc == PMD_OK) {
@@ -1456,6 +1466,17 @@ int pmd_autotune(const pmd_params* params, const pmd_pore* pore, int64_t n_vapor
             }
         }
         if (*best < 0) return fail(PMD_EHIP, "no candidate tuning completed its trial");
+        // among candidates within 2% of the fastest, take the largest skin
+        // (then the longest period): early rebuilds become more frequent as a
+        // run goes on, and a larger skin keeps them rare
+        if (us_per_step) {
+            for (int32_t c = 0; c < n_candidates; ++c) {
+                if (!(us_per_step[c] <= 1.02 * best_us)) continue;
+                const pmd_tuning& a = candidates[c];
+                const pmd_tuning& b = candidates[*best];
+                if (a.skin > b.skin || (a.skin == b.skin && a.rebin_every > b.rebin_every)) *best = c;
+            }
+        }
         return PMD_OK;
     } catch (const std::bad_alloc&) {
         return fail(PMD_ENOMEM, "host allocation failed");
@@ -1511,6 +1532,27 @@ int pmd_kernel_time(pmd_system* sys, int64_t* launches, double* mean_ms)
         }
         if (launches) *launches = n;
         if (mean_ms) *mean_ms = n ? tot / n : 0.0;
+        return PMD_OK;
+    } catch (...) {
+        return fail(PMD_EHIP, "unexpected exception");
+    }
+}
+
+int pmd_kernel_times(pmd_system* sys, double* out_ms, int64_t cap, int64_t* n_out)
+{
+    try {
+        CHK(check_free(sys));
+        if (!n_out || (cap > 0 && !out_ms)) return fail(PMD_EINVAL, "NULL argument");
+        Pool& p = *sys->pool;
+        HIPCHK(hipStreamSynchronize(p.stream));
+        int64_t n = 0;
+        for (auto& e : p.events) {
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, e.first, e.second) != hipSuccess) continue;
+            if (n < cap) out_ms[n] = ms;
+            ++n;
+        }
+        *n_out = n;
         return PMD_OK;
     } catch (...) {
         return fail(PMD_EHIP, "unexpected exception");

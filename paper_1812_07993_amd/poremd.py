@@ -88,6 +88,7 @@ _SIGS = {
     "pmd_destroy": (ctypes.c_int, [_vp]),
     "pmd_timing_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
     "pmd_kernel_time": (ctypes.c_int, [_vp, _P(_i64), _P(_d)]),
+    "pmd_kernel_times": (ctypes.c_int, [_vp, _vp, _i64, _P(_i64)]),
     "pmd_debug_cells": (ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _vp, _vp, _vp]),
     "pmd_debug_pairs": (ctypes.c_int, [_vp, _vp, _i64, _P(_i64), _vp, _P(_i64)]),
     "pmd_debug_lists": (ctypes.c_int, [_vp, _P(_i64), _P(_i64)]),
@@ -336,6 +337,14 @@ def pmd_kernel_time(h):
     n, ms = ctypes.c_int64(), ctypes.c_double()
     _check(load().pmd_kernel_time(h, ctypes.byref(n), ctypes.byref(ms)))
     return n.value, ms.value
+
+
+def pmd_kernel_times(h):
+    n = ctypes.c_int64()
+    _check(load().pmd_kernel_times(h, None, 0, ctypes.byref(n)))
+    out = np.zeros(n.value, dtype=np.float64)
+    _check(load().pmd_kernel_times(h, _ptr(out), n.value, ctypes.byref(n)))
+    return out
 
 
 def pmd_debug_cells(h):

@@ -93,7 +93,10 @@ def test_autotune_picks_a_runnable_candidate():
     # skin 6 leaves fewer than 3 cells per axis of a 24-sigma box: not runnable
     assert np.isinf(us[3])
     assert np.all(np.isfinite(us[:3])) and np.all(us[:3] > 0)
-    assert best == int(np.argmin(us))
+    # the fastest, or the largest skin within 2% of it
+    ok = np.flatnonzero(us <= 1.02 * us.min())
+    assert best in ok
+    assert cands[best].skin == max(cands[i].skin for i in ok)
     # the caller's arrays are untouched and a system made with the winner runs
     s = poremd.System.from_desc(desc, precision="mixed", tuning=cands[best])
     s.step(20)
