@@ -214,9 +214,9 @@ int pmd_set_state(pmd_system *sys, const double *pos, const double *vel,
  * us_per_step [n_candidates] (may be NULL) receives each candidate's
  * microseconds per step (infinity for a candidate that cannot run, e.g. a
  * skin leaving fewer than 3 cells per axis); *best the index of the fastest,
- * or, when us_per_step is given, of the candidate with the largest skin
- * (then longest period) within 2% of the fastest, since early rebuilds grow
- * more frequent as a run goes on.  Fails if none runs.  pmd_autotune_grid writes the built-in candidate grid (skin x
+ * or, when us_per_step is given, of the fastest candidate with the largest
+ * skin among those within 2% of the fastest, since early rebuilds grow more
+ * frequent as a run goes on.  Fails if none runs.  pmd_autotune_grid writes the built-in candidate grid (skin x
  * rebuild period, other knobs at their defaults) into out[cap]; with
  * out == NULL it only reports the count in *n_out. */
 int pmd_autotune_grid(const pmd_params *params, int64_t n_vapor, pmd_tuning *out,

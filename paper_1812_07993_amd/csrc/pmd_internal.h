@@ -80,6 +80,7 @@ struct SysState {
     int max_nbr;      // longest neighbour list at the last rebuild
     int rebins;       // rebuilds so far
     int steps_since;  // steps since the last rebuild
+    int stop;         // first step of the current replay that raised a stop bit (INT_MAX: none)
     long long step;   // completed steps
 };
 
@@ -111,6 +112,7 @@ struct PoolDev {
     int brick_order;      // 1: contiguous runs of bricks per XCD, 2: round-robin over XCDs
     int vt, wt;           // vapour and wall slot capacity
     int cap;              // neighbour-list capacity per atom
+    int nbt;              // brick capacity (stride of the two energy-partial slots)
     // per-atom state, double buffered by SysState::sbuf; SoA with stride vt
     double* X[2];
     double* V[2];
@@ -138,7 +140,7 @@ struct PoolDev {
     int* wid;             // canonical wall index of each sorted wall slot
     int* wcstart;         // wall cell_start (global wall slots)
     // energies
-    double* partial;      // 3 doubles per workgroup
+    double* partial;      // 3 doubles per brick, two slots (step parity)
     EnergyRec* erec;
 };
 
@@ -160,10 +162,11 @@ hipError_t launch_wall_generate(const PoreDev& pore, const double* L, double* ou
 hipError_t launch_wall_bin(const PoolDev& P, int sys, const double* raw_soa, int raw_stride,
                            int nw, int precision, hipStream_t s);
 hipError_t launch_rebuild(const PoolDev& P, int nslots, int precision, hipStream_t s);
-hipError_t launch_set_run(const PoolDev& P, int slot, int add_steps, int phase_init, hipStream_t s);
+hipError_t launch_set_run(const PoolDev& P, int slot, int add_steps, hipStream_t s);
 hipError_t launch_reset_state(const PoolDev& P, int slot, long long step, hipStream_t s);
-hipError_t launch_step(const PoolDev& P, int nslots, int precision, hipStream_t s, hipEvent_t ev0,
+hipError_t launch_step(const PoolDev& P, int kk, int precision, hipStream_t s, hipEvent_t ev0,
                        hipEvent_t ev1);
+hipError_t launch_commit(const PoolDev& P, int nslots, int R, hipStream_t s);
 hipError_t launch_unpermute(const PoolDev& P, int slot, int which, double* out_aos,
                             int n, hipStream_t s);
 hipError_t launch_wall_unpermute(const PoolDev& P, int slot, double* out_aos, int n,

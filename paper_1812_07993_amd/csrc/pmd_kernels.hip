@@ -805,14 +805,14 @@ __global__ void __launch_bounds__(256) k_list_build(PoolDev P)
             const int w0 = wcs[cl], w1 = wcs[cl + 1];
             if (w0 >= w1) continue;
             const T sx = (T)(-dx * sp.h[0]), sy = (T)(-dy * sp.h[1]), sz = (T)(-dz * sp.h[2]);
-            // four candidates per round, loads issued together (indices
+            // eight candidates per round, loads issued together (indices
             // clamped to the cell's last wall)
-            for (int w = w0; w < w1; w += 4) {
-                V o[4];
+            for (int w = w0; w < w1; w += 8) {
+                V o[8];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) o[u] = Lw[min(w + u, w1 - 1)];
+                for (int u = 0; u < 8; ++u) o[u] = Lw[min(w + u, w1 - 1)];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < 8; ++u) {
                     const T ex = me.x - o[u].x + sx, ey = me.y - o[u].y + sy, ez = me.z - o[u].z + sz;
                     if (w + u < w1 && ex * ex + ey * ey + ez * ez < rw2) {
                         if (nv + nw < cap)
@@ -865,6 +865,56 @@ hipError_t launch_rebuild(const PoolDev& P, int nslots, int precision, hipStream
 // Step: forces (F1) + second half-kick (F3) [+ next drift and half-kick (F2)]
 // ---------------------------------------------------------------------------
 
+// Whether the energies of step kstep are recorded: the initial evaluation,
+// the last step of a run and every energy_every-th step.
+__device__ __forceinline__ bool step_records(const SysParams& sp, bool init, bool last, long long kstep)
+{
+    return init || last || (sp.energy_every > 0 && (kstep % sp.energy_every) == 0);
+}
+
+// Sum one step's per-brick energy partials in brick order (fixed, so the
+// total is deterministic) and append the record.  Called by a whole
+// workgroup; the partials were written by an earlier launch.
+__device__ void record_energies(const PoolDev& P, const SysParams& sp, int s, int ring, long long kstep)
+{
+    __shared__ double red[3][4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
+    const double* pp = P.partial + 3 * ((size_t)ring * P.nbt + sp.pboff);
+    double a = 0.0, b = 0.0, cc = 0.0;
+    for (int q = tid; q < sp.nbrick; q += blockDim.x) {
+        a += pp[3 * q];
+        b += pp[3 * q + 1];
+        cc += pp[3 * q + 2];
+    }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    cc = wave_sum(cc);
+    if (lane == 0) {
+        red[0][wave] = a;
+        red[1][wave] = b;
+        red[2][wave] = cc;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        a = b = cc = 0.0;
+        for (int w = 0; w < nwave; ++w) {
+            a += red[0][w];
+            b += red[1][w];
+            cc += red[2][w];
+        }
+        SysState* sw = P.st + s;
+        const int n = sw->nrec;
+        EnergyRec r;
+        r.step = kstep;
+        r.ke = a;
+        r.pe_vv = b;
+        r.pe_vw = cc;
+        P.erec[sp.ering_off + (n % sp.ering_cap)] = r;
+        sw->nrec = n + 1;
+    }
+    __syncthreads();
+}
+
 constexpr int kGroup = 6;  // list entries fetched together in the step kernel
 
 
@@ -877,7 +927,7 @@ template <>
 __device__ __forceinline__ double inv_of<double>(double r2) { return 1.0 / r2; }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_step(PoolDev P)
+__global__ void __launch_bounds__(256) k_step(PoolDev P, int kk)
 {
     using V = typename V4<T>::type;
     extern __shared__ __align__(32) unsigned char smem[];
@@ -886,20 +936,29 @@ __global__ void __launch_bounds__(256) k_step(PoolDev P)
     __shared__ int lds_scan[17];
 
     BrickCtx c;
-    if (!brick_ctx(P, c, ST_HALT | ST_OVERFLOW | ST_NONFINITE)) return;
+    if (!brick_ctx(P, c, ST_OVERFLOW | ST_NONFINITE)) return;
     const int s = c.s;
     const SysParams& sp = P.sp[s];
     const SysState st = P.st[s];
+    // step kk of the replay runs unless the run ends earlier or an earlier
+    // step of the replay raised a stop (travel beyond skin/2, non-finite)
+    if (kk >= st.remaining || kk > st.stop) return;
     const int tid = threadIdx.x;
-    const V* Lc = (const V*)P.L[st.lbuf];
+    const bool init = st.phase == PH_INIT;
+    const bool last = !init && kk == st.remaining - 1;
+    const long long kstep = init ? st.step : st.step + kk + 1;
+    const bool doE = step_records(sp, init, last, kstep);
+    // the system's first brick records the previous step's energies
+    if (c.b == 0 && kk > 0) {
+        const long long kprev = st.step + kk;
+        if (step_records(sp, false, false, kprev)) record_energies(P, sp, s, (kk - 1) & 1, kprev);
+    }
+    const int lbuf = st.lbuf ^ (kk & 1);
+    const V* Lc = (const V*)P.L[lbuf];
     const HaloGeo g = halo_geo(sp, c.b);
     Tile<T> tl = tile_of<T>(smem, P);
     const int tot = stage_halo<T>(P, sp, g, tl, Lc, true, lds_scan);
 
-    const bool init = st.phase == PH_INIT;
-    const bool last = !init && st.remaining == 1;
-    const long long kstep = init ? st.step : st.step + 1;
-    const bool doE = init || last || (sp.energy_every > 0 && (kstep % sp.energy_every) == 0);
     const int vt = P.vt;
     const int key0 = c.b * sp.bcells;
     const int i0 = P.cstart[sp.coff + key0], i1 = P.cstart[sp.coff + key0 + sp.bcells];
@@ -1076,7 +1135,7 @@ __global__ void __launch_bounds__(256) k_step(PoolDev P)
                 X[vt + i] = y;
                 X[2 * vt + i] = z;
                 const int cx = cr & 1023, cy = (cr >> 10) & 1023, cz = cr >> 20;
-                V* Ln = (V*)P.L[st.lbuf ^ 1];
+                V* Ln = (V*)P.L[lbuf ^ 1];
                 Ln[i] = make4<T>(local_axis(x, cx, sp.h[0], sp.L[0], sp.invL[0]),
                                  local_axis(y, cy, sp.h[1], sp.L[1], sp.invL[1]),
                                  local_axis(z, cz, sp.h[2], sp.L[2], sp.invL[2]));
@@ -1106,7 +1165,10 @@ __global__ void __launch_bounds__(256) k_step(PoolDev P)
     if (tid == 0) {
         int f = 0;
         for (int w = 0; w < nwave; ++w) f |= flag_or[w];
-        if (f) atomicOr(&P.st[s].status_next, f);
+        if (f) {
+            atomicOr(&P.st[s].status_next, f);
+            if (f & (ST_HALT | ST_NONFINITE | ST_OVERFLOW)) atomicMin(&P.st[s].stop, kk);
+        }
         if (doE) {
             double a = 0.0, b = 0.0, cc = 0.0;
             for (int w = 0; w < nwave; ++w) {
@@ -1114,7 +1176,7 @@ __global__ void __launch_bounds__(256) k_step(PoolDev P)
                 b += red[1][w];
                 cc += red[2][w];
             }
-            double* pp = P.partial + 3 * (size_t)(sp.pboff + c.b);
+            double* pp = P.partial + 3 * ((size_t)(kk & 1) * P.nbt + sp.pboff + c.b);
             pp[0] = a;
             pp[1] = b;
             pp[2] = cc;
@@ -1122,76 +1184,48 @@ __global__ void __launch_bounds__(256) k_step(PoolDev P)
     }
 }
 
-// After each step launch, one workgroup per system: sum the per-brick
-// energy partials in brick order (fixed, so the total is deterministic),
-// record them, and advance the step state.  The launch boundary makes every
-// brick's partials and status bits visible without device-wide fences.
-__global__ void __launch_bounds__(256) k_finish(PoolDev P, int nslots)
+// End of a replay, one workgroup per system: count the steps the replay
+// did, record the last one's energies if due, and advance the state.
+__global__ void __launch_bounds__(256) k_commit(PoolDev P, int nslots, int R)
 {
-    __shared__ double red[3][4];
     const int s = blockIdx.x;
     if (s >= nslots) return;
     const SysParams& sp = P.sp[s];
     const SysState st = P.st[s];
-    if (!sp.active || st.remaining <= 0 || (st.status & (ST_HALT | ST_OVERFLOW | ST_NONFINITE)))
+    if (!sp.active || st.remaining <= 0 || (st.status & (ST_OVERFLOW | ST_NONFINITE))) {
+        if (threadIdx.x == 0 && sp.active) {
+            P.st[s].status = st.status | st.status_next;
+            P.st[s].status_next = 0;
+            P.st[s].stop = 0x7fffffff;
+        }
         return;
+    }
     const bool init = st.phase == PH_INIT;
-    const bool last = !init && st.remaining == 1;
-    const long long kstep = init ? st.step : st.step + 1;
-    const bool doE = init || last || (sp.energy_every > 0 && (kstep % sp.energy_every) == 0);
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
-    double a = 0.0, b = 0.0, cc = 0.0;
-    if (doE) {
-        const double* pp = P.partial + 3 * (size_t)sp.pboff;
-        for (int q = tid; q < sp.nbrick; q += blockDim.x) {
-            a += pp[3 * q];
-            b += pp[3 * q + 1];
-            cc += pp[3 * q + 2];
-        }
-        a = wave_sum(a);
-        b = wave_sum(b);
-        cc = wave_sum(cc);
-        if (lane == 0) {
-            red[0][wave] = a;
-            red[1][wave] = b;
-            red[2][wave] = cc;
-        }
-        __syncthreads();
-    }
-    if (tid != 0) return;
+    const int done = min(min(R, st.remaining), st.stop == 0x7fffffff ? R : st.stop + 1);
+    const int kl = done - 1;  // last step of the replay
+    const bool last = !init && kl == st.remaining - 1;
+    const long long kstep = init ? st.step : st.step + kl + 1;
+    if (step_records(sp, init, last, kstep)) record_energies(P, sp, s, kl & 1, kstep);
+    if (threadIdx.x != 0) return;
     SysState* sw = P.st + s;
-    if (doE) {
-        a = b = cc = 0.0;
-        for (int w = 0; w < nwave; ++w) {
-            a += red[0][w];
-            b += red[1][w];
-            cc += red[2][w];
-        }
-        EnergyRec r;
-        r.step = kstep;
-        r.ke = a;
-        r.pe_vv = b;
-        r.pe_vw = cc;
-        P.erec[sp.ering_off + (st.nrec % sp.ering_cap)] = r;
-        sw->nrec = st.nrec + 1;
-    }
     sw->status = st.status | st.status_next;
     sw->status_next = 0;
+    sw->stop = 0x7fffffff;
     if (init) {
         sw->phase = PH_REST;
         sw->remaining = 0;
-    } else {
-        sw->step = kstep;
-        sw->remaining = st.remaining - 1;
-        sw->steps_since = st.steps_since + 1;
-        if (last)
-            sw->phase = PH_REST;
-        else
-            sw->lbuf = st.lbuf ^ 1;
+        return;
     }
+    sw->step = st.step + done;
+    sw->remaining = st.remaining - done;
+    sw->steps_since = st.steps_since + done;
+    // every step but the run's last one moved the positions into the other
+    // local-coordinate buffer
+    sw->lbuf = st.lbuf ^ ((done - (last ? 1 : 0)) & 1);
+    if (last) sw->phase = PH_REST;
 }
 
-hipError_t launch_step(const PoolDev& P, int nslots, int precision, hipStream_t s, hipEvent_t ev0,
+hipError_t launch_step(const PoolDev& P, int kk, int precision, hipStream_t s, hipEvent_t ev0,
                        hipEvent_t ev1)
 {
     const int G = ((P.nbrick + 7) / 8) * 8;
@@ -1200,16 +1234,21 @@ hipError_t launch_step(const PoolDev& P, int nslots, int precision, hipStream_t 
     const size_t lds = tile_bytes(P, precision);
     if (ev0 && ev1) {
         if (precision == 1)
-            hipExtLaunchKernelGGL(k_step<float>, dim3(G), dim3(B), lds, s, ev0, ev1, 0, P);
+            hipExtLaunchKernelGGL(k_step<float>, dim3(G), dim3(B), lds, s, ev0, ev1, 0, P, kk);
         else
-            hipExtLaunchKernelGGL(k_step<double>, dim3(G), dim3(B), lds, s, ev0, ev1, 0, P);
+            hipExtLaunchKernelGGL(k_step<double>, dim3(G), dim3(B), lds, s, ev0, ev1, 0, P, kk);
     } else {
         if (precision == 1)
-            hipLaunchKernelGGL(k_step<float>, dim3(G), dim3(B), lds, s, P);
+            hipLaunchKernelGGL(k_step<float>, dim3(G), dim3(B), lds, s, P, kk);
         else
-            hipLaunchKernelGGL(k_step<double>, dim3(G), dim3(B), lds, s, P);
+            hipLaunchKernelGGL(k_step<double>, dim3(G), dim3(B), lds, s, P, kk);
     }
-    hipLaunchKernelGGL(k_finish, dim3(nslots), dim3(256), 0, s, P, nslots);
+    return hipGetLastError();
+}
+
+hipError_t launch_commit(const PoolDev& P, int nslots, int R, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_commit, dim3(nslots), dim3(256), 0, s, P, nslots, R);
     return hipGetLastError();
 }
 
@@ -1217,20 +1256,14 @@ hipError_t launch_step(const PoolDev& P, int nslots, int precision, hipStream_t 
 // Host-requested state changes and readbacks
 // ---------------------------------------------------------------------------
 
-__global__ void k_set_run(PoolDev P, int slot, int add_steps, int phase_init)
+__global__ void k_set_run(PoolDev P, int slot, int add_steps)
 {
-    SysState* st = P.st + slot;
-    if (phase_init) {
-        st->phase = PH_INIT;
-        st->remaining = 1;
-    } else {
-        st->remaining += add_steps;
-    }
+    P.st[slot].remaining += add_steps;
 }
 
-hipError_t launch_set_run(const PoolDev& P, int slot, int add_steps, int phase_init, hipStream_t s)
+hipError_t launch_set_run(const PoolDev& P, int slot, int add_steps, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_set_run, dim3(1), dim3(1), 0, s, P, slot, add_steps, phase_init);
+    hipLaunchKernelGGL(k_set_run, dim3(1), dim3(1), 0, s, P, slot, add_steps);
     return hipGetLastError();
 }
 
@@ -1246,6 +1279,7 @@ __global__ void k_reset_state(PoolDev P, int slot, long long step)
     st->nrec = 0;
     st->max_nbr = 0;
     st->steps_since = 0;
+    st->stop = 0x7fffffff;
     st->step = step;
 }
 

@@ -316,6 +316,7 @@ struct Pool {
         d.vt = vt;
         d.wt = wt;
         d.cap = cap;
+        d.nbt = nbt;
         for (int b = 0; b < 2; ++b) {
             d.X[b] = X[b];
             d.V[b] = V[b];
@@ -357,7 +358,7 @@ size_t pool_bytes(int precision, int vt, int wt, int ct, int wct, int nbt, int n
     s += 3 * (size_t)ct * 4 + 3 * (size_t)std::max(vt, wt) * 4;
     s += (size_t)vt * cap * 4 + (size_t)vt * 4;            // lists
     s += 3 * (size_t)wt * 8 + (size_t)wt * 4 + (size_t)wct * 4;
-    s += 3 * (size_t)nbt * 8 + (size_t)nslots * erings * sizeof(EnergyRec);
+    s += 6 * (size_t)nbt * 8 + (size_t)nslots * erings * sizeof(EnergyRec);
     s += 3 * (size_t)std::max(vt, wt) * 8 + (size_t)nslots * (sizeof(SysParams) + sizeof(SysState));
     return s;
 }
@@ -406,7 +407,7 @@ int pool_allocate(Pool& p)
     CHK(p.alloc(&p.wid, wt));
     CHK(p.alloc(&p.wcstart, std::max(p.wct, 1)));
     HIPCHK(hipMemset(p.wcstart, 0, sizeof(int) * (size_t)std::max(p.wct, 1)));
-    CHK(p.alloc(&p.partial, 3 * (size_t)std::max(p.nbt, 1)));
+    CHK(p.alloc(&p.partial, 6 * (size_t)std::max(p.nbt, 1)));
     CHK(p.alloc(&p.erec, (size_t)p.nslots * p.ering_cap));
     CHK(p.alloc(&p.stage, 3 * (size_t)sc));
     CHK(p.alloc(&p.dbg, 16));
@@ -616,7 +617,8 @@ int pool_capture(Pool& p, int R, int reps)
     HIPCHK(hipStreamBeginCapture(p.cap_stream, hipStreamCaptureModeThreadLocal));
     for (int r = 0; r < reps; ++r) {
         launch_rebuild(d, p.nslots, p.precision, p.cap_stream);
-        for (int k = 0; k < R; ++k) launch_step(d, p.nslots, p.precision, p.cap_stream, nullptr, nullptr);
+        for (int k = 0; k < R; ++k) launch_step(d, k, p.precision, p.cap_stream, nullptr, nullptr);
+        launch_commit(d, p.nslots, R, p.cap_stream);
     }
     hipGraph_t g = nullptr;
     HIPCHK(hipStreamEndCapture(p.cap_stream, &g));
@@ -651,11 +653,12 @@ int pool_enqueue(Pool& p, int R, int use_graph, int64_t replays)
                 HIPCHK(hipEventCreateWithFlags(&a, hipEventDisableSystemFence));
                 HIPCHK(hipEventCreateWithFlags(&b, hipEventDisableSystemFence));
                 p.events.emplace_back(a, b);
-                HIPCHK(launch_step(d, p.nslots, p.precision, p.stream, a, b));
+                HIPCHK(launch_step(d, k, p.precision, p.stream, a, b));
             } else {
-                HIPCHK(launch_step(d, p.nslots, p.precision, p.stream, nullptr, nullptr));
+                HIPCHK(launch_step(d, k, p.precision, p.stream, nullptr, nullptr));
             }
         }
+        HIPCHK(launch_commit(d, p.nslots, R, p.stream));
     }
     return PMD_OK;
 }
@@ -756,7 +759,8 @@ int load_state(pmd_system* sys, const double* pos, const double* vel, int64_t st
     HIPCHK(e);
     for (int attempt = 0; attempt < 8; ++attempt) {
         HIPCHK(launch_rebuild(q.dev(), q.nslots, q.precision, q.stream));
-        HIPCHK(launch_step(q.dev(), q.nslots, q.precision, q.stream, nullptr, nullptr));
+        HIPCHK(launch_step(q.dev(), 0, q.precision, q.stream, nullptr, nullptr));
+        HIPCHK(launch_commit(q.dev(), q.nslots, 1, q.stream));
         SysState st;
         CHK(read_state(q, slot, &st));
         if (st.status & ST_NONFINITE) return fail(PMD_ENUMERIC, "non-finite initial forces");
@@ -1168,7 +1172,7 @@ int pmd_step(pmd_system* sys, int64_t nsteps)
         if (nsteps < 0 || nsteps > (int64_t)1 << 30) return fail(PMD_EINVAL, "nsteps out of range");
         if (nsteps == 0) return PMD_OK;
         Pool& p = *sys->pool;
-        HIPCHK(launch_set_run(p.dev(), sys->slot, (int)nsteps, 0, p.stream));
+        HIPCHK(launch_set_run(p.dev(), sys->slot, (int)nsteps, p.stream));
         const int R = sys->tuning.rebin_every;
         CHK(pool_enqueue(p, R, sys->tuning.use_graph, (nsteps + R - 1) / R));
         return PMD_OK;
@@ -1467,14 +1471,14 @@ int pmd_autotune(const pmd_params* params, const pmd_pore* pore, int64_t n_vapor
         }
         if (*best < 0) return fail(PMD_EHIP, "no candidate tuning completed its trial");
         // among candidates within 2% of the fastest, take the largest skin
-        // (then the longest period): early rebuilds become more frequent as a
+        // (the fastest of those): early rebuilds become more frequent as a
         // run goes on, and a larger skin keeps them rare
         if (us_per_step) {
             for (int32_t c = 0; c < n_candidates; ++c) {
                 if (!(us_per_step[c] <= 1.02 * best_us)) continue;
                 const pmd_tuning& a = candidates[c];
                 const pmd_tuning& b = candidates[*best];
-                if (a.skin > b.skin || (a.skin == b.skin && a.rebin_every > b.rebin_every)) *best = c;
+                if (a.skin > b.skin || (a.skin == b.skin && us_per_step[c] < us_per_step[*best])) *best = c;
             }
         }
         return PMD_OK;
@@ -1748,7 +1752,7 @@ int pmd_batch_admit(pmd_batch* b, pmd_system* sys, int64_t nsteps, int* slot)
         sys->pool = &p;
         sys->slot = free_slot;
         sys->batch = b;
-        if (nsteps > 0) HIPCHK(launch_set_run(p.dev(), free_slot, (int)nsteps, 0, p.stream));
+        if (nsteps > 0) HIPCHK(launch_set_run(p.dev(), free_slot, (int)nsteps, p.stream));
         *slot = free_slot;
         return PMD_OK;
     } catch (const std::bad_alloc&) {
