@@ -126,16 +126,14 @@ def run_path(poremd, desc, prec, steps, warmup, energy_every, tuning_kw):
 
 
 def kernel_time(poremd, s, steps):
-    """Mean duration of the step kernel over the launches that did a step
-    (launches shorter than 30% of the 90th percentile are the ones that
-    returned at once: the rest of a replay after an early-rebuild halt)."""
+    """Mean duration of one step-kernel launch, from HIP events around the R
+    back-to-back launches of each replay that did R full steps."""
     poremd.pmd_timing_enable(s.h, True)
     s.step(steps)
     s.sync()
-    t = poremd.pmd_kernel_times(s.h)
+    n, mean_ms = poremd.pmd_kernel_time(s.h)
     poremd.pmd_timing_enable(s.h, False)
-    full = t[t >= 0.3 * np.percentile(t, 90)]
-    return len(full), float(full.mean())
+    return n, mean_ms
 
 
 def cpu_baseline(desc, sample_atoms, seed=0):

@@ -232,15 +232,19 @@ int pmd_destroy(pmd_system *sys);
 
 /* ---- Kernel timing, for measurement ------------------------------------ */
 
-/* When enabled, every launch of the force-and-integrate kernel is bracketed
- * by HIP events recorded on the launch stream; pmd_kernel_time returns the
- * number of launches timed and their mean duration in milliseconds. */
+/* When enabled, the system's steps are queued without graph capture and the
+ * R back-to-back launches of the force-and-integrate kernel in each replay
+ * (R = rebin_every) are bracketed by one pair of HIP events on the system's
+ * stream; the host waits after each replay to read how many steps it did.
+ * Only replays whose R launches all did a full step are used (a replay cut
+ * short by an early rebuild also holds launches that return at once).
+ * pmd_kernel_time returns the number of launches in those replays and the
+ * mean duration of one launch in milliseconds; pmd_kernel_times writes one
+ * value per such replay (its mean launch duration, oldest first, at most
+ * cap values) and the number of such replays in *n_out.  Enabling or
+ * disabling clears earlier timings. */
 int pmd_timing_enable(pmd_system *sys, int enable);
 int pmd_kernel_time(pmd_system *sys, int64_t *launches, double *mean_ms);
-/* The duration of every timed launch, oldest first, in milliseconds; at most
- * cap values are written, *n_out receives the number timed.  Launches that
- * return at once (the steps of a replay after an early-rebuild halt) are
- * included; callers separate them by duration. */
 int pmd_kernel_times(pmd_system *sys, double *out_ms, int64_t cap, int64_t *n_out);
 
 /* ---- Test-only debug exports (same library; unstable) ------------------- */

@@ -261,7 +261,15 @@ struct Pool {
     int g_R = 0, g_reps = 0;
     bool dirty = true;
     bool timing = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+    // timing mode: one event pair around the R step launches of each replay,
+    // with the steps that replay did (a replay cut short by an early rebuild
+    // also holds launches that returned at once)
+    struct TimedReplay {
+        hipEvent_t a, b;
+        int R;
+        int done;
+    };
+    std::vector<TimedReplay> events;
     std::vector<void*> allocs;
 
     ~Pool() { release(); }
@@ -272,8 +280,8 @@ struct Pool {
         if (gexec) hipGraphExecDestroy(gexec);
         gexec = nullptr;
         for (auto& e : events) {
-            hipEventDestroy(e.first);
-            hipEventDestroy(e.second);
+            hipEventDestroy(e.a);
+            hipEventDestroy(e.b);
         }
         events.clear();
         for (void* p : allocs) hipFree(p);
@@ -631,6 +639,13 @@ int pool_capture(Pool& p, int R, int reps)
     return PMD_OK;
 }
 
+int read_state(Pool& p, int slot, SysState* out)
+{
+    HIPCHK(hipMemcpyAsync(out, p.d_st + slot, sizeof(SysState), hipMemcpyDeviceToHost, p.stream));
+    HIPCHK(hipStreamSynchronize(p.stream));
+    return PMD_OK;
+}
+
 // Queue `replays` repetitions of [rebuild, R steps].
 int pool_enqueue(Pool& p, int R, int use_graph, int64_t replays)
 {
@@ -645,30 +660,33 @@ int pool_enqueue(Pool& p, int R, int use_graph, int64_t replays)
     }
     for (int64_t r = 0; r < replays; ++r) {
         HIPCHK(launch_rebuild(d, p.nslots, p.precision, p.stream));
-        for (int k = 0; k < R; ++k) {
-            if (p.timing) {
-                hipEvent_t a, b;
-                // no system-scope fence on the timing events: the kernel's
-                // duration is wanted, not that of a cache flush behind it
-                HIPCHK(hipEventCreateWithFlags(&a, hipEventDisableSystemFence));
-                HIPCHK(hipEventCreateWithFlags(&b, hipEventDisableSystemFence));
-                p.events.emplace_back(a, b);
-                HIPCHK(launch_step(d, k, p.precision, p.stream, a, b));
-            } else {
-                HIPCHK(launch_step(d, k, p.precision, p.stream, nullptr, nullptr));
-            }
+        Pool::TimedReplay t{nullptr, nullptr, R, 0};
+        long long before = 0;
+        if (p.timing) {
+            // the timed pool holds one system (slot 0); the step count before
+            // and after the replay gives the steps it did
+            SysState st;
+            CHK(read_state(p, 0, &st));
+            before = st.step;
+            // no system-scope fence on the timing events: the kernels'
+            // duration is wanted, not that of a cache flush behind them
+            HIPCHK(hipEventCreateWithFlags(&t.a, hipEventDisableSystemFence));
+            HIPCHK(hipEventCreateWithFlags(&t.b, hipEventDisableSystemFence));
+            HIPCHK(hipEventRecord(t.a, p.stream));
         }
+        for (int k = 0; k < R; ++k) HIPCHK(launch_step(d, k, p.precision, p.stream, nullptr, nullptr));
+        if (p.timing) HIPCHK(hipEventRecord(t.b, p.stream));
         HIPCHK(launch_commit(d, p.nslots, R, p.stream));
+        if (p.timing) {
+            SysState st;
+            CHK(read_state(p, 0, &st));
+            t.done = (int)(st.step - before);
+            p.events.push_back(t);
+        }
     }
     return PMD_OK;
 }
 
-int read_state(Pool& p, int slot, SysState* out)
-{
-    HIPCHK(hipMemcpyAsync(out, p.d_st + slot, sizeof(SysState), hipMemcpyDeviceToHost, p.stream));
-    HIPCHK(hipStreamSynchronize(p.stream));
-    return PMD_OK;
-}
 
 }  // namespace
 
@@ -1508,8 +1526,8 @@ int pmd_timing_enable(pmd_system* sys, int enable)
         Pool& p = *sys->pool;
         HIPCHK(hipStreamSynchronize(p.stream));
         for (auto& e : p.events) {
-            hipEventDestroy(e.first);
-            hipEventDestroy(e.second);
+            hipEventDestroy(e.a);
+            hipEventDestroy(e.b);
         }
         p.events.clear();
         p.timing = enable != 0;
@@ -1529,10 +1547,9 @@ int pmd_kernel_time(pmd_system* sys, int64_t* launches, double* mean_ms)
         int64_t n = 0;
         for (auto& e : p.events) {
             float ms = 0.0f;
-            if (hipEventElapsedTime(&ms, e.first, e.second) == hipSuccess) {
-                tot += ms;
-                ++n;
-            }
+            if (e.done != e.R || hipEventElapsedTime(&ms, e.a, e.b) != hipSuccess) continue;
+            tot += ms;
+            n += e.R;
         }
         if (launches) *launches = n;
         if (mean_ms) *mean_ms = n ? tot / n : 0.0;
@@ -1552,8 +1569,8 @@ int pmd_kernel_times(pmd_system* sys, double* out_ms, int64_t cap, int64_t* n_ou
         int64_t n = 0;
         for (auto& e : p.events) {
             float ms = 0.0f;
-            if (hipEventElapsedTime(&ms, e.first, e.second) != hipSuccess) continue;
-            if (n < cap) out_ms[n] = ms;
+            if (e.done != e.R || hipEventElapsedTime(&ms, e.a, e.b) != hipSuccess) continue;
+            if (n < cap) out_ms[n] = ms / e.R;
             ++n;
         }
         *n_out = n;

@@ -102,3 +102,25 @@ def test_autotune_picks_a_runnable_candidate():
     s.step(20)
     assert s.step_count() == 20
     s.close()
+
+
+def test_kernel_timing_mode():
+    """Timing mode times whole replays of R back-to-back step launches and
+    leaves the trajectory unchanged (same kernels, no graph)."""
+    desc = _desc()
+    tun = poremd.make_tuning(rebin_every=5, skin=0.8)
+    a = poremd.System.from_desc(desc, tuning=tun)
+    b = poremd.System.from_desc(desc, tuning=tun)
+    poremd.pmd_timing_enable(a.h, True)
+    a.step(20)
+    b.step(20)
+    n, ms = poremd.pmd_kernel_time(a.h)
+    t = poremd.pmd_kernel_times(a.h)
+    assert n % 5 == 0 and n == 5 * len(t) and n > 0
+    assert ms > 0 and np.isclose(ms, t.mean(), rtol=1e-9)
+    poremd.pmd_timing_enable(a.h, False)
+    assert poremd.pmd_kernel_time(a.h) == (0, 0.0)
+    assert a.step_count() == b.step_count() == 20
+    assert np.array_equal(a.positions(), b.positions())
+    a.close()
+    b.close()
