@@ -236,13 +236,14 @@ int pmd_destroy(pmd_system *sys);
  * R back-to-back launches of the force-and-integrate kernel in each replay
  * (R = rebin_every) are bracketed by one pair of HIP events on the system's
  * stream; the host waits after each replay to read how many steps it did.
- * Only replays whose R launches all did a full step are used (a replay cut
- * short by an early rebuild also holds launches that return at once).
- * pmd_kernel_time returns the number of launches in those replays and the
- * mean duration of one launch in milliseconds; pmd_kernel_times writes one
- * value per such replay (its mean launch duration, oldest first, at most
- * cap values) and the number of such replays in *n_out.  Enabling or
- * disabling clears earlier timings. */
+ * A replay cut short by an early rebuild also holds launches that return at
+ * once; their duration is measured when timing is enabled (32 back-to-back
+ * launches on the system at rest; the system must have no queued steps) and
+ * subtracted.  pmd_kernel_time returns the number of launches that did a
+ * step and the mean duration of one in milliseconds; pmd_kernel_times writes
+ * one value per replay that did a step (its mean launch duration, oldest
+ * first, at most cap values) and the number of such replays in *n_out.
+ * Enabling or disabling clears earlier timings. */
 int pmd_timing_enable(pmd_system *sys, int enable);
 int pmd_kernel_time(pmd_system *sys, int64_t *launches, double *mean_ms);
 int pmd_kernel_times(pmd_system *sys, double *out_ms, int64_t cap, int64_t *n_out);

@@ -74,8 +74,11 @@ struct SysState {
     int status;       // Status bits seen by the current launch
     int status_next;  // bits raised during the current launch (merged at its end)
     int lbuf;         // current local-coordinate buffer (0/1)
-    int sbuf;         // current state buffer (0/1)
-    int sbuf_prev;    // state buffer before the last rebuild
+    int sbuf;         // buffer holding the latest positions and velocities (0/1);
+                      // every step reads one and writes the other
+    int sbuf_prev;    // that buffer before the last rebuild (the placement's source)
+    int ibuf;         // buffer holding the caller ids in the current storage order
+    int ibuf_prev;    // that buffer before the last rebuild
     int nrec;         // energy records written
     int max_nbr;      // longest neighbour list at the last rebuild
     int rebins;       // rebuilds so far

@@ -499,6 +499,8 @@ __global__ void k_bin_scan_finish(PoolDev P, int nslots)
     }
     st->sbuf_prev = st->sbuf;
     st->sbuf ^= 1;
+    st->ibuf_prev = st->ibuf;
+    st->ibuf ^= 1;
     st->status &= ~(ST_HALT | ST_OVERFLOW | ST_TILE);
     if (st->phase == PH_REST) st->phase = PH_RUN;
     st->rebins += 1;
@@ -528,7 +530,7 @@ __global__ void k_bin_place(PoolDev P)
     const int o = P.tmp[c.i];
     const int cell = P.cell_tmp[o];
     const int b0 = cell_begin(P, sp, cell), b1 = cell_begin(P, sp, cell + 1);
-    const int* ids = P.id[src];
+    const int* ids = P.id[st.ibuf_prev];
     const int myid = ids[o];
     int rank = 0;
     for (int q = b0; q < b1; ++q) rank += (ids[P.tmp[q]] < myid);
@@ -544,7 +546,7 @@ __global__ void k_bin_place(PoolDev P)
     Vd[d] = Vs[o];
     Vd[vt + d] = Vs[vt + o];
     Vd[2 * vt + d] = Vs[2 * vt + o];
-    P.id[dst][d] = myid;
+    P.id[st.ibuf][d] = myid;
     P.travel[d] = 0.0f;
     V* Lc = (V*)P.L[st.lbuf];
     if (cell < sp.nkey) {
@@ -640,6 +642,12 @@ template <typename T>
 __device__ __forceinline__ Tile<T> tile_of(unsigned char* smem, const PoolDev& P)
 {
     return tile_at<T>(smem, 0, P.lds_atoms, P.hmax);
+}
+
+template <typename T>
+__device__ __forceinline__ size_t tile_bytes_of(const PoolDev& P)
+{
+    return tile_size<T>(P.lds_atoms, P.hmax);
 }
 
 // Stage the halo box of brick g into LDS.  Returns the number of staged
@@ -745,10 +753,23 @@ __global__ void __launch_bounds__(256) k_list_build(PoolDev P)
     const V* Lc = (const V*)P.L[st.lbuf];
     const HaloGeo g = halo_geo(sp, c.b);
     Tile<T> t = tile_of<T>(smem, P);
+    // wall slot range of every halo cell, next to the staged tile, so the
+    // wall search reads its cell ranges from LDS
+    int* wrange = (int*)(smem + tile_bytes_of<T>(P));
+    {
+        const int* wcs = P.wcstart + sp.wcoff;
+        for (int h = threadIdx.x; h < g.H; h += blockDim.x) {
+            const int hx = h % g.hd[0], hy = (h / g.hd[0]) % g.hd[1], hz = h / (g.hd[0] * g.hd[1]);
+            const int cl = wrap_cell(g.start[0] - 1 + hx, sp.nc[0]) +
+                           sp.nc[0] * (wrap_cell(g.start[1] - 1 + hy, sp.nc[1]) +
+                                       sp.nc[1] * wrap_cell(g.start[2] - 1 + hz, sp.nc[2]));
+            wrange[2 * h] = wcs[cl];
+            wrange[2 * h + 1] = wcs[cl + 1];
+        }
+    }
     const int tot = stage_halo<T>(P, sp, g, t, Lc, true, lds_scan);
     const int key0 = c.b * sp.bcells;
     const int i0 = P.cstart[sp.coff + key0], i1 = P.cstart[sp.coff + key0 + sp.bcells];
-    const int* wcs = P.wcstart + sp.wcoff;
     const V* Lw = Lc + vt;
     if (tot < 0) {
         for (int i = i0 + (int)threadIdx.x; i < i1; i += blockDim.x) P.nlist[i] = 0;
@@ -800,9 +821,8 @@ __global__ void __launch_bounds__(256) k_list_build(PoolDev P)
             const double gx = box_gap(lx, dx, sp.h[0]), gy = box_gap(ly, dy, sp.h[1]),
                          gz = box_gap(lz, dz, sp.h[2]);
             if (gx * gx + gy * gy + gz * gz >= cull_w) continue;
-            const int cl = wrap_cell(cx + dx, sp.nc[0]) +
-                           sp.nc[0] * (wrap_cell(cy + dy, sp.nc[1]) + sp.nc[1] * wrap_cell(cz + dz, sp.nc[2]));
-            const int w0 = wcs[cl], w1 = wcs[cl + 1];
+            const int h = halo_cell(g, cx, cy, cz, q);
+            const int w0 = wrange[2 * h], w1 = wrange[2 * h + 1];
             if (w0 >= w1) continue;
             const T sx = (T)(-dx * sp.h[0]), sy = (T)(-dy * sp.h[1]), sz = (T)(-dz * sp.h[2]);
             // eight candidates per round, loads issued together (indices
@@ -846,7 +866,7 @@ hipError_t launch_rebuild(const PoolDev& P, int nslots, int precision, hipStream
     const int G = ((nrb + 7) / 8) * 8;
     const int GB = ((P.nbrick + 7) / 8) * 8;
     if (G == 0) return hipSuccess;
-    const size_t lds = tile_bytes(P, precision);
+    const size_t lds = tile_bytes(P, precision) + 8 * (size_t)P.hmax;  // tile + wall ranges
     hipLaunchKernelGGL(k_bin_count, dim3(G), dim3(kRebuildBlock), 0, s, P);
     hipLaunchKernelGGL(k_bin_scan, dim3(P.ntile), dim3(1024), 0, s, P);
     hipLaunchKernelGGL(k_bin_scan_finish, dim3(nslots), dim3(64), 0, s, P, nslots);
@@ -965,8 +985,14 @@ __global__ void __launch_bounds__(256) k_step(PoolDev P, int kk)
 
     double ke = 0.0, evv = 0.0, evw = 0.0;
     int flags = tot < 0 ? (ST_OVERFLOW | ST_TILE) : 0;
-    double* X = P.X[st.sbuf];
-    double* Vv = P.V[st.sbuf];
+    // positions and velocities: read from one buffer, written to the other,
+    // so every workgroup (the cutoff-edge re-test reads partners' positions)
+    // sees the positions at the start of the step
+    const int xb = init ? st.sbuf : st.sbuf ^ (kk & 1);
+    const double* X = P.X[xb];
+    const double* Vv = P.V[xb];
+    double* Xn = P.X[xb ^ 1];
+    double* Vn = P.V[xb ^ 1];
     const T rc2 = (T)sp.rc2;
     const T Av = (T)sp.A, Bv = (T)sp.B, Aw = (T)sp.Aw, Bw = (T)sp.Bw;
     const T A12v = (T)12 * Av, B6v = (T)6 * Bv, A12w = (T)12 * Aw, B6w = (T)6 * Bw;
@@ -1114,9 +1140,12 @@ __global__ void __launch_bounds__(256) k_step(PoolDev P, int kk)
         ke += kei;
         if (!init) {
             if (last) {
-                Vv[i] = vx;
-                Vv[vt + i] = vy;
-                Vv[2 * vt + i] = vz;
+                Xn[i] = xi;
+                Xn[vt + i] = yi;
+                Xn[2 * vt + i] = zi;
+                Vn[i] = vx;
+                Vn[vt + i] = vy;
+                Vn[2 * vt + i] = vz;
                 P.A[i] = ax;
                 P.A[vt + i] = ay;
                 P.A[2 * vt + i] = az;
@@ -1128,12 +1157,12 @@ __global__ void __launch_bounds__(256) k_step(PoolDev P, int kk)
                 const double x = wrap_box(xi + vx * sp.dt, sp.L[0]);
                 const double y = wrap_box(yi + vy * sp.dt, sp.L[1]);
                 const double z = wrap_box(zi + vz * sp.dt, sp.L[2]);
-                Vv[i] = vx;
-                Vv[vt + i] = vy;
-                Vv[2 * vt + i] = vz;
-                X[i] = x;
-                X[vt + i] = y;
-                X[2 * vt + i] = z;
+                Vn[i] = vx;
+                Vn[vt + i] = vy;
+                Vn[2 * vt + i] = vz;
+                Xn[i] = x;
+                Xn[vt + i] = y;
+                Xn[2 * vt + i] = z;
                 const int cx = cr & 1023, cy = (cr >> 10) & 1023, cz = cr >> 20;
                 V* Ln = (V*)P.L[lbuf ^ 1];
                 Ln[i] = make4<T>(local_axis(x, cx, sp.h[0], sp.L[0], sp.invL[0]),
@@ -1222,6 +1251,8 @@ __global__ void __launch_bounds__(256) k_commit(PoolDev P, int nslots, int R)
     // every step but the run's last one moved the positions into the other
     // local-coordinate buffer
     sw->lbuf = st.lbuf ^ ((done - (last ? 1 : 0)) & 1);
+    // every step wrote its positions and velocities into the other buffer
+    sw->sbuf = st.sbuf ^ (done & 1);
     if (last) sw->phase = PH_REST;
 }
 
@@ -1298,7 +1329,7 @@ __global__ void k_unpermute(PoolDev P, int slot, int which, double* out, int n)
     if (p >= sp.nv || p >= n) return;
     const int i = sp.voff + p;
     const int vt = P.vt;
-    const int id = P.id[st.sbuf][i];
+    const int id = P.id[st.ibuf][i];
     if (id < 0 || id >= n) return;
     const double* src = which == 0 ? P.X[st.sbuf] : which == 1 ? P.V[st.sbuf] : P.A;
     const double m = which == 2 ? sp.mass : 1.0;
@@ -1353,7 +1384,7 @@ __global__ void k_debug_pairs(PoolDev P, int slot, int* out, int cap, int* count
     if (tot < 0) return;
     const int vt = P.vt;
     const double* X = P.X[st.sbuf];
-    const int* ids = P.id[st.sbuf];
+    const int* ids = P.id[st.ibuf];
     const int key0 = b * sp.bcells;
     const int i0 = P.cstart[sp.coff + key0], i1 = P.cstart[sp.coff + key0 + sp.bcells];
     for (int i = i0 + (int)threadIdx.x; i < i1; i += blockDim.x) {
@@ -1437,7 +1468,7 @@ __global__ void k_copy_in(PoolDev P, int slot, const double* pos, const double* 
         Vv[i] = Vv[vt + i] = Vv[2 * vt + i] = 0.0;
     }
     P.A[i] = P.A[vt + i] = P.A[2 * vt + i] = 0.0;
-    P.id[st.sbuf][i] = p;
+    P.id[st.ibuf][i] = p;
     P.travel[i] = 0.0f;
 }
 

@@ -261,6 +261,7 @@ struct Pool {
     int g_R = 0, g_reps = 0;
     bool dirty = true;
     bool timing = false;
+    double t_exit_ms = 0.0;  // duration of a step launch whose workgroups all return at once
     // timing mode: one event pair around the R step launches of each replay,
     // with the steps that replay did (a replay cut short by an early rebuild
     // also holds launches that returned at once)
@@ -831,7 +832,7 @@ int move_system(Pool& src, int sslot, Pool& dst, int dslot)
             HIPCHK(hipMemcpy(dst.WX + (size_t)k * dst.wt + b.woff, src.WX + (size_t)k * src.wt + a.woff,
                              (size_t)a.nw * 8, hipMemcpyDeviceToDevice));
     }
-    HIPCHK(hipMemcpy(dst.id[0] + b.voff, src.id[sb] + a.voff, nv * 4, hipMemcpyDeviceToDevice));
+    HIPCHK(hipMemcpy(dst.id[0] + b.voff, src.id[st.ibuf] + a.voff, nv * 4, hipMemcpyDeviceToDevice));
     HIPCHK(hipMemcpy(dst.travel + b.voff, src.travel + a.voff, nv * 4, hipMemcpyDeviceToDevice));
     HIPCHK(hipMemcpy(dst.cref + b.voff, src.cref + a.voff, nv * 4, hipMemcpyDeviceToDevice));
     HIPCHK(hipMemcpy(dst.cell_lin + b.voff, src.cell_lin + a.voff, nv * 4, hipMemcpyDeviceToDevice));
@@ -868,6 +869,8 @@ int move_system(Pool& src, int sslot, Pool& dst, int dslot)
     SysState nst = st;
     nst.sbuf = 0;
     nst.sbuf_prev = 0;
+    nst.ibuf = 0;
+    nst.ibuf_prev = 0;
     nst.status_next = 0;
     HIPCHK(hipMemcpy(dst.d_st + dslot, &nst, sizeof(SysState), hipMemcpyHostToDevice));
     return PMD_OK;
@@ -1531,6 +1534,31 @@ int pmd_timing_enable(pmd_system* sys, int enable)
         }
         p.events.clear();
         p.timing = enable != 0;
+        p.t_exit_ms = 0.0;
+        if (p.timing) {
+            // duration of a launch whose workgroups all return at once (the
+            // launches after an early-rebuild halt): 32 back-to-back launches
+            // on the system at rest
+            SysState st;
+            CHK(read_state(p, sys->slot, &st));
+            if (st.remaining != 0) return fail(PMD_ESTATE, "system has queued steps");
+            hipEvent_t a, b;
+            HIPCHK(hipEventCreateWithFlags(&a, hipEventDisableSystemFence));
+            HIPCHK(hipEventCreateWithFlags(&b, hipEventDisableSystemFence));
+            const PoolDev d = p.dev();
+            hipError_t e = launch_step(d, 0, p.precision, p.stream, nullptr, nullptr);  // warm
+            if (e == hipSuccess) e = hipEventRecord(a, p.stream);
+            for (int k = 0; k < 32 && e == hipSuccess; ++k)
+                e = launch_step(d, 0, p.precision, p.stream, nullptr, nullptr);
+            if (e == hipSuccess) e = hipEventRecord(b, p.stream);
+            if (e == hipSuccess) e = hipEventSynchronize(b);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+            hipEventDestroy(a);
+            hipEventDestroy(b);
+            HIPCHK(e);
+            p.t_exit_ms = ms / 32.0;
+        }
         return PMD_OK;
     } catch (...) {
         return fail(PMD_EHIP, "unexpected exception");
@@ -1547,9 +1575,9 @@ int pmd_kernel_time(pmd_system* sys, int64_t* launches, double* mean_ms)
         int64_t n = 0;
         for (auto& e : p.events) {
             float ms = 0.0f;
-            if (e.done != e.R || hipEventElapsedTime(&ms, e.a, e.b) != hipSuccess) continue;
-            tot += ms;
-            n += e.R;
+            if (e.done <= 0 || hipEventElapsedTime(&ms, e.a, e.b) != hipSuccess) continue;
+            tot += ms - (e.R - e.done) * p.t_exit_ms;
+            n += e.done;
         }
         if (launches) *launches = n;
         if (mean_ms) *mean_ms = n ? tot / n : 0.0;
@@ -1569,8 +1597,8 @@ int pmd_kernel_times(pmd_system* sys, double* out_ms, int64_t cap, int64_t* n_ou
         int64_t n = 0;
         for (auto& e : p.events) {
             float ms = 0.0f;
-            if (e.done != e.R || hipEventElapsedTime(&ms, e.a, e.b) != hipSuccess) continue;
-            if (n < cap) out_ms[n] = ms / e.R;
+            if (e.done <= 0 || hipEventElapsedTime(&ms, e.a, e.b) != hipSuccess) continue;
+            if (n < cap) out_ms[n] = (ms - (e.R - e.done) * p.t_exit_ms) / e.done;
             ++n;
         }
         *n_out = n;
@@ -1597,7 +1625,7 @@ int pmd_debug_cells(pmd_system* sys, int32_t* cell_of_atom, int64_t n, int32_t* 
         SysState st;
         CHK(read_state(p, sys->slot, &st));
         std::vector<int> ids(sp.vcap), cl(sp.vcap), cs(sp.nkey + 2);
-        HIPCHK(hipMemcpy(ids.data(), p.id[st.sbuf] + sp.voff, sizeof(int) * sp.vcap, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(ids.data(), p.id[st.ibuf] + sp.voff, sizeof(int) * sp.vcap, hipMemcpyDeviceToHost));
         HIPCHK(hipMemcpy(cl.data(), p.cell_lin + sp.voff, sizeof(int) * sp.vcap, hipMemcpyDeviceToHost));
         HIPCHK(hipMemcpy(cs.data(), p.cstart + sp.coff, sizeof(int) * (sp.nkey + 2), hipMemcpyDeviceToHost));
         // first storage position of each cell (cells are stored brick by brick)

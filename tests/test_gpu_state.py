@@ -116,8 +116,8 @@ def test_kernel_timing_mode():
     b.step(20)
     n, ms = poremd.pmd_kernel_time(a.h)
     t = poremd.pmd_kernel_times(a.h)
-    assert n % 5 == 0 and n == 5 * len(t) and n > 0
-    assert ms > 0 and np.isclose(ms, t.mean(), rtol=1e-9)
+    assert 0 < len(t) <= n <= 20 and np.all(t > 0)
+    assert ms > 0 and t.min() * (1 - 1e-9) <= ms <= t.max() * (1 + 1e-9)
     poremd.pmd_timing_enable(a.h, False)
     assert poremd.pmd_kernel_time(a.h) == (0, 0.0)
     assert a.step_count() == b.step_count() == 20

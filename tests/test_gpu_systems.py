@@ -152,3 +152,21 @@ def test_batch_admission_by_budget():
     poremd.pmd_batch_destroy(b)
     for h in (h0, h1, h3):
         h.close()
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_runs_are_reproducible(prec):
+    """The same inputs give bit-identical trajectories: no floating-point
+    atomics, fixed summation orders, and every workgroup reads the positions
+    as of the start of the step (cutoff-edge re-tests read partners' master
+    positions while other workgroups write the next ones)."""
+    for d in _small_systems(prec):
+        runs = []
+        for _ in range(2):
+            s = poremd.System.from_desc(d, tuning=poremd.make_tuning(rebin_every=9))
+            s.step(150)
+            runs.append((s.positions(), s.velocities(), s.energies()["etotal"]))
+            s.close()
+        assert np.array_equal(runs[0][0], runs[1][0])
+        assert np.array_equal(runs[0][1], runs[1][1])
+        assert runs[0][2] == runs[1][2]
