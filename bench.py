@@ -292,6 +292,8 @@ def main():
                     help="pores of the 4M-atom leg, comma separated (cylinder,cone,inkbottle); "
                          "'none' skips it")
     ap.add_argument("--sweep-steps", type=int, default=500)
+    ap.add_argument("--sweep-only", action="store_true",
+                    help="run only the 4M-atom pore leg (for profiling it)")
     ap.add_argument("--serve-chunk", type=int, default=250)
     ap.add_argument("--timing-steps", type=int, default=500)
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -313,6 +315,14 @@ def main():
 
     poremd.load()
     assert torch.cuda.is_available(), "needs a GPU"
+    if args.sweep_only:
+        tkw = dict(skin=args.skin, rebin_every=args.rebin_every, block=args.block,
+                   brick_atoms=args.brick_atoms, brick_order=args.brick_order)
+        out = {"pore_sweep": pore_sweep_leg(poremd, args.sweep.split(","), args.sweep_steps,
+                                            0 if (args.skin or args.rebin_every)
+                                            else min(args.autotune_steps, 50), tkw)}
+        print(json.dumps(out), flush=True)
+        return
     if args.copy_mib > 0:
         # an elementwise kernel (not a DMA copy) that reads and writes exactly
         # copy_mib MiB each
