@@ -288,7 +288,7 @@ def main():
     ap.add_argument("--batch-systems", type=int, default=256,
                     help="replica systems of the batched leg (0 = skip it)")
     ap.add_argument("--batch-steps", type=int, default=1000)
-    ap.add_argument("--sweep", default="cylinder",
+    ap.add_argument("--sweep", default="cylinder,cone,inkbottle",
                     help="pores of the 4M-atom leg, comma separated (cylinder,cone,inkbottle); "
                          "'none' skips it")
     ap.add_argument("--sweep-steps", type=int, default=500)

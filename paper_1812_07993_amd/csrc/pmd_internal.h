@@ -80,7 +80,7 @@ struct SysState {
     int ibuf;         // buffer holding the caller ids in the current storage order
     int ibuf_prev;    // that buffer before the last rebuild
     int nrec;         // energy records written
-    int max_nbr;      // longest vapour or wall list at the last rebuild
+    int max_nbr;      // longest neighbour list at the last rebuild
     int rebins;       // rebuilds so far
     int steps_since;  // steps since the last rebuild
     int stop;         // first step of the current replay that raised a stop bit (INT_MAX: none)
@@ -133,13 +133,10 @@ struct PoolDev {
     int* arr;             // arrival rank within the cell (per slot)
     int* tmp;             // slots in arrival order
     int* cell_tmp;        // cell key of each old slot
-    // neighbour lists, entry k of slot i at k * vt + i (row k holds every
-    // atom's k-th entry): vapour entries are 16-bit indices into the brick's
-    // staged tile (the staged atom carries its halo cell, which gives the
-    // periodic shift); wall entries are wall slots with the neighbour cell's
-    // offset as 2 bits per axis above kIndexBits.  nlist = n_vapour | n_wall << 16
-    unsigned short* vlist;
-    unsigned* wlist;
+    // neighbour lists, entry k of slot i at k * vt + i: vapour entries index
+    // the brick's staged tile, wall entries are wall slots; both carry the
+    // cell-offset code above kIndexBits.  nlist = n_vapour | n_wall << 16
+    unsigned* list;
     int* nlist;
     // walls
     double* WX;           // sorted wall positions, SoA stride wt

@@ -47,15 +47,6 @@ __device__ __forceinline__ unsigned offset_code(int q)
     return (unsigned)(q % 3) | ((unsigned)((q / 3) % 3) << 2) | ((unsigned)(q / 9) << 4);
 }
 
-// A staged atom carries its halo cell (hx | hy << 8 | hz << 16, each below
-// 256) in the unused fourth component of its LDS copy; the difference of two
-// halo cells along an axis is the neighbour cell offset, and so the shift.
-template <typename T> __device__ __forceinline__ T pack_halo(int h);
-template <> __device__ __forceinline__ float pack_halo<float>(int h) { return __int_as_float(h); }
-template <> __device__ __forceinline__ double pack_halo<double>(int h) { return __longlong_as_double((long long)h); }
-__device__ __forceinline__ int halo_bits(float w) { return __float_as_int(w); }
-__device__ __forceinline__ int halo_bits(double w) { return (int)__double_as_longlong(w); }
-
 // Shift -d h that moves the neighbour's cell-local coordinate into the frame
 // of the atom's cell along one axis (exactly h, 0 or -h).
 template <typename T>
@@ -702,36 +693,21 @@ __device__ int stage_halo(const PoolDev& P, const SysParams& sp, const HaloGeo& 
     for (int a = threadIdx.x; a < tot; a += T_) {
         const int h = t.slot[a];
         t.slot[a] = t.hbeg[h] + (a - t.hoff[h]);
-        if (with_pos) {
-            const int hx = h % g.hd[0], hy = (h / g.hd[0]) % g.hd[1], hz = h / (g.hd[0] * g.hd[1]);
-            t.pos[a].w = pack_halo<T>(hx | (hy << 8) | (hz << 16));
-        }
     }
     __syncthreads();
     if (with_pos) {
         // each thread issues 4 independent loads (indices clamped to a valid
-        // staged atom) before storing the ones in range; the fourth
-        // component keeps the halo cell written above
+        // staged atom) before storing the ones in range
         for (int a0 = threadIdx.x; a0 < tot; a0 += 4 * T_) {
             const int a1 = a0 + T_, a2 = a0 + 2 * T_, a3 = a0 + 3 * T_;
-            typename V4<T>::type v0 = Lc[t.slot[a0]];
-            typename V4<T>::type v1 = Lc[t.slot[min(a1, tot - 1)]];
-            typename V4<T>::type v2 = Lc[t.slot[min(a2, tot - 1)]];
-            typename V4<T>::type v3 = Lc[t.slot[min(a3, tot - 1)]];
-            v0.w = t.pos[a0].w;
+            const typename V4<T>::type v0 = Lc[t.slot[a0]];
+            const typename V4<T>::type v1 = Lc[t.slot[min(a1, tot - 1)]];
+            const typename V4<T>::type v2 = Lc[t.slot[min(a2, tot - 1)]];
+            const typename V4<T>::type v3 = Lc[t.slot[min(a3, tot - 1)]];
             t.pos[a0] = v0;
-            if (a1 < tot) {
-                v1.w = t.pos[a1].w;
-                t.pos[a1] = v1;
-            }
-            if (a2 < tot) {
-                v2.w = t.pos[a2].w;
-                t.pos[a2] = v2;
-            }
-            if (a3 < tot) {
-                v3.w = t.pos[a3].w;
-                t.pos[a3] = v3;
-            }
+            if (a1 < tot) t.pos[a1] = v1;
+            if (a2 < tot) t.pos[a2] = v2;
+            if (a3 < tot) t.pos[a3] = v3;
         }
     }
     __syncthreads();
@@ -832,7 +808,8 @@ __global__ void __launch_bounds__(256) k_list_build(PoolDev P)
                 for (int u = 0; u < 4; ++u) {
                     const T ex = me.x - o[u].x + sx, ey = me.y - o[u].y + sy, ez = me.z - o[u].z + sz;
                     if (a + u < a1 && ex * ex + ey * ey + ez * ez < rl2 && sl[u] != i) {
-                        if (nv < cap) P.vlist[(size_t)nv * vt + i] = (unsigned short)(a + u);
+                        if (nv < cap)
+                            P.list[(size_t)nv * vt + i] = (unsigned)(a + u) | (offset_code(q) << kIndexBits);
                         ++nv;
                     }
                 }
@@ -858,16 +835,17 @@ __global__ void __launch_bounds__(256) k_list_build(PoolDev P)
                 for (int u = 0; u < 8; ++u) {
                     const T ex = me.x - o[u].x + sx, ey = me.y - o[u].y + sy, ez = me.z - o[u].z + sz;
                     if (w + u < w1 && ex * ex + ey * ey + ez * ez < rw2) {
-                        if (nw < cap)
-                            P.wlist[(size_t)nw * vt + i] = (unsigned)(w + u) | (offset_code(q) << kIndexBits);
+                        if (nv + nw < cap)
+                            P.list[(size_t)(nv + nw) * vt + i] =
+                                (unsigned)(w + u) | (offset_code(q) << kIndexBits);
                         ++nw;
                     }
                 }
             }
         }
-        const bool ok = nv <= cap && nw <= cap;
+        const bool ok = nv + nw <= cap;
         P.nlist[i] = ok ? (nv | (nw << 16)) : 0;
-        mx = max(mx, max(nv, nw));
+        mx = max(mx, nv + nw);
     }
     mx = wave_max(mx);
     if ((threadIdx.x & 63) == 0 && mx > 0) {
@@ -1023,7 +1001,10 @@ __global__ void __launch_bounds__(256) k_step(PoolDev P, int kk)
     const T hx = (T)sp.h[0], hy = (T)sp.h[1], hz = (T)sp.h[2];
     for (int i = i0 + tid; tot >= 0 && i < i1; i += blockDim.x) {
         const V me = Lc[i];
+        const double xi = X[i], yi = X[vt + i], zi = X[2 * vt + i];
+        const double vx0 = Vv[i], vy0 = Vv[vt + i], vz0 = Vv[2 * vt + i];
         const int cr = P.cref[i];
+        const float tr0 = P.travel[i];
         const int nl = P.nlist[i];
         const int nvap = nl & 0xFFFF, nall = nvap + (nl >> 16);
         double fx = 0.0, fy = 0.0, fz = 0.0, eav = 0.0, eaw = 0.0;
@@ -1044,99 +1025,83 @@ __global__ void __launch_bounds__(256) k_step(PoolDev P, int kk)
                     eav += u_;
             }
         };
-        const unsigned short* vl = P.vlist + i;
-        const unsigned* wl = P.wlist + i;
-        const int nwall = nall - nvap;
-        // halo cell of this atom (the staged partners carry theirs)
-        const int hix = (cr & 1023) - g.start[0] + 1;
-        const int hiy = ((cr >> 10) & 1023) - g.start[1] + 1;
-        const int hiz = (cr >> 20) - g.start[2] + 1;
+        const unsigned* lst = P.list + i;
         // entries come kGroup at a time, the next group's loads in flight while
         // the current one is evaluated; vapour partners are read from LDS,
-        // wall partners from global memory.  Pairs whose FP32 r^2 lies within
-        // a narrow band around the cutoff are left out here and decided in
-        // FP64 after the whole list (a rare slow path: a few atoms per step),
-        // so the per-pair code has no branch.  Every load is unconditional,
-        // with indices clamped to valid memory (list rows past the end of this
-        // atom's list exist up to the capacity; their values are not used), so
-        // the code is straight-line and each wait covers only the loads it needs
+        // the group's wall partners are fetched together
+        // pairs whose FP32 r^2 lies within a narrow band around the cutoff
+        // are left out here and decided in FP64 after the whole list (a rare
+        // slow path: a few atoms per step), so the per-pair code has no branch
         bool edge = false;
+        // every load below is unconditional, with indices clamped to valid
+        // memory (list rows past the end of this atom's list exist up to the
+        // capacity; their values are not used), so the code is straight-line
+        // and each wait covers only the loads it needs
         const int lastrow = P.cap - 1;
-        {
-            unsigned ec[kGroup];
+        unsigned ec[kGroup];
+        // vapour partners (the first nvap entries), positions from LDS
 #pragma unroll
-            for (int u = 0; u < kGroup; ++u) ec[u] = vl[(size_t)min(u, lastrow) * vt];
-            for (int k0 = 0; k0 < nvap; k0 += kGroup) {
-                unsigned en[kGroup];
+        for (int u = 0; u < kGroup; ++u) ec[u] = lst[(size_t)min(u, lastrow) * vt];
+        for (int k0 = 0; k0 < nvap; k0 += kGroup) {
+            unsigned en[kGroup];
 #pragma unroll
-                for (int u = 0; u < kGroup; ++u) en[u] = vl[(size_t)min(k0 + kGroup + u, lastrow) * vt];
+            for (int u = 0; u < kGroup; ++u)
+                en[u] = lst[(size_t)min(k0 + kGroup + u, lastrow) * vt];
 #pragma unroll
-                for (int u = 0; u < kGroup; ++u) {
-                    const bool live = k0 + u < nvap;
-                    const V o = tl.pos[live ? (int)ec[u] : 0];
-                    const int hj = halo_bits(o.w);
-                    const T dx = fma((T)(hix - (hj & 255)), hx, me.x - o.x);
-                    const T dy = fma((T)(hiy - ((hj >> 8) & 255)), hy, me.y - o.y);
-                    const T dz = fma((T)(hiz - (hj >> 16)), hz, me.z - o.z);
-                    const T r2 = dx * dx + dy * dy + dz * dz;
-                    const bool near = live && sizeof(T) == 4 && fabs(r2 - rc2) < band;
-                    edge |= near;
-                    if (live && r2 < rc2 && !near) pair(dx, dy, dz, r2, false);
-                }
-#pragma unroll
-                for (int u = 0; u < kGroup; ++u) ec[u] = en[u];
+            for (int u = 0; u < kGroup; ++u) {
+                const bool live = k0 + u < nvap;
+                const unsigned e = ec[u];
+                const V o = tl.pos[live ? (int)(e & kIndexMask) : 0];
+                const T dx = me.x - o.x + shift_of<T>(e, 0, hx);
+                const T dy = me.y - o.y + shift_of<T>(e, 2, hy);
+                const T dz = me.z - o.z + shift_of<T>(e, 4, hz);
+                const T r2 = dx * dx + dy * dy + dz * dz;
+                const bool near = live && sizeof(T) == 4 && fabs(r2 - rc2) < band;
+                edge |= near;
+                if (live && r2 < rc2 && !near) pair(dx, dy, dz, r2, false);
             }
+#pragma unroll
+            for (int u = 0; u < kGroup; ++u) ec[u] = en[u];
         }
-        if (nwall > 0) {
-            unsigned ec[kGroup];
+        // wall partners (entries nvap .. nall), positions from global memory
+        if (nall > nvap) {
 #pragma unroll
-            for (int u = 0; u < kGroup; ++u) ec[u] = wl[(size_t)min(u, lastrow) * vt];
-            for (int k0 = 0; k0 < nwall; k0 += kGroup) {
-                V ow[kGroup];
+            for (int u = 0; u < kGroup; ++u) ec[u] = lst[(size_t)min(nvap + u, lastrow) * vt];
+        }
+        for (int k0 = nvap; k0 < nall; k0 += kGroup) {
+            V ow[kGroup];
 #pragma unroll
-                for (int u = 0; u < kGroup; ++u)
-                    ow[u] = Lc[vt + (k0 + u < nwall ? (int)(ec[u] & kIndexMask) : 0)];
-                unsigned en[kGroup];
+            for (int u = 0; u < kGroup; ++u)
+                ow[u] = Lc[vt + (k0 + u < nall ? (int)(ec[u] & kIndexMask) : 0)];
+            unsigned en[kGroup];
 #pragma unroll
-                for (int u = 0; u < kGroup; ++u) en[u] = wl[(size_t)min(k0 + kGroup + u, lastrow) * vt];
+            for (int u = 0; u < kGroup; ++u)
+                en[u] = lst[(size_t)min(k0 + kGroup + u, lastrow) * vt];
 #pragma unroll
-                for (int u = 0; u < kGroup; ++u) {
-                    const bool live = k0 + u < nwall;
-                    const unsigned e = ec[u];
-                    const V o = ow[u];
-                    const T dx = me.x - o.x + shift_of<T>(e, 0, hx);
-                    const T dy = me.y - o.y + shift_of<T>(e, 2, hy);
-                    const T dz = me.z - o.z + shift_of<T>(e, 4, hz);
-                    const T r2 = dx * dx + dy * dy + dz * dz;
-                    const bool near = live && sizeof(T) == 4 && fabs(r2 - rc2) < band;
-                    edge |= near;
-                    if (live && r2 < rc2 && !near) pair(dx, dy, dz, r2, true);
-                }
-#pragma unroll
-                for (int u = 0; u < kGroup; ++u) ec[u] = en[u];
+            for (int u = 0; u < kGroup; ++u) {
+                const bool live = k0 + u < nall;
+                const unsigned e = ec[u];
+                const V o = ow[u];
+                const T dx = me.x - o.x + shift_of<T>(e, 0, hx);
+                const T dy = me.y - o.y + shift_of<T>(e, 2, hy);
+                const T dz = me.z - o.z + shift_of<T>(e, 4, hz);
+                const T r2 = dx * dx + dy * dy + dz * dz;
+                const bool near = live && sizeof(T) == 4 && fabs(r2 - rc2) < band;
+                edge |= near;
+                if (live && r2 < rc2 && !near) pair(dx, dy, dz, r2, true);
             }
+#pragma unroll
+            for (int u = 0; u < kGroup; ++u) ec[u] = en[u];
         }
         if (edge) {
-            const double xi = X[i], yi = X[vt + i], zi = X[2 * vt + i];
             for (int k = 0; k < nall; ++k) {
+                const unsigned e = lst[(size_t)k * vt];
                 const bool wall = k >= nvap;
-                T dx, dy, dz;
-                int a;
-                if (wall) {
-                    const unsigned e = wl[(size_t)(k - nvap) * vt];
-                    a = (int)(e & kIndexMask);
-                    const V o = Lc[vt + a];
-                    dx = me.x - o.x + shift_of<T>(e, 0, hx);
-                    dy = me.y - o.y + shift_of<T>(e, 2, hy);
-                    dz = me.z - o.z + shift_of<T>(e, 4, hz);
-                } else {
-                    a = (int)vl[(size_t)k * vt];
-                    const V o = tl.pos[a];
-                    const int hj = halo_bits(o.w);
-                    dx = fma((T)(hix - (hj & 255)), hx, me.x - o.x);
-                    dy = fma((T)(hiy - ((hj >> 8) & 255)), hy, me.y - o.y);
-                    dz = fma((T)(hiz - (hj >> 16)), hz, me.z - o.z);
-                }
+                const int a = (int)(e & kIndexMask);
+                const V o = wall ? Lc[vt + a] : tl.pos[a];
+                const T dx = me.x - o.x + shift_of<T>(e, 0, hx);
+                const T dy = me.y - o.y + shift_of<T>(e, 2, hy);
+                const T dz = me.z - o.z + shift_of<T>(e, 4, hz);
                 const T r2 = dx * dx + dy * dy + dz * dz;
                 if (!(fabs(r2 - rc2) < band)) continue;
                 double ox, oy, oz;
@@ -1159,11 +1124,6 @@ __global__ void __launch_bounds__(256) k_step(PoolDev P, int kk)
         }
         evv += 0.5 * eav;
         evw += eaw;
-        // the atom's own state, read after the pair loops so that it does not
-        // hold registers through them
-        const double xi = X[i], yi = X[vt + i], zi = X[2 * vt + i];
-        const double vx0 = Vv[i], vy0 = Vv[vt + i], vz0 = Vv[2 * vt + i];
-        const float tr0 = P.travel[i];
         const double ax = fx * sp.inv_mass, ay = fy * sp.inv_mass, az = fz * sp.inv_mass;
         double vx = vx0, vy = vy0, vz = vz0;
         if (init) {
@@ -1432,8 +1392,8 @@ __global__ void k_debug_pairs(PoolDev P, int slot, int* out, int cap, int* count
         const int nvap = nl & 0xFFFF, n = nvap + (nl >> 16);
         const double xi = X[i], yi = X[vt + i], zi = X[2 * vt + i];
         for (int k = 0; k < n; ++k) {
-            const int a = k < nvap ? (int)P.vlist[(size_t)k * vt + i]
-                                   : (int)(P.wlist[(size_t)(k - nvap) * vt + i] & kIndexMask);
+            const unsigned e = P.list[(size_t)k * vt + i];
+            const int a = (int)(e & kIndexMask);
             double ox, oy, oz;
             int kind, bb;
             if (k >= nvap) {

@@ -52,10 +52,6 @@ int fail(int code, const char* fmt, ...)
 
 int round_up(int a, int b) { return ((a + b - 1) / b) * b; }
 
-// Bytes per neighbour-list slot: a 16-bit vapour entry and a 32-bit wall
-// entry (each list holds up to `cap` entries per atom).
-constexpr size_t kListEntryBytes = 6;
-
 // Workgroup order of the brick kernels: 1 = each XCD takes a contiguous run
 // of bricks (spatial neighbours share an L2), 2 = bricks dealt round-robin
 // over the XCDs (a dense region of the box is spread over all of them).
@@ -347,9 +343,7 @@ struct Pool {
         d.arr = arr;
         d.tmp = tmp;
         d.cell_tmp = cell_tmp;
-        // one allocation: 16-bit vapour entries, then 32-bit wall entries
-        d.vlist = (unsigned short*)list;
-        d.wlist = (unsigned*)((unsigned short*)list + (size_t)vt * cap);
+        d.list = list;
         d.nlist = nlist;
         d.WX = WX;
         d.wid = wid;
@@ -371,7 +365,7 @@ size_t pool_bytes(int precision, int vt, int wt, int ct, int wct, int nbt, int n
     s += 2 * (size_t)vt * 4 + 3 * (size_t)vt * 4;          // id x2, travel, cref, cell_lin
     s += 2 * (size_t)(vt + wt) * lsize(precision);         // local coordinates x2
     s += 3 * (size_t)ct * 4 + 3 * (size_t)std::max(vt, wt) * 4;
-    s += (size_t)vt * cap * kListEntryBytes + (size_t)vt * 4;  // lists
+    s += (size_t)vt * cap * 4 + (size_t)vt * 4;            // lists
     s += 3 * (size_t)wt * 8 + (size_t)wt * 4 + (size_t)wct * 4;
     s += 6 * (size_t)nbt * 8 + (size_t)nslots * erings * sizeof(EnergyRec);
     s += 3 * (size_t)std::max(vt, wt) * 8 + (size_t)nslots * (sizeof(SysParams) + sizeof(SysState));
@@ -416,7 +410,7 @@ int pool_allocate(Pool& p)
     CHK(p.alloc(&p.arr, sc));
     CHK(p.alloc(&p.tmp, sc));
     CHK(p.alloc(&p.cell_tmp, sc));
-    CHK(p.alloc(&p.list, (size_t)vt * p.cap * kListEntryBytes / 4));
+    CHK(p.alloc(&p.list, (size_t)vt * p.cap));
     CHK(p.alloc(&p.nlist, vt));
     CHK(p.alloc(&p.WX, 3 * (size_t)wt));
     CHK(p.alloc(&p.wid, wt));
@@ -445,23 +439,22 @@ int pool_grow_lists(Pool& p, int new_cap)
 {
     HIPCHK(hipStreamSynchronize(p.stream));
     auto it = std::find(p.allocs.begin(), p.allocs.end(), (void*)p.list);
-    size_t old = (size_t)p.vt * p.cap * kListEntryBytes;
+    size_t old = (size_t)p.vt * p.cap * 4;
     unsigned* q = nullptr;
-    hipError_t e = hipMalloc(&q, (size_t)p.vt * new_cap * kListEntryBytes);
+    hipError_t e = hipMalloc(&q, (size_t)p.vt * new_cap * 4);
     if (e != hipSuccess) return fail(PMD_ENOMEM, "growing neighbour lists to %d failed", new_cap);
     if (it != p.allocs.end()) {
         hipFree(*it);
         *it = q;
     }
-    p.bytes = p.bytes - old + (size_t)p.vt * new_cap * kListEntryBytes;
+    p.bytes = p.bytes - old + (size_t)p.vt * new_cap * 4;
     p.list = q;
     p.cap = new_cap;
     p.dirty = true;
     return PMD_OK;
 }
 
-constexpr size_t kTileBytesMax = 60 * 1024;  // dynamic LDS of the staged halo tile (at most
-                                              // 65535 staged atoms: vapour entries are 16-bit)
+constexpr size_t kTileBytesMax = 60 * 1024;  // dynamic LDS of the staged halo tile
 
 size_t tile_atom_bytes(int precision) { return (precision == PMD_MIXED ? sizeof(f4) : sizeof(d4)) + 4; }
 
