@@ -946,238 +946,192 @@ __device__ __forceinline__ float inv_of<float>(float r2) { return __builtin_amdg
 template <>
 __device__ __forceinline__ double inv_of<double>(double r2) { return 1.0 / r2; }
 
+// Per-workgroup context of one step of one system.
 template <typename T>
-__global__ void __launch_bounds__(256) k_step(PoolDev P, int kk)
-{
+struct StepCtx {
     using V = typename V4<T>::type;
-    extern __shared__ __align__(32) unsigned char smem[];
-    __shared__ double red[3][4];
-    __shared__ int flag_or[4];
-    __shared__ int lds_scan[17];
+    bool init, last, doE;
+    int lbuf;
+    const V* Lc;           // local coordinates read this step (walls at vt + w)
+    const double* X;       // positions and velocities at the start of the step
+    const double* Vv;
+    double* Xn;            // ... and after it (the other buffer)
+    double* Vn;
+    T rc2, Av, Bv, Aw, Bw, A12v, B6v, A12w, B6w, ucv, ucw, band, hx, hy, hz;
+};
 
-    BrickCtx c;
-    if (!brick_ctx(P, c, ST_OVERFLOW | ST_NONFINITE)) return;
-    const int s = c.s;
-    const SysParams& sp = P.sp[s];
-    const SysState st = P.st[s];
-    // step kk of the replay runs unless the run ends earlier or an earlier
-    // step of the replay raised a stop (travel beyond skin/2, non-finite)
-    if (kk >= st.remaining || kk > st.stop) return;
-    const int tid = threadIdx.x;
-    const bool init = st.phase == PH_INIT;
-    const bool last = !init && kk == st.remaining - 1;
-    const long long kstep = init ? st.step : st.step + kk + 1;
-    const bool doE = step_records(sp, init, last, kstep);
-    // the system's first brick records the previous step's energies
-    if (c.b == 0 && kk > 0) {
-        const long long kprev = st.step + kk;
-        if (step_records(sp, false, false, kprev)) record_energies(P, sp, s, (kk - 1) & 1, kprev);
-    }
-    const int lbuf = st.lbuf ^ (kk & 1);
-    const V* Lc = (const V*)P.L[lbuf];
-    const HaloGeo g = halo_geo(sp, c.b);
-    Tile<T> tl = tile_of<T>(smem, P);
-    const int tot = stage_halo<T>(P, sp, g, tl, Lc, true, lds_scan);
-
-    const int vt = P.vt;
-    const int key0 = c.b * sp.bcells;
-    const int i0 = P.cstart[sp.coff + key0], i1 = P.cstart[sp.coff + key0 + sp.bcells];
-
-    double ke = 0.0, evv = 0.0, evw = 0.0;
-    int flags = tot < 0 ? (ST_OVERFLOW | ST_TILE) : 0;
+template <typename T>
+__device__ __forceinline__ StepCtx<T> step_ctx(const PoolDev& P, const SysParams& sp, const SysState& st, int kk)
+{
+    StepCtx<T> x;
+    x.init = st.phase == PH_INIT;
+    x.last = !x.init && kk == st.remaining - 1;
+    const long long kstep = x.init ? st.step : st.step + kk + 1;
+    x.doE = step_records(sp, x.init, x.last, kstep);
+    x.lbuf = st.lbuf ^ (kk & 1);
+    x.Lc = (const typename V4<T>::type*)P.L[x.lbuf];
     // positions and velocities: read from one buffer, written to the other,
     // so every workgroup (the cutoff-edge re-test reads partners' positions)
     // sees the positions at the start of the step
-    const int xb = init ? st.sbuf : st.sbuf ^ (kk & 1);
-    const double* X = P.X[xb];
-    const double* Vv = P.V[xb];
-    double* Xn = P.X[xb ^ 1];
-    double* Vn = P.V[xb ^ 1];
-    const T rc2 = (T)sp.rc2;
-    const T Av = (T)sp.A, Bv = (T)sp.B, Aw = (T)sp.Aw, Bw = (T)sp.Bw;
-    const T A12v = (T)12 * Av, B6v = (T)6 * Bv, A12w = (T)12 * Aw, B6w = (T)6 * Bw;
-    const T ucv = (T)sp.uc, ucw = (T)sp.ucw;
-    const T band = (T)(4.0e-6 * sp.rc2);
-    const T hx = (T)sp.h[0], hy = (T)sp.h[1], hz = (T)sp.h[2];
-    for (int i = i0 + tid; tot >= 0 && i < i1; i += blockDim.x) {
-        const V me = Lc[i];
-        const double xi = X[i], yi = X[vt + i], zi = X[2 * vt + i];
-        const double vx0 = Vv[i], vy0 = Vv[vt + i], vz0 = Vv[2 * vt + i];
-        const int cr = P.cref[i];
-        const float tr0 = P.travel[i];
-        const int nl = P.nlist[i];
-        const int nvap = nl & 0xFFFF, nall = nvap + (nl >> 16);
-        double fx = 0.0, fy = 0.0, fz = 0.0, eav = 0.0, eaw = 0.0;
-        // one in-cutoff pair: FP32 (mixed) or FP64 LJ, FP64 sums
-        auto pair = [&](T dx, T dy, T dz, T r2, bool wall) {
-            const T A = wall ? Aw : Av, B = wall ? Bw : Bv;
-            const T sr2 = inv_of<T>(r2);
-            const T sr6 = sr2 * sr2 * sr2;
-            const T w = sr2 * sr6 * ((wall ? A12w : A12v) * sr6 - (wall ? B6w : B6v));
-            fx += (double)(w * dx);
-            fy += (double)(w * dy);
-            fz += (double)(w * dz);
-            if (doE) {
-                const double u_ = (double)(sr6 * (A * sr6 - B) - (wall ? ucw : ucv));
-                if (wall)
-                    eaw += u_;
-                else
-                    eav += u_;
-            }
-        };
-        const unsigned* lst = P.list + i;
-        // entries come kGroup at a time, the next group's loads in flight while
-        // the current one is evaluated; vapour partners are read from LDS,
-        // the group's wall partners are fetched together
-        // pairs whose FP32 r^2 lies within a narrow band around the cutoff
-        // are left out here and decided in FP64 after the whole list (a rare
-        // slow path: a few atoms per step), so the per-pair code has no branch
-        bool edge = false;
-        // every load below is unconditional, with indices clamped to valid
-        // memory (list rows past the end of this atom's list exist up to the
-        // capacity; their values are not used), so the code is straight-line
-        // and each wait covers only the loads it needs
-        const int lastrow = P.cap - 1;
-        unsigned ec[kGroup];
-        // vapour partners (the first nvap entries), positions from LDS
-#pragma unroll
-        for (int u = 0; u < kGroup; ++u) ec[u] = lst[(size_t)min(u, lastrow) * vt];
-        for (int k0 = 0; k0 < nvap; k0 += kGroup) {
-            unsigned en[kGroup];
-#pragma unroll
-            for (int u = 0; u < kGroup; ++u)
-                en[u] = lst[(size_t)min(k0 + kGroup + u, lastrow) * vt];
-#pragma unroll
-            for (int u = 0; u < kGroup; ++u) {
-                const bool live = k0 + u < nvap;
-                const unsigned e = ec[u];
-                const V o = tl.pos[live ? (int)(e & kIndexMask) : 0];
-                const T dx = me.x - o.x + shift_of<T>(e, 0, hx);
-                const T dy = me.y - o.y + shift_of<T>(e, 2, hy);
-                const T dz = me.z - o.z + shift_of<T>(e, 4, hz);
-                const T r2 = dx * dx + dy * dy + dz * dz;
-                const bool near = live && sizeof(T) == 4 && fabs(r2 - rc2) < band;
-                edge |= near;
-                if (live && r2 < rc2 && !near) pair(dx, dy, dz, r2, false);
-            }
-#pragma unroll
-            for (int u = 0; u < kGroup; ++u) ec[u] = en[u];
+    const int xb = x.init ? st.sbuf : st.sbuf ^ (kk & 1);
+    x.X = P.X[xb];
+    x.Vv = P.V[xb];
+    x.Xn = P.X[xb ^ 1];
+    x.Vn = P.V[xb ^ 1];
+    x.rc2 = (T)sp.rc2;
+    x.Av = (T)sp.A;
+    x.Bv = (T)sp.B;
+    x.Aw = (T)sp.Aw;
+    x.Bw = (T)sp.Bw;
+    x.A12v = (T)12 * x.Av;
+    x.B6v = (T)6 * x.Bv;
+    x.A12w = (T)12 * x.Aw;
+    x.B6w = (T)6 * x.Bw;
+    x.ucv = (T)sp.uc;
+    x.ucw = (T)sp.ucw;
+    x.band = (T)(4.0e-6 * sp.rc2);
+    x.hx = (T)sp.h[0];
+    x.hy = (T)sp.h[1];
+    x.hz = (T)sp.h[2];
+    return x;
+}
+
+// Per-atom force and energy sums (FP64).
+struct Acc {
+    double fx, fy, fz, ev, ew;
+};
+
+// One in-cutoff pair: FP32 (mixed) or FP64 LJ, FP64 sums.
+template <typename T>
+__device__ __forceinline__ void pair_term(const StepCtx<T>& x, Acc& a, T dx, T dy, T dz, T r2, bool wall)
+{
+    const T A = wall ? x.Aw : x.Av, B = wall ? x.Bw : x.Bv;
+    const T sr2 = inv_of<T>(r2);
+    const T sr6 = sr2 * sr2 * sr2;
+    const T w = sr2 * sr6 * ((wall ? x.A12w : x.A12v) * sr6 - (wall ? x.B6w : x.B6v));
+    a.fx += (double)(w * dx);
+    a.fy += (double)(w * dy);
+    a.fz += (double)(w * dz);
+    if (x.doE) {
+        const double u_ = (double)(sr6 * (A * sr6 - B) - (wall ? x.ucw : x.ucv));
+        if (wall)
+            a.ew += u_;
+        else
+            a.ev += u_;
+    }
+}
+
+// The rare pass over an atom's list for pairs whose FP32 r^2 fell within the
+// band around the cutoff: decided on the FP64 master positions, in list order.
+template <typename T>
+__device__ void edge_pass(const PoolDev& P, const SysParams& sp, const StepCtx<T>& x,
+                          const Tile<T>& tl, int i, int nvap, int nall, Acc& a)
+{
+    using V = typename V4<T>::type;
+    const int vt = P.vt;
+    const V me = x.Lc[i];
+    const double xi = x.X[i], yi = x.X[vt + i], zi = x.X[2 * vt + i];
+    const unsigned* lst = P.list + i;
+    for (int k = 0; k < nall; ++k) {
+        const unsigned e = lst[(size_t)k * vt];
+        const bool wall = k >= nvap;
+        const int ai = (int)(e & kIndexMask);
+        const V o = wall ? x.Lc[vt + ai] : tl.pos[ai];
+        const T dx = me.x - o.x + shift_of<T>(e, 0, x.hx);
+        const T dy = me.y - o.y + shift_of<T>(e, 2, x.hy);
+        const T dz = me.z - o.z + shift_of<T>(e, 4, x.hz);
+        const T r2 = dx * dx + dy * dy + dz * dz;
+        if (!(fabs(r2 - x.rc2) < x.band)) continue;
+        double ox, oy, oz;
+        if (wall) {
+            ox = P.WX[ai];
+            oy = P.WX[P.wt + ai];
+            oz = P.WX[2 * P.wt + ai];
+        } else {
+            const int j = tl.slot[ai];
+            ox = x.X[j];
+            oy = x.X[vt + j];
+            oz = x.X[2 * vt + j];
         }
-        // wall partners (entries nvap .. nall), positions from global memory
-        if (nall > nvap) {
-#pragma unroll
-            for (int u = 0; u < kGroup; ++u) ec[u] = lst[(size_t)min(nvap + u, lastrow) * vt];
-        }
-        for (int k0 = nvap; k0 < nall; k0 += kGroup) {
-            V ow[kGroup];
-#pragma unroll
-            for (int u = 0; u < kGroup; ++u)
-                ow[u] = Lc[vt + (k0 + u < nall ? (int)(ec[u] & kIndexMask) : 0)];
-            unsigned en[kGroup];
-#pragma unroll
-            for (int u = 0; u < kGroup; ++u)
-                en[u] = lst[(size_t)min(k0 + kGroup + u, lastrow) * vt];
-#pragma unroll
-            for (int u = 0; u < kGroup; ++u) {
-                const bool live = k0 + u < nall;
-                const unsigned e = ec[u];
-                const V o = ow[u];
-                const T dx = me.x - o.x + shift_of<T>(e, 0, hx);
-                const T dy = me.y - o.y + shift_of<T>(e, 2, hy);
-                const T dz = me.z - o.z + shift_of<T>(e, 4, hz);
-                const T r2 = dx * dx + dy * dy + dz * dz;
-                const bool near = live && sizeof(T) == 4 && fabs(r2 - rc2) < band;
-                edge |= near;
-                if (live && r2 < rc2 && !near) pair(dx, dy, dz, r2, true);
-            }
-#pragma unroll
-            for (int u = 0; u < kGroup; ++u) ec[u] = en[u];
-        }
-        if (edge) {
-            for (int k = 0; k < nall; ++k) {
-                const unsigned e = lst[(size_t)k * vt];
-                const bool wall = k >= nvap;
-                const int a = (int)(e & kIndexMask);
-                const V o = wall ? Lc[vt + a] : tl.pos[a];
-                const T dx = me.x - o.x + shift_of<T>(e, 0, hx);
-                const T dy = me.y - o.y + shift_of<T>(e, 2, hy);
-                const T dz = me.z - o.z + shift_of<T>(e, 4, hz);
-                const T r2 = dx * dx + dy * dy + dz * dz;
-                if (!(fabs(r2 - rc2) < band)) continue;
-                double ox, oy, oz;
-                if (wall) {
-                    ox = P.WX[a];
-                    oy = P.WX[P.wt + a];
-                    oz = P.WX[2 * P.wt + a];
-                } else {
-                    const int j = tl.slot[a];
-                    ox = X[j];
-                    oy = X[vt + j];
-                    oz = X[2 * vt + j];
-                }
-                double ex = xi - ox, ey = yi - oy, ez = zi - oz;
-                ex -= sp.L[0] * rint(ex * sp.invL[0]);
-                ey -= sp.L[1] * rint(ey * sp.invL[1]);
-                ez -= sp.L[2] * rint(ez * sp.invL[2]);
-                if (ex * ex + ey * ey + ez * ez < sp.rc2) pair(dx, dy, dz, r2, wall);
-            }
-        }
-        evv += 0.5 * eav;
-        evw += eaw;
-        const double ax = fx * sp.inv_mass, ay = fy * sp.inv_mass, az = fz * sp.inv_mass;
-        double vx = vx0, vy = vy0, vz = vz0;
-        if (init) {
+        double ex = xi - ox, ey = yi - oy, ez = zi - oz;
+        ex -= sp.L[0] * rint(ex * sp.invL[0]);
+        ey -= sp.L[1] * rint(ey * sp.invL[1]);
+        ez -= sp.L[2] * rint(ez * sp.invL[2]);
+        if (ex * ex + ey * ey + ez * ez < sp.rc2) pair_term<T>(x, a, dx, dy, dz, r2, wall);
+    }
+}
+
+// F3 (second half-kick) and, unless the run ends, F2 of the next step (first
+// half-kick, drift, wrap, local coordinates, travelled path).  Returns the
+// kinetic energy at the full step; raises halt and non-finite bits.
+template <typename T>
+__device__ double atom_epilogue(const PoolDev& P, const SysParams& sp, const StepCtx<T>& x, int i,
+                                const Acc& a, int& flags)
+{
+    using V = typename V4<T>::type;
+    const int vt = P.vt;
+    const double xi = x.X[i], yi = x.X[vt + i], zi = x.X[2 * vt + i];
+    double vx = x.Vv[i], vy = x.Vv[vt + i], vz = x.Vv[2 * vt + i];
+    const double ax = a.fx * sp.inv_mass, ay = a.fy * sp.inv_mass, az = a.fz * sp.inv_mass;
+    if (x.init) {
+        P.A[i] = ax;
+        P.A[vt + i] = ay;
+        P.A[2 * vt + i] = az;
+    } else {
+        const double hdt = 0.5 * sp.dt;
+        vx += hdt * ax;  // F3: v(t) = v(t - dt/2) + a(t) dt/2
+        vy += hdt * ay;
+        vz += hdt * az;
+    }
+    const double kei = 0.5 * sp.mass * (vx * vx + vy * vy + vz * vz);
+    if (!x.init) {
+        if (x.last) {
+            x.Xn[i] = xi;
+            x.Xn[vt + i] = yi;
+            x.Xn[2 * vt + i] = zi;
+            x.Vn[i] = vx;
+            x.Vn[vt + i] = vy;
+            x.Vn[2 * vt + i] = vz;
             P.A[i] = ax;
             P.A[vt + i] = ay;
             P.A[2 * vt + i] = az;
         } else {
             const double hdt = 0.5 * sp.dt;
-            vx += hdt * ax;  // F3: v(t) = v(t - dt/2) + a(t) dt/2
+            vx += hdt * ax;  // F2 of the next step: v(t + dt/2) = v(t) + a(t) dt/2
             vy += hdt * ay;
             vz += hdt * az;
+            const double xx = wrap_box(xi + vx * sp.dt, sp.L[0]);
+            const double yy = wrap_box(yi + vy * sp.dt, sp.L[1]);
+            const double zz = wrap_box(zi + vz * sp.dt, sp.L[2]);
+            x.Vn[i] = vx;
+            x.Vn[vt + i] = vy;
+            x.Vn[2 * vt + i] = vz;
+            x.Xn[i] = xx;
+            x.Xn[vt + i] = yy;
+            x.Xn[2 * vt + i] = zz;
+            const int cr = P.cref[i];
+            const int cx = cr & 1023, cy = (cr >> 10) & 1023, cz = cr >> 20;
+            V* Ln = (V*)P.L[x.lbuf ^ 1];
+            Ln[i] = make4<T>(local_axis(xx, cx, sp.h[0], sp.L[0], sp.invL[0]),
+                             local_axis(yy, cy, sp.h[1], sp.L[1], sp.invL[1]),
+                             local_axis(zz, cz, sp.h[2], sp.L[2], sp.invL[2]));
+            const float tr = P.travel[i] + (float)(sqrt(vx * vx + vy * vy + vz * vz) * sp.dt);
+            P.travel[i] = tr;
+            if (tr > sp.half_skin) flags |= ST_HALT;
         }
-        const double kei = 0.5 * sp.mass * (vx * vx + vy * vy + vz * vz);
-        ke += kei;
-        if (!init) {
-            if (last) {
-                Xn[i] = xi;
-                Xn[vt + i] = yi;
-                Xn[2 * vt + i] = zi;
-                Vn[i] = vx;
-                Vn[vt + i] = vy;
-                Vn[2 * vt + i] = vz;
-                P.A[i] = ax;
-                P.A[vt + i] = ay;
-                P.A[2 * vt + i] = az;
-            } else {
-                const double hdt = 0.5 * sp.dt;
-                vx += hdt * ax;  // F2 of the next step: v(t + dt/2) = v(t) + a(t) dt/2
-                vy += hdt * ay;
-                vz += hdt * az;
-                const double x = wrap_box(xi + vx * sp.dt, sp.L[0]);
-                const double y = wrap_box(yi + vy * sp.dt, sp.L[1]);
-                const double z = wrap_box(zi + vz * sp.dt, sp.L[2]);
-                Vn[i] = vx;
-                Vn[vt + i] = vy;
-                Vn[2 * vt + i] = vz;
-                Xn[i] = x;
-                Xn[vt + i] = y;
-                Xn[2 * vt + i] = z;
-                const int cx = cr & 1023, cy = (cr >> 10) & 1023, cz = cr >> 20;
-                V* Ln = (V*)P.L[lbuf ^ 1];
-                Ln[i] = make4<T>(local_axis(x, cx, sp.h[0], sp.L[0], sp.invL[0]),
-                                 local_axis(y, cy, sp.h[1], sp.L[1], sp.invL[1]),
-                                 local_axis(z, cz, sp.h[2], sp.L[2], sp.invL[2]));
-                const float tr = tr0 + (float)(sqrt(vx * vx + vy * vy + vz * vz) * sp.dt);
-                P.travel[i] = tr;
-                if (tr > sp.half_skin) flags |= ST_HALT;
-            }
-        }
-        if (!isfinite(fx + fy + fz) || !isfinite(kei)) flags |= ST_NONFINITE;
     }
+    if (!isfinite(a.fx + a.fy + a.fz) || !isfinite(kei)) flags |= ST_NONFINITE;
+    return kei;
+}
 
-    // workgroup reductions (fixed order: lane tree, then waves in order)
-    const int lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
+// Workgroup reductions in a fixed order (lane tree, then waves in order):
+// status bits to the system, energies to the brick's partial of slot kk & 1.
+__device__ void step_reduce(const PoolDev& P, const SysParams& sp, int s, int b, int kk, bool doE,
+                            int flags, double ke, double evv, double evw)
+{
+    __shared__ double red[3][4];
+    __shared__ int flag_or[4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
     flags = wave_or(flags);
     if (lane == 0) flag_or[wave] = flags;
     if (doE) {
@@ -1199,18 +1153,126 @@ __global__ void __launch_bounds__(256) k_step(PoolDev P, int kk)
             if (f & (ST_HALT | ST_NONFINITE | ST_OVERFLOW)) atomicMin(&P.st[s].stop, kk);
         }
         if (doE) {
-            double a = 0.0, b = 0.0, cc = 0.0;
+            double a = 0.0, bb = 0.0, cc = 0.0;
             for (int w = 0; w < nwave; ++w) {
                 a += red[0][w];
-                b += red[1][w];
+                bb += red[1][w];
                 cc += red[2][w];
             }
-            double* pp = P.partial + 3 * ((size_t)(kk & 1) * P.nbt + sp.pboff + c.b);
+            double* pp = P.partial + 3 * ((size_t)(kk & 1) * P.nbt + sp.pboff + b);
             pp[0] = a;
-            pp[1] = b;
+            pp[1] = bb;
             pp[2] = cc;
         }
     }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_step(PoolDev P, int kk)
+{
+    using V = typename V4<T>::type;
+    extern __shared__ __align__(32) unsigned char smem[];
+    __shared__ int lds_scan[17];
+
+    BrickCtx c;
+    if (!brick_ctx(P, c, ST_OVERFLOW | ST_NONFINITE)) return;
+    const int s = c.s;
+    const SysParams& sp = P.sp[s];
+    const SysState st = P.st[s];
+    // step kk of the replay runs unless the run ends earlier or an earlier
+    // step of the replay raised a stop (travel beyond skin/2, non-finite)
+    if (kk >= st.remaining || kk > st.stop) return;
+    const int tid = threadIdx.x;
+    const StepCtx<T> x = step_ctx<T>(P, sp, st, kk);
+    // the system's first brick records the previous step's energies
+    if (c.b == 0 && kk > 0) {
+        const long long kprev = st.step + kk;
+        if (step_records(sp, false, false, kprev)) record_energies(P, sp, s, (kk - 1) & 1, kprev);
+    }
+    const HaloGeo g = halo_geo(sp, c.b);
+    Tile<T> tl = tile_of<T>(smem, P);
+    const int tot = stage_halo<T>(P, sp, g, tl, x.Lc, true, lds_scan);
+
+    const int vt = P.vt;
+    const int key0 = c.b * sp.bcells;
+    const int i0 = P.cstart[sp.coff + key0], i1 = P.cstart[sp.coff + key0 + sp.bcells];
+
+    double ke = 0.0, evv = 0.0, evw = 0.0;
+    int flags = tot < 0 ? (ST_OVERFLOW | ST_TILE) : 0;
+    for (int i = i0 + tid; tot >= 0 && i < i1; i += blockDim.x) {
+        const V me = x.Lc[i];
+        const int nl = P.nlist[i];
+        const int nvap = nl & 0xFFFF, nall = nvap + (nl >> 16);
+        Acc a{0.0, 0.0, 0.0, 0.0, 0.0};
+        const unsigned* lst = P.list + i;
+        // entries come kGroup at a time, the next group's loads in flight while
+        // the current one is evaluated; vapour partners are read from LDS,
+        // wall partners from global memory.  Pairs whose FP32 r^2 lies within
+        // a narrow band around the cutoff are left out here and decided in
+        // FP64 after the whole list (a rare slow path: a few atoms per step),
+        // so the per-pair code has no branch.  Every load is unconditional,
+        // with indices clamped to valid memory (list rows past the end of this
+        // atom's list exist up to the capacity; their values are not used), so
+        // the code is straight-line and each wait covers only the loads it needs
+        bool edge = false;
+        const int lastrow = P.cap - 1;
+        unsigned ec[kGroup];
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) ec[u] = lst[(size_t)min(u, lastrow) * vt];
+        for (int k0 = 0; k0 < nvap; k0 += kGroup) {
+            unsigned en[kGroup];
+#pragma unroll
+            for (int u = 0; u < kGroup; ++u) en[u] = lst[(size_t)min(k0 + kGroup + u, lastrow) * vt];
+#pragma unroll
+            for (int u = 0; u < kGroup; ++u) {
+                const bool live = k0 + u < nvap;
+                const unsigned e = ec[u];
+                const V o = tl.pos[live ? (int)(e & kIndexMask) : 0];
+                const T dx = me.x - o.x + shift_of<T>(e, 0, x.hx);
+                const T dy = me.y - o.y + shift_of<T>(e, 2, x.hy);
+                const T dz = me.z - o.z + shift_of<T>(e, 4, x.hz);
+                const T r2 = dx * dx + dy * dy + dz * dz;
+                const bool near = live && sizeof(T) == 4 && fabs(r2 - x.rc2) < x.band;
+                edge |= near;
+                if (live && r2 < x.rc2 && !near) pair_term<T>(x, a, dx, dy, dz, r2, false);
+            }
+#pragma unroll
+            for (int u = 0; u < kGroup; ++u) ec[u] = en[u];
+        }
+        if (nall > nvap) {
+#pragma unroll
+            for (int u = 0; u < kGroup; ++u) ec[u] = lst[(size_t)min(nvap + u, lastrow) * vt];
+        }
+        for (int k0 = nvap; k0 < nall; k0 += kGroup) {
+            V ow[kGroup];
+#pragma unroll
+            for (int u = 0; u < kGroup; ++u)
+                ow[u] = x.Lc[vt + (k0 + u < nall ? (int)(ec[u] & kIndexMask) : 0)];
+            unsigned en[kGroup];
+#pragma unroll
+            for (int u = 0; u < kGroup; ++u) en[u] = lst[(size_t)min(k0 + kGroup + u, lastrow) * vt];
+#pragma unroll
+            for (int u = 0; u < kGroup; ++u) {
+                const bool live = k0 + u < nall;
+                const unsigned e = ec[u];
+                const V o = ow[u];
+                const T dx = me.x - o.x + shift_of<T>(e, 0, x.hx);
+                const T dy = me.y - o.y + shift_of<T>(e, 2, x.hy);
+                const T dz = me.z - o.z + shift_of<T>(e, 4, x.hz);
+                const T r2 = dx * dx + dy * dy + dz * dz;
+                const bool near = live && sizeof(T) == 4 && fabs(r2 - x.rc2) < x.band;
+                edge |= near;
+                if (live && r2 < x.rc2 && !near) pair_term<T>(x, a, dx, dy, dz, r2, true);
+            }
+#pragma unroll
+            for (int u = 0; u < kGroup; ++u) ec[u] = en[u];
+        }
+        if (edge) edge_pass<T>(P, sp, x, tl, i, nvap, nall, a);
+        evv += 0.5 * a.ev;
+        evw += a.ew;
+        ke += atom_epilogue<T>(P, sp, x, i, a, flags);
+    }
+    step_reduce(P, sp, s, c.b, kk, x.doE, flags, ke, evv, evw);
 }
 
 // End of a replay, one workgroup per system: count the steps the replay
