@@ -14,7 +14,6 @@ namespace pmd {
 
 constexpr int kPad = 256;            // vapour slots per system are padded to this
 constexpr int kChunk = 16;           // atoms per entry of the chunk -> system table
-constexpr int kLanes = 4;            // lanes per atom in the list-build and step kernels
 constexpr int kTile = 4096;          // cells per workgroup of the cell-count scan
 constexpr int kRebuildBlock = 256;   // threads per workgroup of the per-atom rebuild kernels
 constexpr unsigned kIndexBits = 26;  // neighbour-list entry: index | cell-offset code << 26
