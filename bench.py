@@ -40,11 +40,15 @@ MEASURED_TRAFFIC = {
 
 
 def kernel_source_hash():
+    """sha256 prefix of the device code's sources (kernels and the layout
+    header they include)."""
     import hashlib
 
-    path = os.path.join(ROOT, "paper_1812_07993_amd", "csrc", "pmd_kernels.hip")
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in ("pmd_kernels.hip", "pmd_internal.h"):
+        with open(os.path.join(ROOT, "paper_1812_07993_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def log(*a):
@@ -85,7 +89,7 @@ def autotune(poremd, desc, prec, trial_steps, tuning_kw):
     if tuning_kw.get("block") or tuning_kw.get("brick_atoms"):
         return out
     # second stage: workgroup size and atoms per brick at the chosen skin and period
-    shapes = [(256, 0), (256, 256), (256, 160), (128, 0)]
+    shapes = [(256, 0), (256, 256), (256, 270), (256, 160), (512, 460), (128, 0)]
     cands = [poremd.make_tuning(skin=b.skin, rebin_every=b.rebin_every, block=bl, brick_atoms=ba)
              for bl, ba in shapes]
     best2, us2 = poremd.pmd_autotune(params, pore, desc.x, desc.v, cands, trial_steps)

@@ -104,8 +104,9 @@ typedef struct {
  * radius of the neighbour lists beyond the cutoff; rebin_every: steps
  * between neighbour-list rebuilds (a rebuild also happens early whenever an
  * atom has travelled more than skin/2 since the last one); block: threads
- * per workgroup of the force kernels (64, 128 or 256; each workgroup owns
- * one brick of cells, sized to hold about 0.8 x block atoms); list_cap:
+ * per workgroup of the force kernels (a multiple of 64 from 64 to 512; each
+ * workgroup owns one brick of cells, sized to hold about 0.8 x block atoms
+ * unless brick_atoms says otherwise); list_cap:
  * neighbour-list slots
  * per atom; energy_every: record energies every k steps (the last step of
  * every pmd_step call is always recorded). */

@@ -16,6 +16,7 @@ constexpr int kPad = 256;            // vapour slots per system are padded to th
 constexpr int kChunk = 16;           // atoms per entry of the chunk -> system table
 constexpr int kTile = 4096;          // cells per workgroup of the cell-count scan
 constexpr int kRebuildBlock = 256;   // threads per workgroup of the per-atom rebuild kernels
+constexpr int kMaxBlock = 1024;      // largest workgroup of the brick kernels (multiple of 64)
 constexpr unsigned kIndexBits = 26;  // neighbour-list entry: index | cell-offset code << 26
 constexpr unsigned kIndexMask = (1u << kIndexBits) - 1u;
 
@@ -29,7 +30,9 @@ enum Status : int {
     ST_HALT = 1,       // an atom travelled more than skin/2 since the last rebuild
     ST_OVERFLOW = 2,   // a neighbour list exceeded its capacity
     ST_NONFINITE = 4,  // a non-finite force or position appeared
-    ST_TILE = 8        // a brick's halo did not fit the LDS tile
+    ST_TILE = 8,       // a brick's halo did not fit the LDS tile
+    ST_STALL = 16      // a rebuild overflowed: later rebuilds and steps wait
+                       // until the host has grown the buffer and cleared this bit
 };
 
 // Per-system constants (set on the host at admission).
@@ -164,7 +167,8 @@ hipError_t launch_wall_generate(const PoreDev& pore, const double* L, double* ou
 hipError_t launch_wall_bin(const PoolDev& P, int sys, const double* raw_soa, int raw_stride,
                            int nw, int precision, hipStream_t s);
 hipError_t launch_rebuild(const PoolDev& P, int nslots, int precision, hipStream_t s);
-hipError_t launch_set_run(const PoolDev& P, int slot, int add_steps, hipStream_t s);
+hipError_t launch_set_run(const PoolDev& P, int slot, int add_steps, int clear_bits,
+                          hipStream_t s);
 hipError_t launch_reset_state(const PoolDev& P, int slot, long long step, hipStream_t s);
 hipError_t launch_step(const PoolDev& P, int kk, int precision, hipStream_t s, hipEvent_t ev0,
                        hipEvent_t ev1);

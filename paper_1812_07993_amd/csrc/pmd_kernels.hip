@@ -394,7 +394,7 @@ __device__ __forceinline__ bool rebuild_ctx(const PoolDev& P, SlotCtx& c)
     const int s = P.chunk_sys[chunk];
     if (s < 0) return false;
     const SysState* st = P.st + s;
-    if (st->remaining <= 0 || (st->status & ST_NONFINITE)) return false;
+    if (st->remaining <= 0 || (st->status & (ST_NONFINITE | ST_STALL))) return false;
     const SysParams* sp = P.sp + s;
     c.s = s;
     c.li = (chunk - sp->choff) * kChunk + (int)threadIdx.x;
@@ -461,7 +461,7 @@ __global__ void __launch_bounds__(1024) k_bin_scan(PoolDev P)
     const int s = P.tile_sys[tile];
     const SysParams& sp = P.sp[s];
     const SysState* st = P.st + s;
-    if (!sp.active || st->remaining <= 0 || (st->status & ST_NONFINITE)) return;
+    if (!sp.active || st->remaining <= 0 || (st->status & (ST_NONFINITE | ST_STALL))) return;
     const int lt = tile - sp.toff;
     const int M = sp.nkey + 2;
     const int c0 = lt * kTile + 4 * (int)threadIdx.x;
@@ -490,7 +490,7 @@ __global__ void k_bin_scan_finish(PoolDev P, int nslots)
     if (s >= nslots || threadIdx.x != 0) return;
     const SysParams& sp = P.sp[s];
     SysState* st = P.st + s;
-    if (!sp.active || st->remaining <= 0 || (st->status & ST_NONFINITE)) return;
+    if (!sp.active || st->remaining <= 0 || (st->status & (ST_NONFINITE | ST_STALL))) return;
     int off = sp.voff;
     for (int t = 0; t < sp.ntile; ++t) {
         const int q = P.ctile[sp.toff + t];
@@ -740,13 +740,13 @@ __device__ __forceinline__ double box_gap(double l, int d, double h)
 // in L2): staging them would size every brick's LDS for the densest wall
 // halo and leave one workgroup per CU.
 template <typename T>
-__global__ void __launch_bounds__(256) k_list_build(PoolDev P)
+__global__ void __launch_bounds__(kMaxBlock) k_list_build(PoolDev P)
 {
     using V = typename V4<T>::type;
     extern __shared__ __align__(32) unsigned char smem[];
     __shared__ int lds_scan[17];
     BrickCtx c;
-    if (!brick_ctx(P, c, ST_NONFINITE)) return;
+    if (!brick_ctx(P, c, ST_NONFINITE | ST_STALL)) return;
     const SysParams& sp = P.sp[c.s];
     const SysState& st = P.st[c.s];
     const int vt = P.vt;
@@ -897,7 +897,7 @@ __device__ __forceinline__ bool step_records(const SysParams& sp, bool init, boo
 // workgroup; the partials were written by an earlier launch.
 __device__ void record_energies(const PoolDev& P, const SysParams& sp, int s, int ring, long long kstep)
 {
-    __shared__ double red[3][4];
+    __shared__ double red[3][kMaxBlock / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
     const double* pp = P.partial + 3 * ((size_t)ring * P.nbt + sp.pboff);
     double a = 0.0, b = 0.0, cc = 0.0;
@@ -1129,8 +1129,8 @@ __device__ double atom_epilogue(const PoolDev& P, const SysParams& sp, const Ste
 __device__ void step_reduce(const PoolDev& P, const SysParams& sp, int s, int b, int kk, bool doE,
                             int flags, double ke, double evv, double evw)
 {
-    __shared__ double red[3][4];
-    __shared__ int flag_or[4];
+    __shared__ double red[3][kMaxBlock / 64];
+    __shared__ int flag_or[kMaxBlock / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
     flags = wave_or(flags);
     if (lane == 0) flag_or[wave] = flags;
@@ -1168,7 +1168,7 @@ __device__ void step_reduce(const PoolDev& P, const SysParams& sp, int s, int b,
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_step(PoolDev P, int kk)
+__global__ void __launch_bounds__(kMaxBlock) k_step(PoolDev P, int kk)
 {
     using V = typename V4<T>::type;
     extern __shared__ __align__(32) unsigned char smem[];
@@ -1285,7 +1285,11 @@ __global__ void __launch_bounds__(256) k_commit(PoolDev P, int nslots, int R)
     const SysState st = P.st[s];
     if (!sp.active || st.remaining <= 0 || (st.status & (ST_OVERFLOW | ST_NONFINITE))) {
         if (threadIdx.x == 0 && sp.active) {
-            P.st[s].status = st.status | st.status_next;
+            // a failed rebuild stalls the system: the replays queued behind
+            // this one skip their rebuilds and steps until the host has
+            // grown the buffer
+            const int f = st.status | st.status_next;
+            P.st[s].status = f | ((f & ST_OVERFLOW) ? ST_STALL : 0);
             P.st[s].status_next = 0;
             P.st[s].stop = 0x7fffffff;
         }
@@ -1349,14 +1353,15 @@ hipError_t launch_commit(const PoolDev& P, int nslots, int R, hipStream_t s)
 // Host-requested state changes and readbacks
 // ---------------------------------------------------------------------------
 
-__global__ void k_set_run(PoolDev P, int slot, int add_steps)
+__global__ void k_set_run(PoolDev P, int slot, int add_steps, int clear_bits)
 {
     P.st[slot].remaining += add_steps;
+    P.st[slot].status &= ~clear_bits;
 }
 
-hipError_t launch_set_run(const PoolDev& P, int slot, int add_steps, hipStream_t s)
+hipError_t launch_set_run(const PoolDev& P, int slot, int add_steps, int clear_bits, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_set_run, dim3(1), dim3(1), 0, s, P, slot, add_steps);
+    hipLaunchKernelGGL(k_set_run, dim3(1), dim3(1), 0, s, P, slot, add_steps, clear_bits);
     return hipGetLastError();
 }
 

@@ -198,8 +198,8 @@ int merge_tuning(const pmd_params& p, int64_t nv, const pmd_tuning* in, pmd_tuni
         if (in->brick_atoms > 0) d.brick_atoms = in->brick_atoms;
         if (in->brick_order > 0) d.brick_order = in->brick_order;
     }
-    if (d.block != 64 && d.block != 128 && d.block != 256)
-        return fail(PMD_EINVAL, "block must be 64, 128 or 256 (got %d)", d.block);
+    if (d.block < 64 || d.block > kMaxBlock || d.block % 64)
+        return fail(PMD_EINVAL, "block must be a multiple of 64 from 64 to %d (got %d)", kMaxBlock, d.block);
     if (d.rebin_every > 1000) return fail(PMD_EINVAL, "rebin_every must be <= 1000");
     if (d.brick_order != 1 && d.brick_order != 2)
         return fail(PMD_EINVAL, "brick_order must be 0, 1 or 2 (got %d)", d.brick_order);
@@ -522,9 +522,11 @@ int pool_layout(Pool& p)
 }
 
 // Brick shape: the largest brick (at most 8 cells per axis) whose expected
-// atom count fits `target`, preferring near-cubic shapes (smallest halo per
-// cell); `target` scales with the workgroup size.
-void choose_bricks(SysParams& sp, double target)
+// atom count fits `target` and whose halo box, at 1.3 times the mean
+// occupancy (room for density fluctuations), fits the LDS tile; near-cubic
+// shapes (smallest halo per cell) are preferred.  `target` scales with the
+// workgroup size.
+void choose_bricks(SysParams& sp, double target, size_t atom_bytes)
 {
     const double occ = std::max((double)sp.nv / sp.ncell, 1e-3);
     int best[3] = {1, 1, 1};
@@ -534,6 +536,9 @@ void choose_bricks(SysParams& sp, double target)
             for (int bz = 1; bz <= std::min(8, sp.nc[2]); ++bz) {
                 const int P = bx * by * bz;
                 if (P * occ > target && P > 1) continue;
+                const int H = (bx + 2) * (by + 2) * (bz + 2);
+                const double fit = (double)(kTileBytesMax - (size_t)(2 * H + 1) * 4) / atom_bytes;
+                if (1.3 * H * occ > fit && P > 1) continue;
                 const double halo = (double)(bx + 2) * (by + 2) * (bz + 2) / P;
                 const double score = P - 0.01 * halo;
                 if (score > best_score) {
@@ -573,7 +578,7 @@ int pool_fix_tile(Pool& p, int slot)
     SysParams& sp = p.hsp[slot];
     if (sp.bcells == 1) return fail(PMD_ENOMEM, "a single cell's neighbourhood exceeds the LDS tile");
     const double occ = std::max((double)sp.nv / sp.ncell, 1e-3);
-    choose_bricks(sp, 0.5 * sp.bcells * occ);
+    choose_bricks(sp, 0.5 * sp.bcells * occ, ab);
     return pool_layout(p);
 }
 
@@ -611,7 +616,8 @@ void fill_sys_params(SysParams& sp, const pmd_params& p, const Grid& g, const pm
     sp.half_skin = (float)(0.5 * t.skin * (1.0 - 1e-3));
     sp.energy_every = t.energy_every;
     sp.active = 1;
-    choose_bricks(sp, brick_target > 0 ? brick_target : t.brick_atoms > 0 ? t.brick_atoms : 0.8 * t.block);
+    choose_bricks(sp, brick_target > 0 ? brick_target : t.brick_atoms > 0 ? t.brick_atoms : 0.8 * t.block,
+                  tile_atom_bytes(p.precision));
 }
 
 // Capture `reps` replays of [rebuild, R steps] into one graph.
@@ -738,6 +744,7 @@ int sys_sync(pmd_system* s)
             CHK(pool_grow_lists(p, need));
             s->tuning.list_cap = need;
         }
+        if (st.status & ST_STALL) HIPCHK(launch_set_run(p.dev(), s->slot, 0, ST_STALL, p.stream));
         const int R = s->tuning.rebin_every;
         CHK(pool_enqueue(p, R, s->tuning.use_graph, (st.remaining + R - 1) / R));
     }
@@ -792,6 +799,7 @@ int load_state(pmd_system* sys, const double* pos, const double* vel, int64_t st
             CHK(pool_grow_lists(q, need));
             sys->tuning.list_cap = need;
         }
+        if (st.status & ST_STALL) HIPCHK(launch_set_run(q.dev(), slot, 0, ST_STALL, q.stream));
     }
     return fail(PMD_EHIP, "initial force evaluation did not complete");
 }
@@ -1193,7 +1201,7 @@ int pmd_step(pmd_system* sys, int64_t nsteps)
         if (nsteps < 0 || nsteps > (int64_t)1 << 30) return fail(PMD_EINVAL, "nsteps out of range");
         if (nsteps == 0) return PMD_OK;
         Pool& p = *sys->pool;
-        HIPCHK(launch_set_run(p.dev(), sys->slot, (int)nsteps, p.stream));
+        HIPCHK(launch_set_run(p.dev(), sys->slot, (int)nsteps, 0, p.stream));
         const int R = sys->tuning.rebin_every;
         CHK(pool_enqueue(p, R, sys->tuning.use_graph, (nsteps + R - 1) / R));
         return PMD_OK;
@@ -1797,7 +1805,7 @@ int pmd_batch_admit(pmd_batch* b, pmd_system* sys, int64_t nsteps, int* slot)
         sys->pool = &p;
         sys->slot = free_slot;
         sys->batch = b;
-        if (nsteps > 0) HIPCHK(launch_set_run(p.dev(), free_slot, (int)nsteps, p.stream));
+        if (nsteps > 0) HIPCHK(launch_set_run(p.dev(), free_slot, (int)nsteps, 0, p.stream));
         *slot = free_slot;
         return PMD_OK;
     } catch (const std::bad_alloc&) {
@@ -1851,6 +1859,9 @@ static int batch_poll_impl(pmd_batch* b, int* done, int cap, int* n_done, bool w
         if (need > 4096) return fail(PMD_ENOMEM, "neighbour list needs %d entries", need);
         CHK(pool_grow_lists(p, need));
     }
+    for (int s = 0; s < p.nslots; ++s)
+        if (b->resident[s] && (st[s].status & ST_STALL))
+            HIPCHK(launch_set_run(p.dev(), s, 0, ST_STALL, p.stream));
     return PMD_OK;
 }
 

@@ -59,3 +59,33 @@ def test_dense_cluster_outgrows_the_tile(prec):
     Fr, _, _ = oracle.forces(X, None, p)
     assert np.linalg.norm(s.forces() - Fr) / np.linalg.norm(Fr) <= TOL_F[prec]
     s.close()
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_lists_overflow_in_the_middle_of_a_run(prec):
+    """An imploding gas (velocities toward the box centre) outgrows its
+    neighbour lists part-way through one step() call that queued 50
+    replays.  The replay whose rebuild overflowed stalls the system, the
+    queued replays behind it skip their rebuilds and steps, the host grows
+    the lists and the run resumes: the result is bit-identical to a run that
+    had room from the start, with one extra rebuild per overflow."""
+    L = 30.0
+    rng = np.random.default_rng(5)
+    x = synth.rsa_place(rng, (L, L, L), 2000, np.zeros((0, 3)), 0.9)
+    v = -0.3 * (x - L / 2.0)
+    params = poremd.make_params(L, prec)
+    a = poremd.System(params, poremd.make_pore("none"), x, v,
+                      tuning=poremd.make_tuning(rebin_every=4, list_cap=16))
+    b = poremd.System(params, poremd.make_pore("none"), x, v,
+                      tuning=poremd.make_tuning(rebin_every=4, list_cap=256))
+    cap0 = poremd.pmd_get_tuning(a.h).list_cap
+    a.step(200)
+    b.step(200)
+    assert np.array_equal(a.positions(), b.positions())  # (waits for the run)
+    assert np.array_equal(a.velocities(), b.velocities())
+    assert poremd.pmd_get_tuning(a.h).list_cap > cap0
+    ra, _ = poremd.pmd_debug_lists(a.h)
+    rb, _ = poremd.pmd_debug_lists(b.h)
+    assert rb < ra <= rb + 4, (ra, rb)
+    a.close()
+    b.close()

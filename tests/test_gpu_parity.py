@@ -90,7 +90,7 @@ def test_forces_energies_at_create(prec, n, name, pore):
     assert e["ke"] == pytest.approx(0.5 * np.sum(v * v), rel=1e-13)
 
 
-@pytest.mark.parametrize("block", [64, 128, 256])
+@pytest.mark.parametrize("block", [64, 128, 256, 320, 512, 1024])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_trajectory_10_steps(prec, block):
     """Ten velocity-Verlet steps from the same start; also crosses a rebuild
