@@ -63,9 +63,12 @@ __device__ __forceinline__ int wrap_cell(int c, int n)
     return c;
 }
 
+// Periodic image in [0, L) of a coordinate at most one box length outside it
+// (an atom moves far less than L in a step): one add or subtract, no
+// division; x + L rounding up to L for a tiny negative x gives 0.
 __device__ __forceinline__ double wrap_box(double x, double L)
 {
-    x -= L * floor(x / L);
+    x = (x < 0.0) ? x + L : (x >= L) ? x - L : x;
     return (x >= L) ? 0.0 : x;
 }
 
@@ -958,7 +961,25 @@ struct StepCtx {
     double* Xn;            // ... and after it (the other buffer)
     double* Vn;
     T rc2, Av, Bv, Aw, Bw, A12v, B6v, A12w, B6w, ucv, ucw, band, hx, hy, hz;
+    // FP64 constants of the integration, held in scalar registers
+    double L[3], invL[3], h[3], dt, hdt, mass, inv_mass;
+    float half_skin;
 };
+
+// A workgroup-uniform value moved into scalar registers, which frees the
+// vector registers a per-lane copy would hold through the kernel.
+__device__ __forceinline__ double uniform_f64(double v)
+{
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)u);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(u >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+__device__ __forceinline__ float uniform_f32(float v)
+{
+    return __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(v)));
+}
 
 template <typename T>
 __device__ __forceinline__ StepCtx<T> step_ctx(const PoolDev& P, const SysParams& sp, const SysState& st, int kk)
@@ -993,6 +1014,16 @@ __device__ __forceinline__ StepCtx<T> step_ctx(const PoolDev& P, const SysParams
     x.hx = (T)sp.h[0];
     x.hy = (T)sp.h[1];
     x.hz = (T)sp.h[2];
+    for (int k = 0; k < 3; ++k) {
+        x.L[k] = uniform_f64(sp.L[k]);
+        x.invL[k] = uniform_f64(sp.invL[k]);
+        x.h[k] = uniform_f64(sp.h[k]);
+    }
+    x.dt = uniform_f64(sp.dt);
+    x.hdt = uniform_f64(0.5 * sp.dt);
+    x.mass = uniform_f64(sp.mass);
+    x.inv_mass = uniform_f64(sp.inv_mass);
+    x.half_skin = uniform_f32(sp.half_skin);
     return x;
 }
 
@@ -1065,25 +1096,25 @@ __device__ void edge_pass(const PoolDev& P, const SysParams& sp, const StepCtx<T
 // half-kick, drift, wrap, local coordinates, travelled path).  Returns the
 // kinetic energy at the full step; raises halt and non-finite bits.
 template <typename T>
-__device__ double atom_epilogue(const PoolDev& P, const SysParams& sp, const StepCtx<T>& x, int i,
+__device__ double atom_epilogue(const PoolDev& P, const StepCtx<T>& x, int i,
                                 const Acc& a, int& flags)
 {
     using V = typename V4<T>::type;
     const int vt = P.vt;
     const double xi = x.X[i], yi = x.X[vt + i], zi = x.X[2 * vt + i];
     double vx = x.Vv[i], vy = x.Vv[vt + i], vz = x.Vv[2 * vt + i];
-    const double ax = a.fx * sp.inv_mass, ay = a.fy * sp.inv_mass, az = a.fz * sp.inv_mass;
+    const double ax = a.fx * x.inv_mass, ay = a.fy * x.inv_mass, az = a.fz * x.inv_mass;
     if (x.init) {
         P.A[i] = ax;
         P.A[vt + i] = ay;
         P.A[2 * vt + i] = az;
     } else {
-        const double hdt = 0.5 * sp.dt;
+        const double hdt = x.hdt;
         vx += hdt * ax;  // F3: v(t) = v(t - dt/2) + a(t) dt/2
         vy += hdt * ay;
         vz += hdt * az;
     }
-    const double kei = 0.5 * sp.mass * (vx * vx + vy * vy + vz * vz);
+    const double kei = 0.5 * x.mass * (vx * vx + vy * vy + vz * vz);
     if (!x.init) {
         if (x.last) {
             x.Xn[i] = xi;
@@ -1096,13 +1127,13 @@ __device__ double atom_epilogue(const PoolDev& P, const SysParams& sp, const Ste
             P.A[vt + i] = ay;
             P.A[2 * vt + i] = az;
         } else {
-            const double hdt = 0.5 * sp.dt;
+            const double hdt = x.hdt;
             vx += hdt * ax;  // F2 of the next step: v(t + dt/2) = v(t) + a(t) dt/2
             vy += hdt * ay;
             vz += hdt * az;
-            const double xx = wrap_box(xi + vx * sp.dt, sp.L[0]);
-            const double yy = wrap_box(yi + vy * sp.dt, sp.L[1]);
-            const double zz = wrap_box(zi + vz * sp.dt, sp.L[2]);
+            const double xx = wrap_box(xi + vx * x.dt, x.L[0]);
+            const double yy = wrap_box(yi + vy * x.dt, x.L[1]);
+            const double zz = wrap_box(zi + vz * x.dt, x.L[2]);
             x.Vn[i] = vx;
             x.Vn[vt + i] = vy;
             x.Vn[2 * vt + i] = vz;
@@ -1112,12 +1143,12 @@ __device__ double atom_epilogue(const PoolDev& P, const SysParams& sp, const Ste
             const int cr = P.cref[i];
             const int cx = cr & 1023, cy = (cr >> 10) & 1023, cz = cr >> 20;
             V* Ln = (V*)P.L[x.lbuf ^ 1];
-            Ln[i] = make4<T>(local_axis(xx, cx, sp.h[0], sp.L[0], sp.invL[0]),
-                             local_axis(yy, cy, sp.h[1], sp.L[1], sp.invL[1]),
-                             local_axis(zz, cz, sp.h[2], sp.L[2], sp.invL[2]));
-            const float tr = P.travel[i] + (float)(sqrt(vx * vx + vy * vy + vz * vz) * sp.dt);
+            Ln[i] = make4<T>(local_axis(xx, cx, x.h[0], x.L[0], x.invL[0]),
+                             local_axis(yy, cy, x.h[1], x.L[1], x.invL[1]),
+                             local_axis(zz, cz, x.h[2], x.L[2], x.invL[2]));
+            const float tr = P.travel[i] + (float)(sqrt(vx * vx + vy * vy + vz * vz) * x.dt);
             P.travel[i] = tr;
-            if (tr > sp.half_skin) flags |= ST_HALT;
+            if (tr > x.half_skin) flags |= ST_HALT;
         }
     }
     if (!isfinite(a.fx + a.fy + a.fz) || !isfinite(kei)) flags |= ST_NONFINITE;
@@ -1270,7 +1301,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_step(PoolDev P, int kk)
         if (edge) edge_pass<T>(P, sp, x, tl, i, nvap, nall, a);
         evv += 0.5 * a.ev;
         evw += a.ew;
-        ke += atom_epilogue<T>(P, sp, x, i, a, flags);
+        ke += atom_epilogue<T>(P, x, i, a, flags);
     }
     step_reduce(P, sp, s, c.b, kk, x.doE, flags, ke, evv, evw);
 }
