@@ -31,11 +31,17 @@ ALG_BYTES = {"mixed": 120.0, "fp64": 144.0}
 PEAK_HBM_GBS = 8000.0
 
 # HBM bytes per k_step<float> launch from the FETCH_SIZE / WRITE_SIZE counter
-# passes summarised in profiles/k_step_slit128_mixed.md, keyed by the hash of
-# the kernel source they were taken on and the tuning they were taken at; any
-# other kernel source or tuning reports null.
+# passes summarised in profiles/k_step_slit128_mixed.md (128^3 slit workload,
+# skin 0.7), keyed by the hash of the device sources they were taken on, the
+# vapour atom count, the skin and the workgroup shape (block, target atoms per
+# brick).  The rebuild period is not part of the key: it changes how often
+# the lists are rebuilt, not what one step launch reads and writes.  Any
+# other source, workload or tuning reports null.
 MEASURED_TRAFFIC = {
-    ("00338fbd0069d3c7", 262144, 0.7, 10, 256, 256): 109.5e6,
+    ("c8adee643b55b995", 262144, 0.7, 256, 270): 107.17e6,
+    ("c8adee643b55b995", 262144, 0.7, 256, 256): 109.80e6,
+    ("c8adee643b55b995", 262144, 0.7, 512, 460): 100.38e6,
+    ("c8adee643b55b995", 262144, 0.7, 256, 0): 106.80e6,
 }
 
 
@@ -405,7 +411,6 @@ def main():
                      "frac": achieved / PEAK_HBM_GBS,
                      "traffic": MEASURED_TRAFFIC.get((kernel_source_hash(), n,
                                                       round(tuned["mixed"].get("skin", 0.0), 3),
-                                                      tuned["mixed"].get("rebin_every", 0),
                                                       tuned["mixed"].get("block") or 256,
                                                       tuned["mixed"].get("brick_atoms") or 0)),
                      "traffic_unit": "bytes per launch",

@@ -1052,44 +1052,61 @@ __device__ __forceinline__ void pair_term(const StepCtx<T>& x, Acc& a, T dx, T d
     }
 }
 
-// The rare pass over an atom's list for pairs whose FP32 r^2 fell within the
-// band around the cutoff: decided on the FP64 master positions, in list order.
+// List entry k of atom i if its FP32 r^2 lies within the band around the
+// cutoff: the pair is decided on the FP64 master positions.
 template <typename T>
-__device__ void edge_pass(const PoolDev& P, const SysParams& sp, const StepCtx<T>& x,
-                          const Tile<T>& tl, int i, int nvap, int nall, Acc& a)
+__device__ __forceinline__ void edge_entry(const PoolDev& P, const SysParams& sp, const StepCtx<T>& x,
+                                           const Tile<T>& tl, int i, int k, int nvap,
+                                           const typename V4<T>::type& me, double xi, double yi,
+                                           double zi, Acc& a)
 {
     using V = typename V4<T>::type;
     const int vt = P.vt;
-    const V me = x.Lc[i];
-    const double xi = x.X[i], yi = x.X[vt + i], zi = x.X[2 * vt + i];
-    const unsigned* lst = P.list + i;
-    for (int k = 0; k < nall; ++k) {
-        const unsigned e = lst[(size_t)k * vt];
-        const bool wall = k >= nvap;
-        const int ai = (int)(e & kIndexMask);
-        const V o = wall ? x.Lc[vt + ai] : tl.pos[ai];
-        const T dx = me.x - o.x + shift_of<T>(e, 0, x.hx);
-        const T dy = me.y - o.y + shift_of<T>(e, 2, x.hy);
-        const T dz = me.z - o.z + shift_of<T>(e, 4, x.hz);
-        const T r2 = dx * dx + dy * dy + dz * dz;
-        if (!(fabs(r2 - x.rc2) < x.band)) continue;
-        double ox, oy, oz;
-        if (wall) {
-            ox = P.WX[ai];
-            oy = P.WX[P.wt + ai];
-            oz = P.WX[2 * P.wt + ai];
-        } else {
-            const int j = tl.slot[ai];
-            ox = x.X[j];
-            oy = x.X[vt + j];
-            oz = x.X[2 * vt + j];
-        }
-        double ex = xi - ox, ey = yi - oy, ez = zi - oz;
-        ex -= sp.L[0] * rint(ex * sp.invL[0]);
-        ey -= sp.L[1] * rint(ey * sp.invL[1]);
-        ez -= sp.L[2] * rint(ez * sp.invL[2]);
-        if (ex * ex + ey * ey + ez * ez < sp.rc2) pair_term<T>(x, a, dx, dy, dz, r2, wall);
+    const unsigned e = P.list[(size_t)k * vt + i];
+    const bool wall = k >= nvap;
+    const int ai = (int)(e & kIndexMask);
+    const V o = wall ? x.Lc[vt + ai] : tl.pos[ai];
+    const T dx = me.x - o.x + shift_of<T>(e, 0, x.hx);
+    const T dy = me.y - o.y + shift_of<T>(e, 2, x.hy);
+    const T dz = me.z - o.z + shift_of<T>(e, 4, x.hz);
+    const T r2 = dx * dx + dy * dy + dz * dz;
+    if (!(fabs(r2 - x.rc2) < x.band)) return;
+    double ox, oy, oz;
+    if (wall) {
+        ox = P.WX[ai];
+        oy = P.WX[P.wt + ai];
+        oz = P.WX[2 * P.wt + ai];
+    } else {
+        const int j = tl.slot[ai];
+        ox = x.X[j];
+        oy = x.X[vt + j];
+        oz = x.X[2 * vt + j];
     }
+    double ex = xi - ox, ey = yi - oy, ez = zi - oz;
+    ex -= sp.L[0] * rint(ex * sp.invL[0]);
+    ey -= sp.L[1] * rint(ey * sp.invL[1]);
+    ez -= sp.L[2] * rint(ez * sp.invL[2]);
+    if (ex * ex + ey * ey + ez * ez < sp.rc2) pair_term<T>(x, a, dx, dy, dz, r2, wall);
+}
+
+// The pairs of atom i that the pair loops left out (FP32 r^2 within the band
+// around the cutoff), decided on the FP64 master positions and added in list
+// order.  The loops record the list positions of the first two such entries
+// (ne counts them all); only an atom with more than two rescans its list.
+template <typename T>
+__device__ void edge_pass(const PoolDev& P, const SysParams& sp, const StepCtx<T>& x,
+                          const Tile<T>& tl, int i, int nvap, int nall, int ne, int k0, int k1,
+                          Acc& a)
+{
+    const int vt = P.vt;
+    const typename V4<T>::type me = x.Lc[i];
+    const double xi = x.X[i], yi = x.X[vt + i], zi = x.X[2 * vt + i];
+    if (ne <= 2) {
+        edge_entry<T>(P, sp, x, tl, i, k0, nvap, me, xi, yi, zi, a);
+        if (ne == 2) edge_entry<T>(P, sp, x, tl, i, k1, nvap, me, xi, yi, zi, a);
+        return;
+    }
+    for (int k = 0; k < nall; ++k) edge_entry<T>(P, sp, x, tl, i, k, nvap, me, xi, yi, zi, a);
 }
 
 // F3 (second half-kick) and, unless the run ends, F2 of the next step (first
@@ -1245,7 +1262,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_step(PoolDev P, int kk)
         // with indices clamped to valid memory (list rows past the end of this
         // atom's list exist up to the capacity; their values are not used), so
         // the code is straight-line and each wait covers only the loads it needs
-        bool edge = false;
+        int ne = 0, ke0 = 0, ke1 = 0;  // cutoff-band entries: count, first two list positions
         const int lastrow = P.cap - 1;
         unsigned ec[kGroup];
 #pragma unroll
@@ -1264,7 +1281,9 @@ __global__ void __launch_bounds__(kMaxBlock) k_step(PoolDev P, int kk)
                 const T dz = me.z - o.z + shift_of<T>(e, 4, x.hz);
                 const T r2 = dx * dx + dy * dy + dz * dz;
                 const bool near = live && sizeof(T) == 4 && fabs(r2 - x.rc2) < x.band;
-                edge |= near;
+                ke0 = (near && ne == 0) ? k0 + u : ke0;
+                ke1 = (near && ne == 1) ? k0 + u : ke1;
+                ne += near ? 1 : 0;
                 if (live && r2 < x.rc2 && !near) pair_term<T>(x, a, dx, dy, dz, r2, false);
             }
 #pragma unroll
@@ -1292,13 +1311,15 @@ __global__ void __launch_bounds__(kMaxBlock) k_step(PoolDev P, int kk)
                 const T dz = me.z - o.z + shift_of<T>(e, 4, x.hz);
                 const T r2 = dx * dx + dy * dy + dz * dz;
                 const bool near = live && sizeof(T) == 4 && fabs(r2 - x.rc2) < x.band;
-                edge |= near;
+                ke0 = (near && ne == 0) ? k0 + u : ke0;
+                ke1 = (near && ne == 1) ? k0 + u : ke1;
+                ne += near ? 1 : 0;
                 if (live && r2 < x.rc2 && !near) pair_term<T>(x, a, dx, dy, dz, r2, true);
             }
 #pragma unroll
             for (int u = 0; u < kGroup; ++u) ec[u] = en[u];
         }
-        if (edge) edge_pass<T>(P, sp, x, tl, i, nvap, nall, a);
+        if (ne) edge_pass<T>(P, sp, x, tl, i, nvap, nall, ne, ke0, ke1, a);
         evv += 0.5 * a.ev;
         evw += a.ew;
         ke += atom_epilogue<T>(P, x, i, a, flags);
