@@ -938,7 +938,10 @@ __device__ void record_energies(const PoolDev& P, const SysParams& sp, int s, in
     __syncthreads();
 }
 
-constexpr int kGroup = 6;  // list entries fetched together in the step kernel
+constexpr int kGroupV = 6;  // vapour list entries fetched together in the step kernel
+// wall list entries (and wall positions) fetched together: 8 FP32 positions,
+// 6 FP64 ones (8 would spill the FP64 kernel's registers)
+template <typename T> constexpr int kGroupW = sizeof(T) == 4 ? 8 : 6;
 
 
 
@@ -1253,26 +1256,26 @@ __global__ void __launch_bounds__(kMaxBlock) k_step(PoolDev P, int kk)
         const int nvap = nl & 0xFFFF, nall = nvap + (nl >> 16);
         Acc a{0.0, 0.0, 0.0, 0.0, 0.0};
         const unsigned* lst = P.list + i;
-        // entries come kGroup at a time, the next group's loads in flight while
-        // the current one is evaluated; vapour partners are read from LDS,
-        // wall partners from global memory.  Pairs whose FP32 r^2 lies within
-        // a narrow band around the cutoff are left out here and decided in
-        // FP64 after the whole list (a rare slow path: a few atoms per step),
-        // so the per-pair code has no branch.  Every load is unconditional,
+        // entries come kGroupV (vapour) or kGroupW<T> (walls) at a time, the next
+        // group's loads in flight while the current one is evaluated; vapour
+        // partners are read from LDS, wall partners from global memory.  Pairs
+        // whose FP32 r^2 lies within a narrow band around the cutoff are left
+        // out here and decided in FP64 after the whole list (a rare slow path:
+        // a few atoms per step), so the per-pair code has no branch.  Every load is unconditional,
         // with indices clamped to valid memory (list rows past the end of this
         // atom's list exist up to the capacity; their values are not used), so
         // the code is straight-line and each wait covers only the loads it needs
         int ne = 0, ke0 = 0, ke1 = 0;  // cutoff-band entries: count, first two list positions
         const int lastrow = P.cap - 1;
-        unsigned ec[kGroup];
+        unsigned ec[kGroupV];
 #pragma unroll
-        for (int u = 0; u < kGroup; ++u) ec[u] = lst[(size_t)min(u, lastrow) * vt];
-        for (int k0 = 0; k0 < nvap; k0 += kGroup) {
-            unsigned en[kGroup];
+        for (int u = 0; u < kGroupV; ++u) ec[u] = lst[(size_t)min(u, lastrow) * vt];
+        for (int k0 = 0; k0 < nvap; k0 += kGroupV) {
+            unsigned en[kGroupV];
 #pragma unroll
-            for (int u = 0; u < kGroup; ++u) en[u] = lst[(size_t)min(k0 + kGroup + u, lastrow) * vt];
+            for (int u = 0; u < kGroupV; ++u) en[u] = lst[(size_t)min(k0 + kGroupV + u, lastrow) * vt];
 #pragma unroll
-            for (int u = 0; u < kGroup; ++u) {
+            for (int u = 0; u < kGroupV; ++u) {
                 const bool live = k0 + u < nvap;
                 const unsigned e = ec[u];
                 const V o = tl.pos[live ? (int)(e & kIndexMask) : 0];
@@ -1287,37 +1290,38 @@ __global__ void __launch_bounds__(kMaxBlock) k_step(PoolDev P, int kk)
                 if (live && r2 < x.rc2 && !near) pair_term<T>(x, a, dx, dy, dz, r2, false);
             }
 #pragma unroll
-            for (int u = 0; u < kGroup; ++u) ec[u] = en[u];
+            for (int u = 0; u < kGroupV; ++u) ec[u] = en[u];
         }
         if (nall > nvap) {
+            unsigned cw[kGroupW<T>];
 #pragma unroll
-            for (int u = 0; u < kGroup; ++u) ec[u] = lst[(size_t)min(nvap + u, lastrow) * vt];
-        }
-        for (int k0 = nvap; k0 < nall; k0 += kGroup) {
-            V ow[kGroup];
+            for (int u = 0; u < kGroupW<T>; ++u) cw[u] = lst[(size_t)min(nvap + u, lastrow) * vt];
+            for (int k0 = nvap; k0 < nall; k0 += kGroupW<T>) {
+                V ow[kGroupW<T>];
 #pragma unroll
-            for (int u = 0; u < kGroup; ++u)
-                ow[u] = x.Lc[vt + (k0 + u < nall ? (int)(ec[u] & kIndexMask) : 0)];
-            unsigned en[kGroup];
+                for (int u = 0; u < kGroupW<T>; ++u)
+                    ow[u] = x.Lc[vt + (k0 + u < nall ? (int)(cw[u] & kIndexMask) : 0)];
+                unsigned nw[kGroupW<T>];
 #pragma unroll
-            for (int u = 0; u < kGroup; ++u) en[u] = lst[(size_t)min(k0 + kGroup + u, lastrow) * vt];
+                for (int u = 0; u < kGroupW<T>; ++u) nw[u] = lst[(size_t)min(k0 + kGroupW<T> + u, lastrow) * vt];
 #pragma unroll
-            for (int u = 0; u < kGroup; ++u) {
-                const bool live = k0 + u < nall;
-                const unsigned e = ec[u];
-                const V o = ow[u];
-                const T dx = me.x - o.x + shift_of<T>(e, 0, x.hx);
-                const T dy = me.y - o.y + shift_of<T>(e, 2, x.hy);
-                const T dz = me.z - o.z + shift_of<T>(e, 4, x.hz);
-                const T r2 = dx * dx + dy * dy + dz * dz;
-                const bool near = live && sizeof(T) == 4 && fabs(r2 - x.rc2) < x.band;
-                ke0 = (near && ne == 0) ? k0 + u : ke0;
-                ke1 = (near && ne == 1) ? k0 + u : ke1;
-                ne += near ? 1 : 0;
-                if (live && r2 < x.rc2 && !near) pair_term<T>(x, a, dx, dy, dz, r2, true);
+                for (int u = 0; u < kGroupW<T>; ++u) {
+                    const bool live = k0 + u < nall;
+                    const unsigned e = cw[u];
+                    const V o = ow[u];
+                    const T dx = me.x - o.x + shift_of<T>(e, 0, x.hx);
+                    const T dy = me.y - o.y + shift_of<T>(e, 2, x.hy);
+                    const T dz = me.z - o.z + shift_of<T>(e, 4, x.hz);
+                    const T r2 = dx * dx + dy * dy + dz * dz;
+                    const bool near = live && sizeof(T) == 4 && fabs(r2 - x.rc2) < x.band;
+                    ke0 = (near && ne == 0) ? k0 + u : ke0;
+                    ke1 = (near && ne == 1) ? k0 + u : ke1;
+                    ne += near ? 1 : 0;
+                    if (live && r2 < x.rc2 && !near) pair_term<T>(x, a, dx, dy, dz, r2, true);
+                }
+#pragma unroll
+                for (int u = 0; u < kGroupW<T>; ++u) cw[u] = nw[u];
             }
-#pragma unroll
-            for (int u = 0; u < kGroup; ++u) ec[u] = en[u];
         }
         if (ne) edge_pass<T>(P, sp, x, tl, i, nvap, nall, ne, ke0, ke1, a);
         evv += 0.5 * a.ev;
