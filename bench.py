@@ -38,10 +38,10 @@ PEAK_HBM_GBS = 8000.0
 # the lists are rebuilt, not what one step launch reads and writes.  Any
 # other source, workload or tuning reports null.
 MEASURED_TRAFFIC = {
-    ("c8adee643b55b995", 262144, 0.7, 256, 270): 107.17e6,
-    ("c8adee643b55b995", 262144, 0.7, 256, 256): 109.80e6,
-    ("c8adee643b55b995", 262144, 0.7, 512, 460): 100.38e6,
-    ("c8adee643b55b995", 262144, 0.7, 256, 0): 106.80e6,
+    ("e7d51af79b9b5a11", 262144, 0.7, 256, 270): 107.81e6,
+    ("e7d51af79b9b5a11", 262144, 0.7, 256, 256): 110.47e6,
+    ("e7d51af79b9b5a11", 262144, 0.7, 512, 460): 101.04e6,
+    ("e7d51af79b9b5a11", 262144, 0.7, 256, 0): 107.47e6,
 }
 
 
