@@ -784,6 +784,9 @@ __global__ void __launch_bounds__(kMaxBlock) k_list_build(PoolDev P)
     // the rounding of the local coordinates)
     const double cull_v = sp.rl2 * (1.0 + 1e-6), cull_w = sp.rw2 * (1.0 + 1e-6);
     const int cap = P.cap;
+    // wall candidates loaded together: 12 FP32 positions, 8 FP64 ones (12
+    // would spill the FP64 kernel's registers)
+    constexpr int kWallRound = sizeof(T) == 4 ? 12 : 8;
     int mx = 0;
     for (int i = i0 + (int)threadIdx.x; i < i1; i += blockDim.x) {
         const V me = Lc[i];
@@ -828,14 +831,14 @@ __global__ void __launch_bounds__(kMaxBlock) k_list_build(PoolDev P)
             const int w0 = wrange[2 * h], w1 = wrange[2 * h + 1];
             if (w0 >= w1) continue;
             const T sx = (T)(-dx * sp.h[0]), sy = (T)(-dy * sp.h[1]), sz = (T)(-dz * sp.h[2]);
-            // eight candidates per round, loads issued together (indices
+            // kWallRound candidates per round, loads issued together (indices
             // clamped to the cell's last wall)
-            for (int w = w0; w < w1; w += 8) {
-                V o[8];
+            for (int w = w0; w < w1; w += kWallRound) {
+                V o[kWallRound];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) o[u] = Lw[min(w + u, w1 - 1)];
+                for (int u = 0; u < kWallRound; ++u) o[u] = Lw[min(w + u, w1 - 1)];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
+                for (int u = 0; u < kWallRound; ++u) {
                     const T ex = me.x - o[u].x + sx, ey = me.y - o[u].y + sy, ez = me.z - o[u].z + sz;
                     if (w + u < w1 && ex * ex + ey * ey + ez * ez < rw2) {
                         if (nv + nw < cap)
