@@ -449,7 +449,27 @@ __global__ void k_bin_count(PoolDev P)
         cell = sp.nkey;  // padding slots gather in one extra cell
     }
     P.cell_tmp[c.i] = cell;
-    P.arr[c.i] = atomicAdd(&P.count[sp.coff + cell], 1);
+    // One atomic per distinct cell of the wave (atoms arrive cell-sorted from
+    // the last rebuild, so a wave holds a few cells): the lowest lane of each
+    // cell adds the cell's lane count, and each lane's arrival rank is the
+    // returned base plus its rank among the cell's lanes.  The ranks are
+    // unique within a cell, which is all the placement needs.
+    const int g = sp.coff + cell;  // count index, distinct across systems
+    const int lane = (int)(threadIdx.x & 63);
+    unsigned long long todo = __ballot(1);
+    int base = 0, rank = 0, lead = lane;
+    while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const int key = __shfl(g, leader, 64);
+        const unsigned long long m = __ballot(g == key);
+        if (g == key) {
+            rank = __popcll(m & ((1ull << lane) - 1ull));
+            lead = leader;
+            if (lane == leader) base = atomicAdd(&P.count[key], __popcll(m));
+        }
+        todo &= ~m;
+    }
+    P.arr[c.i] = __shfl(base, lead, 64) + rank;
 }
 
 // One workgroup (1024 threads x 4 cells) per scan tile writes the exclusive
