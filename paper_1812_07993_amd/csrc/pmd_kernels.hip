@@ -556,7 +556,18 @@ __global__ void k_bin_place(PoolDev P)
     const int* ids = P.id[st.ibuf_prev];
     const int myid = ids[o];
     int rank = 0;
-    for (int q = b0; q < b1; ++q) rank += (ids[P.tmp[q]] < myid);
+    // the cell's arrivals eight at a time, loads issued together (indices
+    // clamped to the cell's last arrival)
+    for (int q = b0; q < b1; q += 8) {
+        int t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) t[u] = P.tmp[min(q + u, b1 - 1)];
+        int idq[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) idq[u] = ids[t[u]];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) rank += (q + u < b1 && idq[u] < myid) ? 1 : 0;
+    }
     const int d = b0 + rank;
     const double* Xs = P.X[src];
     const double* Vs = P.V[src];
