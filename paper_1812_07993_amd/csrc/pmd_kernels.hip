@@ -824,6 +824,11 @@ __global__ void __launch_bounds__(kMaxBlock) k_list_build(PoolDev P)
         const int cr = P.cref[i];
         const int cx = cr & 1023, cy = (cr >> 10) & 1023, cz = cr >> 20;
         const double lx = (double)me.x, ly = (double)me.y, lz = (double)me.z;
+        // the atom's own staged index (its cell's atoms are staged in slot
+        // order; with at least 3 cells per axis the 27 cells are distinct, so
+        // this is its only copy in the tile)
+        const int hs = halo_cell(g, cx, cy, cz, 13);
+        const int aself = t.hoff[hs] + (i - t.hbeg[hs]);
         int nv = 0;
         for (int q = 0; q < 27; ++q) {
             const int dx = q % 3 - 1, dy = (q / 3) % 3 - 1, dz = q / 9 - 1;
@@ -835,16 +840,12 @@ __global__ void __launch_bounds__(kMaxBlock) k_list_build(PoolDev P)
             const int a1 = t.hoff[h + 1];
             for (int a = t.hoff[h]; a < a1; a += 4) {
                 V o[4];
-                int sl[4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    o[u] = t.pos[min(a + u, a1 - 1)];
-                    sl[u] = t.slot[min(a + u, a1 - 1)];
-                }
+                for (int u = 0; u < 4; ++u) o[u] = t.pos[min(a + u, a1 - 1)];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const T ex = me.x - o[u].x + sx, ey = me.y - o[u].y + sy, ez = me.z - o[u].z + sz;
-                    if (a + u < a1 && ex * ex + ey * ey + ez * ez < rl2 && sl[u] != i) {
+                    if (a + u < a1 && ex * ex + ey * ey + ez * ez < rl2 && a + u != aself) {
                         if (nv < cap)
                             P.list[(size_t)nv * vt + i] = (unsigned)(a + u) | (offset_code(q) << kIndexBits);
                         ++nv;
