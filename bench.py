@@ -94,15 +94,27 @@ def autotune(poremd, desc, prec, trial_steps, tuning_kw):
     out = dict(skin=float(b.skin), rebin_every=int(b.rebin_every))
     if tuning_kw.get("block") or tuning_kw.get("brick_atoms"):
         return out
-    # second stage: workgroup size and atoms per brick at the chosen skin and period
+    # second stage: workgroup size and atoms per brick, jointly with the three
+    # fastest (skin, period) pairs of the first stage (which ran at the
+    # default shape, so its ranking can change with the shape)
     shapes = [(256, 0), (256, 256), (256, 270), (256, 160), (512, 460), (128, 0)]
-    cands = [poremd.make_tuning(skin=b.skin, rebin_every=b.rebin_every, block=bl, brick_atoms=ba)
-             for bl, ba in shapes]
+    pairs = []
+    for i in order:
+        sr = (float(grid[i].skin), int(grid[i].rebin_every))
+        if sr not in pairs:
+            pairs.append(sr)
+        if len(pairs) == 3:
+            break
+    combos = [(sk, rb, bl, ba) for sk, rb in pairs for bl, ba in shapes]
+    cands = [poremd.make_tuning(skin=sk, rebin_every=rb, block=bl, brick_atoms=ba)
+             for sk, rb, bl, ba in combos]
     best2, us2 = poremd.pmd_autotune(params, pore, desc.x, desc.v, cands, trial_steps)
     log("[%s] autotune shapes: %s" % (prec, ", ".join(
-        "(%d, %d) %.2f" % (bl, ba, u) for (bl, ba), u in zip(shapes, us2))))
-    out.update(block=shapes[best2][0], brick_atoms=shapes[best2][1])
-    return out
+        "(%.2f, %d, %d, %d) %.2f" % (c + (u,)) for c, u in zip(combos, us2))))
+    sk, rb, bl, ba = combos[best2]
+    log("[%s] autotune choice: skin %.2f, rebuild every %d, block %d, atoms per brick %d: %.2f us/step"
+        % (prec, sk, rb, bl, ba, us2[best2]))
+    return dict(skin=sk, rebin_every=rb, block=bl, brick_atoms=ba)
 
 
 def run_path(poremd, desc, prec, steps, warmup, energy_every, tuning_kw):
