@@ -32,16 +32,19 @@ PEAK_HBM_GBS = 8000.0
 
 # HBM bytes per k_step<float> launch from the FETCH_SIZE / WRITE_SIZE counter
 # passes summarised in profiles/k_step_slit128_mixed.md (128^3 slit workload,
-# skin 0.7), keyed by the hash of the device sources they were taken on, the
+# skins 0.7 and 1.0), keyed by the hash of the device sources they were taken on, the
 # vapour atom count, the skin and the workgroup shape (block, target atoms per
 # brick).  The rebuild period is not part of the key: it changes how often
 # the lists are rebuilt, not what one step launch reads and writes.  Any
 # other source, workload or tuning reports null.
 MEASURED_TRAFFIC = {
-    ("e7d51af79b9b5a11", 262144, 0.7, 256, 270): 107.81e6,
-    ("e7d51af79b9b5a11", 262144, 0.7, 256, 256): 110.47e6,
-    ("e7d51af79b9b5a11", 262144, 0.7, 512, 460): 101.04e6,
-    ("e7d51af79b9b5a11", 262144, 0.7, 256, 0): 107.47e6,
+    ("af3f145bfe7eda14", 262144, 0.7, 256, 270): 107.75e6,
+    ("af3f145bfe7eda14", 262144, 0.7, 256, 256): 110.42e6,
+    ("af3f145bfe7eda14", 262144, 0.7, 512, 460): 101.02e6,
+    ("af3f145bfe7eda14", 262144, 0.7, 256, 0): 107.41e6,
+    ("af3f145bfe7eda14", 262144, 1.0, 256, 270): 114.72e6,
+    ("af3f145bfe7eda14", 262144, 1.0, 512, 460): 102.14e6,
+    ("af3f145bfe7eda14", 262144, 1.0, 256, 0): 115.49e6,
 }
 
 
