@@ -213,3 +213,30 @@ def test_invalid_inputs_rejected():
     small_box = poremd.make_params(7.0, "fp64")
     with pytest.raises(poremd.PmdError):
         poremd.System(small_box, pore, np.array([[1.0, 2.0, 3.0]]), np.zeros((1, 3)))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_pairs_at_the_cutoff(prec):
+    """A simple cubic lattice of spacing r_c, each site moved by at most 2e-6:
+    every atom has six partners within the band around the cutoff where the
+    mixed path leaves the decision to FP64 (more than the two entries the
+    pair loops record, so the pass rescans the list), each on either side
+    of r_c at random (the closest lies 4e-9 from r_c^2, far beyond FP64
+    rounding).  Forces against the oracle's all-pairs sums."""
+    rc, m = 2.5, 10
+    L = rc * m
+    g = (np.arange(m) + 0.5) * rc
+    x = np.stack(np.meshgrid(g, g, g, indexing="ij"), axis=-1).reshape(-1, 3)
+    rng = np.random.default_rng(21)
+    x = x + rng.uniform(-2e-6, 2e-6, size=x.shape)
+    v = np.zeros_like(x)
+    s = make(x, v, L, synth.Pore("none"), prec)
+    p = oracle.make_params(L)
+    Fr, _, _ = oracle.forces(x, None, p)
+    d = x[:, None, :] - x[None, :, :]
+    d -= L * np.rint(d / L)
+    r2 = (d * d).sum(-1)
+    inside = (r2 < rc * rc) & (r2 > 0)
+    assert 0 < inside.sum() < 6 * len(x)  # both sides of r_c occur
+    assert rel(s.forces(), Fr) <= TOL_F[prec]
+    s.close()
