@@ -135,9 +135,10 @@ struct PoolDev {
     int* arr;             // arrival rank within the cell (per slot)
     int* tmp;             // slots in arrival order
     int* cell_tmp;        // cell key of each old slot
-    // neighbour lists, entry k of slot i at k * vt + i: vapour entries index
-    // the brick's staged tile, wall entries are wall slots; both carry the
-    // cell-offset code above kIndexBits.  nlist = n_vapour | n_wall << 16
+    // neighbour lists, entry k of slot i at ((k / 4) * vt + i) * 4 + k % 4
+    // (chunks of four entries per slot): vapour entries index the brick's
+    // staged tile, wall entries are wall slots; both carry the cell-offset
+    // code above kIndexBits.  nlist = n_vapour | n_wall << 16
     unsigned* list;
     int* nlist;
     // walls

@@ -56,6 +56,17 @@ __device__ __forceinline__ T shift_of(unsigned e, int bit, T h)
     return fma(-b, h, h);
 }
 
+// Storage index of neighbour-list entry k of slot i.  Entries are kept in
+// chunks of four consecutive entries of one atom; chunk c of every slot is
+// contiguous (16 bytes per slot, stride vt), so a lane's four entries are one
+// 16-byte load, a wave's chunk loads cover one contiguous 1 KB, and the list
+// build's writes of one atom fill a 16-byte piece instead of one word in each
+// of four rows.  The capacity is a multiple of four entries.
+__device__ __forceinline__ size_t list_at(int vt, int i, int k)
+{
+    return (((size_t)(k >> 2) * vt + i) << 2) + (k & 3);
+}
+
 __device__ __forceinline__ int wrap_cell(int c, int n)
 {
     c += (c < 0) ? n : 0;
@@ -847,7 +858,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_list_build(PoolDev P)
                     const T ex = me.x - o[u].x + sx, ey = me.y - o[u].y + sy, ez = me.z - o[u].z + sz;
                     if (a + u < a1 && ex * ex + ey * ey + ez * ez < rl2 && a + u != aself) {
                         if (nv < cap)
-                            P.list[(size_t)nv * vt + i] = (unsigned)(a + u) | (offset_code(q) << kIndexBits);
+                            P.list[list_at(vt, i, nv)] = (unsigned)(a + u) | (offset_code(q) << kIndexBits);
                         ++nv;
                     }
                 }
@@ -874,7 +885,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_list_build(PoolDev P)
                     const T ex = me.x - o[u].x + sx, ey = me.y - o[u].y + sy, ez = me.z - o[u].z + sz;
                     if (w + u < w1 && ex * ex + ey * ey + ez * ez < rw2) {
                         if (nv + nw < cap)
-                            P.list[(size_t)(nv + nw) * vt + i] =
+                            P.list[list_at(vt, i, nv + nw)] =
                                 (unsigned)(w + u) | (offset_code(q) << kIndexBits);
                         ++nw;
                     }
@@ -973,7 +984,7 @@ __device__ void record_energies(const PoolDev& P, const SysParams& sp, int s, in
     __syncthreads();
 }
 
-constexpr int kGroupV = 6;  // vapour list entries fetched together in the step kernel
+constexpr int kGroupV = 4;  // vapour list entries fetched together in the step kernel (multiple of 4)
 // wall list entries (and wall positions) fetched together: 8 FP32 positions,
 // 6 FP64 ones (8 would spill the FP64 kernel's registers)
 template <typename T> constexpr int kGroupW = sizeof(T) == 4 ? 8 : 6;
@@ -1100,7 +1111,7 @@ __device__ __forceinline__ void edge_entry(const PoolDev& P, const SysParams& sp
 {
     using V = typename V4<T>::type;
     const int vt = P.vt;
-    const unsigned e = P.list[(size_t)k * vt + i];
+    const unsigned e = P.list[list_at(vt, i, k)];
     const bool wall = k >= nvap;
     const int ai = (int)(e & kIndexMask);
     const V o = wall ? x.Lc[vt + ai] : tl.pos[ai];
@@ -1290,25 +1301,35 @@ __global__ void __launch_bounds__(kMaxBlock) k_step(PoolDev P, int kk)
         const int nl = P.nlist[i];
         const int nvap = nl & 0xFFFF, nall = nvap + (nl >> 16);
         Acc a{0.0, 0.0, 0.0, 0.0, 0.0};
-        const unsigned* lst = P.list + i;
-        // entries come kGroupV (vapour) or kGroupW<T> (walls) at a time, the next
-        // group's loads in flight while the current one is evaluated; vapour
-        // partners are read from LDS, wall partners from global memory.  Pairs
-        // whose FP32 r^2 lies within a narrow band around the cutoff are left
-        // out here and decided in FP64 after the whole list (a rare slow path:
-        // a few atoms per step), so the per-pair code has no branch.  Every load is unconditional,
-        // with indices clamped to valid memory (list rows past the end of this
+        // entries come kGroupV (vapour, as kGroupV / 4 chunk loads) or
+        // kGroupW<T> (walls) at a time, the next group's loads in flight while
+        // the current one is evaluated; vapour partners are read from LDS, wall
+        // partners from global memory.  Pairs whose FP32 r^2 lies within a
+        // narrow band around the cutoff are left out here and decided in FP64
+        // after the whole list (a rare slow path: a few atoms per step), so
+        // the per-pair code has no branch.  Every load is unconditional, with
+        // indices clamped to valid memory (list chunks past the end of this
         // atom's list exist up to the capacity; their values are not used), so
         // the code is straight-line and each wait covers only the loads it needs
         int ne = 0, ke0 = 0, ke1 = 0;  // cutoff-band entries: count, first two list positions
-        const int lastrow = P.cap - 1;
-        unsigned ec[kGroupV];
+        const int lastrow = P.cap - 1, lastchunk = P.cap / 4 - 1;
+        const uint4* lst4 = (const uint4*)P.list + i;  // chunk c of this atom at lst4[c * vt]
+        constexpr int NC = kGroupV / 4;
+        uint4 cc[NC];
 #pragma unroll
-        for (int u = 0; u < kGroupV; ++u) ec[u] = lst[(size_t)min(u, lastrow) * vt];
+        for (int c = 0; c < NC; ++c) cc[c] = lst4[(size_t)min(c, lastchunk) * vt];
         for (int k0 = 0; k0 < nvap; k0 += kGroupV) {
-            unsigned en[kGroupV];
+            uint4 cn[NC];
 #pragma unroll
-            for (int u = 0; u < kGroupV; ++u) en[u] = lst[(size_t)min(k0 + kGroupV + u, lastrow) * vt];
+            for (int c = 0; c < NC; ++c) cn[c] = lst4[(size_t)min((k0 >> 2) + NC + c, lastchunk) * vt];
+            unsigned ec[kGroupV];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                ec[4 * c] = cc[c].x;
+                ec[4 * c + 1] = cc[c].y;
+                ec[4 * c + 2] = cc[c].z;
+                ec[4 * c + 3] = cc[c].w;
+            }
 #pragma unroll
             for (int u = 0; u < kGroupV; ++u) {
                 const bool live = k0 + u < nvap;
@@ -1325,12 +1346,12 @@ __global__ void __launch_bounds__(kMaxBlock) k_step(PoolDev P, int kk)
                 if (live && r2 < x.rc2 && !near) pair_term<T>(x, a, dx, dy, dz, r2, false);
             }
 #pragma unroll
-            for (int u = 0; u < kGroupV; ++u) ec[u] = en[u];
+            for (int c = 0; c < NC; ++c) cc[c] = cn[c];
         }
         if (nall > nvap) {
             unsigned cw[kGroupW<T>];
 #pragma unroll
-            for (int u = 0; u < kGroupW<T>; ++u) cw[u] = lst[(size_t)min(nvap + u, lastrow) * vt];
+            for (int u = 0; u < kGroupW<T>; ++u) cw[u] = P.list[list_at(vt, i, min(nvap + u, lastrow))];
             for (int k0 = nvap; k0 < nall; k0 += kGroupW<T>) {
                 V ow[kGroupW<T>];
 #pragma unroll
@@ -1338,7 +1359,8 @@ __global__ void __launch_bounds__(kMaxBlock) k_step(PoolDev P, int kk)
                     ow[u] = x.Lc[vt + (k0 + u < nall ? (int)(cw[u] & kIndexMask) : 0)];
                 unsigned nw[kGroupW<T>];
 #pragma unroll
-                for (int u = 0; u < kGroupW<T>; ++u) nw[u] = lst[(size_t)min(k0 + kGroupW<T> + u, lastrow) * vt];
+                for (int u = 0; u < kGroupW<T>; ++u)
+                    nw[u] = P.list[list_at(vt, i, min(k0 + kGroupW<T> + u, lastrow))];
 #pragma unroll
                 for (int u = 0; u < kGroupW<T>; ++u) {
                     const bool live = k0 + u < nall;
@@ -1550,7 +1572,7 @@ __global__ void k_debug_pairs(PoolDev P, int slot, int* out, int cap, int* count
         const int nvap = nl & 0xFFFF, n = nvap + (nl >> 16);
         const double xi = X[i], yi = X[vt + i], zi = X[2 * vt + i];
         for (int k = 0; k < n; ++k) {
-            const unsigned e = P.list[(size_t)k * vt + i];
+            const unsigned e = P.list[list_at(vt, i, k)];
             const int a = (int)(e & kIndexMask);
             double ox, oy, oz;
             int kind, bb;
