@@ -38,13 +38,13 @@ PEAK_HBM_GBS = 8000.0
 # the lists are rebuilt, not what one step launch reads and writes.  Any
 # other source, workload or tuning reports null.
 MEASURED_TRAFFIC = {
-    ("af3f145bfe7eda14", 262144, 0.7, 256, 270): 107.75e6,
-    ("af3f145bfe7eda14", 262144, 0.7, 256, 256): 110.42e6,
-    ("af3f145bfe7eda14", 262144, 0.7, 512, 460): 101.02e6,
-    ("af3f145bfe7eda14", 262144, 0.7, 256, 0): 107.41e6,
-    ("af3f145bfe7eda14", 262144, 1.0, 256, 270): 114.72e6,
-    ("af3f145bfe7eda14", 262144, 1.0, 512, 460): 102.14e6,
-    ("af3f145bfe7eda14", 262144, 1.0, 256, 0): 115.49e6,
+    ("57b1e6e775edcec0", 262144, 0.7, 512, 460): 92.52e6,
+    ("57b1e6e775edcec0", 262144, 0.7, 256, 270): 95.83e6,
+    ("57b1e6e775edcec0", 262144, 0.7, 256, 256): 98.86e6,
+    ("57b1e6e775edcec0", 262144, 0.7, 256, 0): 96.87e6,
+    ("57b1e6e775edcec0", 262144, 1.0, 256, 270): 101.98e6,
+    ("57b1e6e775edcec0", 262144, 1.0, 512, 460): 92.81e6,
+    ("57b1e6e775edcec0", 262144, 1.0, 256, 0): 102.82e6,
 }
 
 
