@@ -67,7 +67,7 @@ def _load():
     lib.orc_forces.argtypes = [i64, vp, i64, vp, P(Params), vp, P(d), P(d), vp]
     lib.orc_forces_subset.argtypes = [i64, vp, i64, vp, P(Params), i64, vp, vp, vp]
     lib.orc_run.argtypes = [i64, vp, vp, vp, ctypes.c_int, i64, vp, P(Params),
-                            i64, i64, vp]
+                            i64, i64, vp, d, d]
     lib.orc_run.restype = i64
     lib.orc_wall_lattice.argtypes = [P(Pore), vp, vp, i64]
     lib.orc_wall_lattice.restype = i64
@@ -154,10 +154,12 @@ def forces_subset(x, walls, params: Params, sel):
     return F, pe
 
 
-def run(x, v, walls, params: Params, nsteps: int, every=1, a=None):
-    """Velocity Verlet for nsteps (F2, F1, F3).  Returns (x, v, a, energies)
-    with energies rows (ke, pe_vv, pe_vw) at step 0, every `every` steps and
-    at the last step."""
+def run(x, v, walls, params: Params, nsteps: int, every=1, a=None, tau=0.0, t0=0.0):
+    """Velocity Verlet for nsteps (F2, F1, F3; with tau > 0 also F4, the
+    Berendsen scaling towards temperature t0 with rise time tau, Sec. 2 and
+    Sec. 3).  Returns (x, v, a, energies) with energies rows (ke, pe_vv,
+    pe_vw) at step 0, every `every` steps and at the last step (ke as the
+    thermostat measured it, before its scaling)."""
     x = _f64(x, (-1, 3)).copy()
     v = _f64(v, (-1, 3)).copy()
     w = _f64(walls if walls is not None else np.zeros((0, 3)), (-1, 3))
@@ -168,7 +170,7 @@ def run(x, v, walls, params: Params, nsteps: int, every=1, a=None):
     rows = _load().orc_run(x.shape[0], _ptr(x), _ptr(v), _ptr(acc),
                            int(have_a), w.shape[0], _ptr(w),
                            ctypes.byref(params), int(nsteps), int(every),
-                           _ptr(E))
+                           _ptr(E), float(tau), float(t0))
     return x, v, acc, E[:rows]
 
 

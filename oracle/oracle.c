@@ -29,16 +29,19 @@
  *   - vapour-wall pairs use (sig_w, eps_w) with the same r_c; wall-wall pairs
  *     are never evaluated; walls never move;
  *   - minimum-image periodic boundaries on all three axes; positions are
- *     wrapped into [0, L) after each drift.
+ *     wrapped into [0, L) after each drift;
+ *   - Berendsen factor lambda = sqrt(1 + (dt/tau)(t0/T - 1)) with
+ *     T = 2K / (3N - 3), applied after F3 (the paper gives the rise time and
+ *     the per-step scaling, not the formula).
  *
  * Determinism: every per-particle sum runs over partners in ascending index
  * order (vapour first, then walls), and every total is summed serially in
  * ascending particle order, so results do not depend on the OpenMP thread
  * count.
  *
- * Parity status: the pair term, the force sum, the integrator, the wall
- * lattice, the cell sort and the pair sets are each pinned by tests against
- * closed forms, invariants or brute force.  Long-run physical observables
+ * Parity status: the pair term, the force sum, the integrator, the
+ * Berendsen step, the wall lattice, the cell sort and the pair sets are each
+ * pinned by tests against closed forms, invariants or brute force.  Long-run physical observables
  * (adsorption, density profiles) are parity unpinned: the paper prints none.
  */
 #include <math.h>
@@ -284,10 +287,19 @@ static double wrap(double x, double L)
  *   F2: r(t+dt) = r(t) + v(t) dt + a(t) dt^2 / 2,  v(t+dt/2) = v(t) + a(t) dt/2,
  *       then r is wrapped into the periodic box;
  *   F1: a(t+dt) = f(r(t+dt)) / m;
- *   F3: v(t+dt) = v(t+dt/2) + a(t+dt) dt/2. */
+ *   F3: v(t+dt) = v(t+dt/2) + a(t+dt) dt/2;
+ *   F4 (only if tau > 0; Berendsen thermostat, Sec. 2 and the F4 listing of
+ *       Sec. 3): T = 2 K / (3 nv - 3) from the F3 velocities, then
+ *       v <- lambda v with lambda = sqrt(1 + (dt / tau) (t0 / T - 1)).  The
+ *       paper names the thermostat, its rise time tau and the scaling of
+ *       every velocity by lambda(t) each step, but not the formula for
+ *       lambda: this is Berendsen's weak-coupling factor.  The recorded
+ *       kinetic energy of a step is the one the thermostat measured (before
+ *       the scaling). */
 int64_t orc_run(int64_t nv, double *x, double *v, double *a, int have_a,
                 int64_t nw, const double *xw, const orc_params *p,
-                int64_t nsteps, int64_t every_k, double *energies)
+                int64_t nsteps, int64_t every_k, double *energies,
+                double tau, double t0)
 {
     double dt = p->dt, m = p->mass, evv = 0.0, evw = 0.0;
     double *F = (double *)malloc(sizeof(double) * 3 * (size_t)(nv > 0 ? nv : 1));
@@ -316,12 +328,19 @@ int64_t orc_run(int64_t nv, double *x, double *v, double *a, int have_a,
             a[q] = F[q] / m;
             v[q] = v[q] + 0.5 * a[q] * dt;
         }
+        double ke = kinetic(nv, v, m);
         int record = energies && ((every_k > 0 && n % every_k == 0) || n == nsteps);
         if (record) {
-            energies[3 * rows + 0] = kinetic(nv, v, m);
+            energies[3 * rows + 0] = ke;
             energies[3 * rows + 1] = evv;
             energies[3 * rows + 2] = evw;
             ++rows;
+        }
+        if (tau > 0.0) {
+            double dof = nv > 1 ? 3.0 * (double)nv - 3.0 : 3.0;
+            double T = 2.0 * ke / dof;
+            double lam = sqrt(1.0 + (dt / tau) * (t0 / T - 1.0));
+            for (int64_t q = 0; q < 3 * nv; ++q) v[q] = lam * v[q];
         }
     }
     free(F);

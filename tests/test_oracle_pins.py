@@ -281,6 +281,58 @@ def test_time_reversibility():
     assert np.abs(v2 + v).max() < 1e-8
 
 
+# --------------------------------------------------------------------------
+# Berendsen thermostat (F4)
+# --------------------------------------------------------------------------
+
+def test_berendsen_free_gas_relaxes_geometrically():
+    """With the pair forces switched off (epsilon = 0) the velocities change
+    only by F4, so the temperature the thermostat measures obeys
+    T_n - t0 = (1 - dt / tau) (T_(n-1) - t0): T_n = t0 + (T_0 - t0)(1 - dt/tau)^n,
+    the discrete form of dT/dt = (t0 - T) / tau (Berendsen's coupling).  The
+    temperature recorded at step n is measured before that step's scaling,
+    after n - 1 of them."""
+    L, n = 20.0, 300
+    rng = np.random.default_rng(4)
+    x = rng.uniform(0.0, L, size=(n, 3))
+    v = rng.normal(0.0, 1.0, size=(n, 3))
+    v -= v.mean(axis=0)
+    p = oracle.make_params(L, epsilon=0.0)
+    dof = 3 * n - 3
+    T0 = 2.0 * 0.5 * np.sum(v * v) / dof
+    tau, t0, steps = 0.1, 2.0, 80
+    _, v1, _, E = oracle.run(x, v, None, p, steps, every=1, tau=tau, t0=t0)
+    T = 2.0 * E[:, 0] / dof
+    k = np.maximum(np.arange(steps + 1) - 1, 0)
+    want = t0 + (T0 - t0) * (1.0 - p.dt / tau) ** k
+    assert np.allclose(T, want, rtol=1e-12, atol=0.0)
+    # the returned velocities carry all `steps` scalings
+    T_end = 2.0 * 0.5 * np.sum(v1 * v1) / dof
+    assert T_end == pytest.approx(t0 + (T0 - t0) * (1.0 - p.dt / tau) ** steps, rel=1e-12)
+    # momentum stays zero: the scaling is one factor for every atom
+    assert np.abs(v1.sum(axis=0)).max() < 1e-11
+
+
+def test_berendsen_weak_coupling_is_the_nve_run():
+    """A rise time so long that lambda rounds to 1 reproduces the run without
+    the thermostat bit for bit (F4 touches nothing else)."""
+    x, v, walls, p = small_system(n=120, L=12.0)
+    a1 = oracle.run(x, v, walls, p, 40)
+    a2 = oracle.run(x, v, walls, p, 40, tau=1e30, t0=1.5)
+    for u, w in zip(a1, a2):
+        assert np.array_equal(u, w)
+
+
+def test_berendsen_drives_an_interacting_system_to_t0():
+    """With forces on, a weak coupling (tau = 20 dt) brings the temperature
+    from 1.2 near t0 = 2.0 within 400 steps."""
+    x, v, walls, p = small_system(n=150, L=12.0)
+    _, _, _, E = oracle.run(x, v, walls, p, 400, every=1, tau=0.1, t0=2.0)
+    T = 2.0 * E[:, 0] / (3 * 150 - 3)
+    assert abs(T[-50:].mean() - 2.0) < 0.1
+    assert T[0] < 1.6
+
+
 def energy_drift(tot, burn=100, window=1000):
     """Drift measures used throughout: the least-squares trend of E_n over
     `window` steps after `burn` steps, times the window, relative to
