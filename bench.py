@@ -150,6 +150,37 @@ def run_path(poremd, desc, prec, steps, warmup, energy_every, tuning_kw):
     return out
 
 
+def thermostat_leg(poremd, desc, steps, tuning_kw, tau=0.5, t0=1.2):
+    """The 128^3 slit workload in mixed precision with the Berendsen
+    thermostat on (rise time tau = 100 dt, target t0 = T* = 1.2), at the NVE
+    path's tuning: the cost of the F4 step (two extra launches per step)."""
+    import torch
+
+    params, pore = poremd.params_of(desc, "mixed")
+    params.thermostat_tau, params.thermostat_t0 = tau, t0
+    stream = torch.cuda.Stream()
+    tun = poremd.make_tuning(energy_every=10, **tuning_kw)
+    s = poremd.System(params, pore, desc.x, desc.v, None, stream.cuda_stream, tun)
+    s.step(max(steps // 10, 10))
+    s.sync()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    s.step(steps)
+    s.sync()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    T_end = float(s.energies()["temperature"])
+    s.close()
+    out = {"value": desc.n * steps / (ms / 1000.0), "unit": "atom-steps/s",
+           "ms_per_step": ms / steps, "steps": steps, "tau": tau, "t0": t0,
+           "temperature_end": T_end}
+    log("[thermostat] %d steps: %.2f us/step, T = %.4f" % (steps, 1000 * ms / steps, T_end))
+    return out
+
+
 def kernel_time(poremd, s, steps):
     """Mean duration of one step-kernel launch, from HIP events around the R
     back-to-back launches of each replay that did R full steps."""
@@ -319,6 +350,8 @@ def main():
     ap.add_argument("--sweep-steps", type=int, default=500)
     ap.add_argument("--sweep-only", action="store_true",
                     help="run only the 4M-atom pore leg (for profiling it)")
+    ap.add_argument("--thermostat-steps", type=int, default=2000,
+                    help="steps of the 128^3 workload with the Berendsen thermostat on (0: skip)")
     ap.add_argument("--serve-chunk", type=int, default=250)
     ap.add_argument("--timing-steps", type=int, default=500)
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -446,6 +479,9 @@ def main():
         out["mixed_over_fp64"] = out["value"] / out["fp64"]["value"]
     for r in res.values():
         r["sys"].close()
+    if args.thermostat_steps > 0:
+        out["thermostat"] = thermostat_leg(poremd, desc, args.thermostat_steps, tuned["mixed"])
+        out["thermostat"]["over_nve"] = out["thermostat"]["value"] / out["value"]
     if args.sweep != "none":
         out["pore_sweep"] = pore_sweep_leg(poremd, args.sweep.split(","), args.sweep_steps,
                                            0 if (args.skin or args.rebin_every)

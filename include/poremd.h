@@ -72,6 +72,13 @@ typedef struct {
                              PMD_MIXED = pair forces in FP32, per-particle
                              force sums, integration and energies in FP64 */
     int32_t reserved;
+    /* Berendsen thermostat (Sec. 2; the F4 listing of Sec. 3): with
+     * thermostat_tau > 0 every step ends with v <- lambda v, lambda =
+     * sqrt(1 + (dt / tau) (t0 / T - 1)), T = 2 ke / (3 n - 3) measured on the
+     * full-step velocities (the recorded ke is this one, before the
+     * scaling).  0 = off (NVE).  Requires tau >= dt and t0 > 0. */
+    double thermostat_tau;
+    double thermostat_t0;
 } pmd_params;
 
 /* Pore geometry.  Wall sites sit on a simple cubic lattice of spacing
@@ -156,7 +163,8 @@ int pmd_create_system(const pmd_params *params, const pmd_pore *pore,
                       const pmd_tuning *tuning, pmd_system **out);
 
 /* Queue nsteps velocity-Verlet steps (each: F2 drift and half-kick, F1
- * forces, F3 half-kick).  Asynchronous; pmd_sync or any readback waits. */
+ * forces, F3 half-kick, and with a thermostat the F4 scaling, Sec. 3).
+ * Asynchronous; pmd_sync or any readback waits. */
 int pmd_step(pmd_system *sys, int64_t nsteps);
 
 /* Wait until every queued step has been done.  Returns PMD_ENUMERIC if a

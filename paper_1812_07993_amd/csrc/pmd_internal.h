@@ -66,7 +66,8 @@ struct SysParams {
     double dt, mass, inv_mass;
     double rw2;            // wall-list radius^2, (r_c + skin/2)^2
     float half_skin;       // rebuild threshold on the travelled path
-    float pad1;
+    int thermo;            // 1: Berendsen thermostat on
+    double tau_t, t0, dof; // its rise time, target temperature, 3 nv - 3
 };
 
 // Per-system dynamic state, written by kernels.
@@ -87,6 +88,7 @@ struct SysState {
     int steps_since;  // steps since the last rebuild
     int stop;         // first step of the current replay that raised a stop bit (INT_MAX: none)
     long long step;   // completed steps
+    double lambda;    // Berendsen factor of the current step
 };
 
 struct EnergyRec {
@@ -118,6 +120,8 @@ struct PoolDev {
     int vt, wt;           // vapour and wall slot capacity
     int cap;              // neighbour-list capacity per atom
     int nbt;              // brick capacity (stride of the two energy-partial slots)
+    int nslots;           // system slots
+    int thermo;           // 1 if a resident system has the thermostat on
     // per-atom state, double buffered by SysState::sbuf; SoA with stride vt
     double* X[2];
     double* V[2];

@@ -1003,6 +1003,7 @@ template <typename T>
 struct StepCtx {
     using V = typename V4<T>::type;
     bool init, last, doE;
+    bool thermo;           // Berendsen thermostat: the step ends in k_thermo
     int lbuf;
     const V* Lc;           // local coordinates read this step (walls at vt + w)
     const double* X;       // positions and velocities at the start of the step
@@ -1037,7 +1038,9 @@ __device__ __forceinline__ StepCtx<T> step_ctx(const PoolDev& P, const SysParams
     x.init = st.phase == PH_INIT;
     x.last = !x.init && kk == st.remaining - 1;
     const long long kstep = x.init ? st.step : st.step + kk + 1;
-    x.doE = step_records(sp, x.init, x.last, kstep);
+    x.thermo = !x.init && sp.thermo;
+    // the thermostat needs every step's kinetic energy
+    x.doE = step_records(sp, x.init, x.last, kstep) || x.thermo;
     x.lbuf = st.lbuf ^ (kk & 1);
     x.Lc = (const typename V4<T>::type*)P.L[x.lbuf];
     // positions and velocities: read from one buffer, written to the other,
@@ -1182,7 +1185,10 @@ __device__ double atom_epilogue(const PoolDev& P, const StepCtx<T>& x, int i,
     }
     const double kei = 0.5 * x.mass * (vx * vx + vy * vy + vz * vz);
     if (!x.init) {
-        if (x.last) {
+        // the last step of a run, and every step under the thermostat (whose
+        // scaling needs the whole system's temperature first), stores the
+        // full-step state; k_thermo then scales v and drifts
+        if (x.last || x.thermo) {
             x.Xn[i] = xi;
             x.Xn[vt + i] = yi;
             x.Xn[2 * vt + i] = zi;
@@ -1435,6 +1441,97 @@ __global__ void __launch_bounds__(256) k_commit(PoolDev P, int nslots, int R)
     if (last) sw->phase = PH_REST;
 }
 
+// ---------------------------------------------------------------------------
+// Berendsen thermostat (F4): after step kk's forces and second half-kick,
+// lambda from the step's temperature, then v <- lambda v and, unless the run
+// ends, the next step's first half-kick and drift.
+// ---------------------------------------------------------------------------
+
+// One workgroup per system: the temperature of step kk from its kinetic
+// energy partials (summed in brick order), and the factor
+// lambda = sqrt(1 + (dt / tau) (t0 / T - 1)).
+__global__ void __launch_bounds__(256) k_lambda(PoolDev P, int kk)
+{
+    __shared__ double red[kMaxBlock / 64];
+    const int s = blockIdx.x;
+    if (s >= P.nslots) return;
+    const SysParams& sp = P.sp[s];
+    const SysState st = P.st[s];
+    if (!sp.active || !sp.thermo || st.phase == PH_INIT || kk >= st.remaining || kk > st.stop ||
+        (st.status & (ST_OVERFLOW | ST_NONFINITE | ST_STALL)))
+        return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
+    const double* pp = P.partial + 3 * ((size_t)(kk & 1) * P.nbt + sp.pboff);
+    double ke = 0.0;
+    for (int q = tid; q < sp.nbrick; q += blockDim.x) ke += pp[3 * q];
+    ke = wave_sum(ke);
+    if (lane == 0) red[wave] = ke;
+    __syncthreads();
+    if (tid != 0) return;
+    ke = 0.0;
+    for (int w = 0; w < nwave; ++w) ke += red[w];
+    const double T = 2.0 * ke / sp.dof;
+    const double l2 = 1.0 + (sp.dt / sp.tau_t) * (sp.t0 / T - 1.0);
+    P.st[s].lambda = sqrt(l2 > 0.0 ? l2 : 0.0);
+}
+
+// Per atom: v <- lambda v on the full-step velocities that k_step stored,
+// then (unless this is the run's last step) v += a dt/2, x += v dt, wrap, new
+// local coordinates and travelled path, exactly as the fused step epilogue
+// does without the thermostat.
+template <typename T>
+__global__ void k_thermo(PoolDev P, int kk)
+{
+    using V = typename V4<T>::type;
+    SlotCtx c;
+    if (!rebuild_ctx(P, c)) return;
+    const SysParams& sp = P.sp[c.s];
+    const SysState st = P.st[c.s];
+    if (!sp.thermo || st.phase == PH_INIT || kk >= st.remaining || kk > st.stop ||
+        (st.status & ST_OVERFLOW) || c.li >= sp.nv)
+        return;
+    const int vt = P.vt, i = c.i;
+    const int xb = st.sbuf ^ (kk & 1) ^ 1;  // the buffer k_step wrote this step
+    double* X = P.X[xb];
+    double* Vv = P.V[xb];
+    const double lam = st.lambda;
+    double vx = lam * Vv[i], vy = lam * Vv[vt + i], vz = lam * Vv[2 * vt + i];
+    if (kk == st.remaining - 1) {
+        Vv[i] = vx;
+        Vv[vt + i] = vy;
+        Vv[2 * vt + i] = vz;
+        return;
+    }
+    const double hdt = 0.5 * sp.dt;
+    vx += hdt * P.A[i];
+    vy += hdt * P.A[vt + i];
+    vz += hdt * P.A[2 * vt + i];
+    const double xx = wrap_box(X[i] + vx * sp.dt, sp.L[0]);
+    const double yy = wrap_box(X[vt + i] + vy * sp.dt, sp.L[1]);
+    const double zz = wrap_box(X[2 * vt + i] + vz * sp.dt, sp.L[2]);
+    Vv[i] = vx;
+    Vv[vt + i] = vy;
+    Vv[2 * vt + i] = vz;
+    X[i] = xx;
+    X[vt + i] = yy;
+    X[2 * vt + i] = zz;
+    const int cr = P.cref[i];
+    const int cx = cr & 1023, cy = (cr >> 10) & 1023, cz = cr >> 20;
+    V* Ln = (V*)P.L[st.lbuf ^ (kk & 1) ^ 1];
+    Ln[i] = make4<T>(local_axis(xx, cx, sp.h[0], sp.L[0], sp.invL[0]),
+                     local_axis(yy, cy, sp.h[1], sp.L[1], sp.invL[1]),
+                     local_axis(zz, cz, sp.h[2], sp.L[2], sp.invL[2]));
+    const float tr = P.travel[i] + (float)(sqrt(vx * vx + vy * vy + vz * vz) * sp.dt);
+    P.travel[i] = tr;
+    int f = tr > sp.half_skin ? ST_HALT : 0;
+    if (!isfinite(xx + yy + zz + vx + vy + vz)) f |= ST_NONFINITE;
+    if (f) {
+        // rare: an early rebuild (or a failure) after this step
+        atomicOr(&P.st[c.s].status_next, f);
+        atomicMin(&P.st[c.s].stop, kk);
+    }
+}
+
 hipError_t launch_step(const PoolDev& P, int kk, int precision, hipStream_t s, hipEvent_t ev0,
                        hipEvent_t ev1)
 {
@@ -1452,6 +1549,14 @@ hipError_t launch_step(const PoolDev& P, int kk, int precision, hipStream_t s, h
             hipLaunchKernelGGL(k_step<float>, dim3(G), dim3(B), lds, s, P, kk);
         else
             hipLaunchKernelGGL(k_step<double>, dim3(G), dim3(B), lds, s, P, kk);
+    }
+    if (P.thermo) {
+        hipLaunchKernelGGL(k_lambda, dim3(P.nslots), dim3(256), 0, s, P, kk);
+        const int GT = ((P.nchunk / (kRebuildBlock / kChunk) + 7) / 8) * 8;
+        if (precision == 1)
+            hipLaunchKernelGGL(k_thermo<float>, dim3(GT), dim3(kRebuildBlock), 0, s, P, kk);
+        else
+            hipLaunchKernelGGL(k_thermo<double>, dim3(GT), dim3(kRebuildBlock), 0, s, P, kk);
     }
     return hipGetLastError();
 }

@@ -93,6 +93,11 @@ int check_params(const pmd_params* p, const pmd_pore* q)
         return fail(PMD_EINVAL, "sigma_wall must be > 0 and epsilon_wall >= 0");
     if (p->precision != PMD_FP64 && p->precision != PMD_MIXED)
         return fail(PMD_EINVAL, "precision must be PMD_FP64 or PMD_MIXED");
+    if (!(p->thermostat_tau >= 0) || !std::isfinite(p->thermostat_tau))
+        return fail(PMD_EINVAL, "thermostat_tau must be >= 0 (0: off)");
+    if (p->thermostat_tau > 0 && (!(p->thermostat_tau >= p->dt) || !(p->thermostat_t0 > 0) ||
+                                  !std::isfinite(p->thermostat_t0)))
+        return fail(PMD_EINVAL, "a thermostat needs thermostat_tau >= dt and thermostat_t0 > 0");
     if (q->kind < PMD_PORE_NONE || q->kind > PMD_PORE_INKBOTTLE) return fail(PMD_EINVAL, "unknown pore kind %d", q->kind);
     if (q->kind != PMD_PORE_NONE) {
         if (!(q->lattice_a > 0)) return fail(PMD_EINVAL, "lattice_a must be > 0");
@@ -219,6 +224,7 @@ struct Pool {
     int brick_order = kDefaultBrickOrder;
     int cap = 64;
     int vt = 0, wt = 0, ct = 0, wct = 0, nbt = 0, nslots = 0, ering_cap = kDefaultErings;
+    int thermo = 0;  // a resident system has the thermostat on
     size_t bytes = 0;
     // device arrays
     SysParams* d_sp = nullptr;
@@ -326,6 +332,8 @@ struct Pool {
         d.wt = wt;
         d.cap = cap;
         d.nbt = nbt;
+        d.nslots = nslots;
+        d.thermo = thermo;
         for (int b = 0; b < 2; ++b) {
             d.X[b] = X[b];
             d.V[b] = V[b];
@@ -502,6 +510,9 @@ int pool_layout(Pool& p)
     p.nchunk = (int)p.hchunk.size();
     p.ntile = (int)p.htile.size();
     p.nbrick = (int)p.hbrick.size();
+    p.thermo = 0;
+    for (int s = 0; s < p.nslots; ++s)
+        if (p.hsp[s].active && p.hsp[s].thermo) p.thermo = 1;
     p.hmax = std::max(hmax, 1);
     const size_t ab = tile_atom_bytes(p.precision);
     const size_t ints = (size_t)(2 * p.hmax + 1) * 4;
@@ -615,6 +626,10 @@ void fill_sys_params(SysParams& sp, const pmd_params& p, const Grid& g, const pm
     sp.inv_mass = 1.0 / p.mass;
     sp.half_skin = (float)(0.5 * t.skin * (1.0 - 1e-3));
     sp.energy_every = t.energy_every;
+    sp.thermo = p.thermostat_tau > 0 ? 1 : 0;
+    sp.tau_t = p.thermostat_tau;
+    sp.t0 = p.thermostat_t0;
+    sp.dof = nv > 1 ? 3.0 * nv - 3.0 : 3.0;
     sp.active = 1;
     choose_bricks(sp, brick_target > 0 ? brick_target : t.brick_atoms > 0 ? t.brick_atoms : 0.8 * t.block,
                   tile_atom_bytes(p.precision));

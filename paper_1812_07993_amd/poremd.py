@@ -33,7 +33,8 @@ class pmd_params(ctypes.Structure):
                 ("epsilon", ctypes.c_double), ("mass", ctypes.c_double),
                 ("cutoff", ctypes.c_double), ("dt", ctypes.c_double),
                 ("sigma_wall", ctypes.c_double), ("epsilon_wall", ctypes.c_double),
-                ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("thermostat_tau", ctypes.c_double), ("thermostat_t0", ctypes.c_double)]
 
 
 class pmd_pore(ctypes.Structure):
@@ -149,7 +150,8 @@ def _ptr(a):
 # ---------------------------------------------------------------------------
 
 def make_params(box, precision="fp64", sigma=1.0, epsilon=1.0, mass=1.0, cutoff=2.5,
-                dt=0.005, sigma_wall=1.0, epsilon_wall=1.5) -> pmd_params:
+                dt=0.005, sigma_wall=1.0, epsilon_wall=1.5, thermostat_tau=0.0,
+                thermostat_t0=0.0) -> pmd_params:
     p = pmd_params()
     b = np.broadcast_to(np.asarray(box, dtype=np.float64), (3,))
     for k in range(3):
@@ -157,6 +159,7 @@ def make_params(box, precision="fp64", sigma=1.0, epsilon=1.0, mass=1.0, cutoff=
     p.sigma, p.epsilon, p.mass, p.cutoff, p.dt = sigma, epsilon, mass, cutoff, dt
     p.sigma_wall, p.epsilon_wall = sigma_wall, epsilon_wall
     p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    p.thermostat_tau, p.thermostat_t0 = thermostat_tau, thermostat_t0
     return p
 
 
