@@ -69,6 +69,7 @@ def _load():
     lib.orc_run.argtypes = [i64, vp, vp, vp, ctypes.c_int, i64, vp, P(Params),
                             i64, i64, vp, d, d]
     lib.orc_run.restype = i64
+    lib.orc_virial.argtypes = [i64, vp, i64, vp, P(Params), P(d), P(d)]
     lib.orc_wall_lattice.argtypes = [P(Pore), vp, vp, i64]
     lib.orc_wall_lattice.restype = i64
     lib.orc_cell_sort.argtypes = [i64, vp, vp, vp, vp, vp, vp]
@@ -172,6 +173,18 @@ def run(x, v, walls, params: Params, nsteps: int, every=1, a=None, tau=0.0, t0=0
                            ctypes.byref(params), int(nsteps), int(every),
                            _ptr(E), float(tau), float(t0))
     return x, v, acc, E[:rows]
+
+
+def virial(x, walls, params: Params):
+    """Virial sums (w_vv, w_vw) of the pressure formula (Sec. 2): sum over
+    vapour pairs i < j and over vapour-wall pairs of r_ij . f_ij (f the force
+    on the first atom, minimum image, inside the cutoff)."""
+    x = _f64(x, (-1, 3))
+    w = _f64(walls if walls is not None else np.zeros((0, 3)), (-1, 3))
+    wvv, wvw = ctypes.c_double(), ctypes.c_double()
+    _load().orc_virial(x.shape[0], _ptr(x), w.shape[0], _ptr(w), ctypes.byref(params),
+                       ctypes.byref(wvv), ctypes.byref(wvw))
+    return wvv.value, wvw.value
 
 
 def wall_lattice(pore: Pore, box):

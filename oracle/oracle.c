@@ -40,8 +40,9 @@
  * count.
  *
  * Parity status: the pair term, the force sum, the integrator, the
- * Berendsen step, the wall lattice, the cell sort and the pair sets are each
- * pinned by tests against closed forms, invariants or brute force.  Long-run physical observables
+ * Berendsen step, the virial sums, the wall lattice, the cell sort and the
+ * pair sets are each pinned by tests against closed forms, invariants or
+ * brute force.  Long-run physical observables
  * (adsorption, density profiles) are parity unpinned: the paper prints none.
  */
 #include <math.h>
@@ -345,6 +346,38 @@ int64_t orc_run(int64_t nv, double *x, double *v, double *a, int have_a,
     }
     free(F);
     return rows;
+}
+
+/* Virial sums of the pressure formula (Sec. 2): w_vv = sum over vapour
+ * pairs i < j of r_ij . f_ij, with r_ij = r_i - r_j (minimum image) and f_ij
+ * the force on i from j (positive for repulsion); w_vw = the same sum over
+ * vapour-wall pairs, f the force on the vapour atom.  Pairs contribute only
+ * inside the cutoff, like the forces.  The pressure reads
+ * P = (2K + w_vv) / (3V): the paper writes the pair term with a minus sign,
+ * which matches a force f(r) = du/dr; here f is the force itself.  Summed
+ * serially in ascending index order. */
+void orc_virial(int64_t nv, const double *xv, int64_t nw, const double *xw,
+                const orc_params *p, double *wvv, double *wvw)
+{
+    double svv = 0.0, svw = 0.0;
+    for (int64_t i = 0; i < nv; ++i) {
+        for (int64_t j = i + 1; j < nv; ++j) {
+            double d[3], u, w;
+            min_image(xv + 3 * i, xv + 3 * j, p->box, d);
+            double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            lj_pair(r2, p->sigma, p->epsilon, p->cutoff, &u, &w);
+            svv += w * r2;
+        }
+        for (int64_t k = 0; k < nw; ++k) {
+            double d[3], u, w;
+            min_image(xv + 3 * i, xw + 3 * k, p->box, d);
+            double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            lj_pair(r2, p->sigma_wall, p->epsilon_wall, p->cutoff, &u, &w);
+            svw += w * r2;
+        }
+    }
+    *wvv = svv;
+    *wvw = svw;
 }
 
 /* ---------------------------------------------------------------------- */

@@ -333,6 +333,49 @@ def test_berendsen_drives_an_interacting_system_to_t0():
     assert T[0] < 1.6
 
 
+# --------------------------------------------------------------------------
+# Virial sums (pressure formula)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("r", [1.0, 1.1, R_MIN, 1.5, 2.4, 2.6])
+def test_virial_dimer_closed_form(r):
+    """r . f for one pair: 48 eps (s/r)^12 - 24 eps (s/r)^6 inside the
+    cutoff (positive when repulsive), zero beyond it."""
+    p = oracle.make_params(40.0, sigma=1.0, epsilon=1.0)
+    x = np.array([[10.0, 20.0, 20.0], [10.0 + r, 20.0, 20.0]])
+    wvv, wvw = oracle.virial(x, None, p)
+    want = 48.0 * r ** -12 - 24.0 * r ** -6 if r < 2.5 else 0.0
+    assert wvv == pytest.approx(want, rel=1e-13, abs=1e-12)
+    assert wvw == 0.0
+
+
+def test_virial_is_minus_the_energy_derivative_under_scaling():
+    """Scaling every coordinate by lambda scales every distance: the sum of
+    r . f equals -dU/dlambda at lambda = 1, for the vapour pairs and (walls
+    scaled too) for the vapour-wall pairs; central difference of the pinned
+    energies, no pair within 1e-3 of the cutoff."""
+    L = 200.0
+    rng = np.random.default_rng(8)
+    xv = synth.rsa_place(rng, (8.0, 8.0, 8.0), 60, np.zeros((0, 3)), 0.95) + 96.0
+    xw = synth.rsa_place(rng, (8.0, 8.0, 8.0), 20, xv - 96.0, 0.95) + 96.0
+    p = oracle.make_params(L)
+    d = xv[:, None, :] - np.concatenate([xv, xw])[None, :, :]
+    r = np.sqrt((d * d).sum(-1))
+    assert np.all(np.abs(r - 2.5) > 1e-3)
+    c = np.array([100.0, 100.0, 100.0])
+    h = 1e-6
+
+    def energies(lam):
+        _, evv, evw = oracle.forces(c + lam * (xv - c), c + lam * (xw - c), p)
+        return evv, evw
+
+    up, dn = energies(1.0 + h), energies(1.0 - h)
+    wvv, wvw = oracle.virial(xv, xw, p)
+    assert wvv == pytest.approx(-(up[0] - dn[0]) / (2 * h), rel=1e-6)
+    assert wvw == pytest.approx(-(up[1] - dn[1]) / (2 * h), rel=1e-6)
+    assert abs(wvv) > 1.0 and abs(wvw) > 0.1
+
+
 def energy_drift(tot, burn=100, window=1000):
     """Drift measures used throughout: the least-squares trend of E_n over
     `window` steps after `burn` steps, times the window, relative to
