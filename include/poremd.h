@@ -101,10 +101,16 @@ typedef struct {
 
 /* Energies at one step (per system).  ke = (m/2) sum |v|^2 at the full
  * step; pe_vv = sum over vapour pairs i<j; pe_vw = sum over vapour-wall
- * pairs; temperature = 2 ke / (3 n - 3). */
+ * pairs; temperature = 2 ke / (3 n - 3).  virial_vv = sum over vapour pairs
+ * i<j inside the cutoff of r_ij . f_ij (r_ij = r_i - r_j, minimum image;
+ * f_ij the force on i from j, positive when repulsive), virial_vw the same
+ * over vapour-wall pairs: the pressure of the formula in Sec. 2 is
+ * P = (2 ke + virial_vv) / (3 V) for the caller's volume V (the pore volume
+ * in the paper); the wall term is reported beside it. */
 typedef struct {
     int64_t step;
     double ke, pe_vv, pe_vw, etotal, temperature;
+    double virial_vv, virial_vw;
 } pmd_energies;
 
 /* Performance knobs; zero fields take the library default.  skin: extra

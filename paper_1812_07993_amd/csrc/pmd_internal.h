@@ -94,7 +94,11 @@ struct SysState {
 struct EnergyRec {
     long long step;
     double ke, pe_vv, pe_vw;
+    double w_vv, w_vw;  // virial sums r . f over vapour pairs and vapour-wall pairs
 };
+
+// Energy partials per brick and step slot: ke, pe_vv, pe_vw, w_vv, w_vw.
+constexpr int kPartial = 5;
 
 typedef float f4 __attribute__((ext_vector_type(4)));   // 16 bytes, one 128-bit load
 typedef double d4 __attribute__((ext_vector_type(4)));  // 32 bytes
@@ -150,7 +154,7 @@ struct PoolDev {
     int* wid;             // canonical wall index of each sorted wall slot
     int* wcstart;         // wall cell_start (global wall slots)
     // energies
-    double* partial;      // 3 doubles per brick, two slots (step parity)
+    double* partial;      // kPartial doubles per brick, two slots (step parity)
     EnergyRec* erec;
 };
 

@@ -944,40 +944,42 @@ __device__ __forceinline__ bool step_records(const SysParams& sp, bool init, boo
 // Sum one step's per-brick energy partials in brick order (fixed, so the
 // total is deterministic) and append the record.  Called by a whole
 // workgroup; the partials were written by an earlier launch.
-__device__ void record_energies(const PoolDev& P, const SysParams& sp, int s, int ring, long long kstep)
+// red: workgroup scratch of kPartial x (waves) doubles.
+typedef double Red[kPartial][kMaxBlock / 64];
+
+__device__ void record_energies(const PoolDev& P, const SysParams& sp, int s, int ring, long long kstep,
+                                Red& red)
 {
-    __shared__ double red[3][kMaxBlock / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
-    const double* pp = P.partial + 3 * ((size_t)ring * P.nbt + sp.pboff);
-    double a = 0.0, b = 0.0, cc = 0.0;
-    for (int q = tid; q < sp.nbrick; q += blockDim.x) {
-        a += pp[3 * q];
-        b += pp[3 * q + 1];
-        cc += pp[3 * q + 2];
+    const double* pp = P.partial + kPartial * ((size_t)ring * P.nbt + sp.pboff);
+    double v[kPartial];
+#pragma unroll
+    for (int q = 0; q < kPartial; ++q) v[q] = 0.0;
+    for (int b = tid; b < sp.nbrick; b += blockDim.x) {
+#pragma unroll
+        for (int q = 0; q < kPartial; ++q) v[q] += pp[kPartial * b + q];
     }
-    a = wave_sum(a);
-    b = wave_sum(b);
-    cc = wave_sum(cc);
-    if (lane == 0) {
-        red[0][wave] = a;
-        red[1][wave] = b;
-        red[2][wave] = cc;
+#pragma unroll
+    for (int q = 0; q < kPartial; ++q) {
+        const double t = wave_sum(v[q]);
+        if (lane == 0) red[q][wave] = t;
     }
     __syncthreads();
     if (tid == 0) {
-        a = b = cc = 0.0;
-        for (int w = 0; w < nwave; ++w) {
-            a += red[0][w];
-            b += red[1][w];
-            cc += red[2][w];
+        double t[kPartial];
+        for (int q = 0; q < kPartial; ++q) {
+            t[q] = 0.0;
+            for (int w = 0; w < nwave; ++w) t[q] += red[q][w];
         }
         SysState* sw = P.st + s;
         const int n = sw->nrec;
         EnergyRec r;
         r.step = kstep;
-        r.ke = a;
-        r.pe_vv = b;
-        r.pe_vw = cc;
+        r.ke = t[0];
+        r.pe_vv = t[1];
+        r.pe_vw = t[2];
+        r.w_vv = t[3];
+        r.w_vw = t[4];
         P.erec[sp.ering_off + (n % sp.ering_cap)] = r;
         sw->nrec = n + 1;
     }
@@ -1082,6 +1084,7 @@ __device__ __forceinline__ StepCtx<T> step_ctx(const PoolDev& P, const SysParams
 // Per-atom force and energy sums (FP64).
 struct Acc {
     double fx, fy, fz, ev, ew;
+    double wv, ww;  // virial sums r . f (vapour and wall partners)
 };
 
 // One in-cutoff pair: FP32 (mixed) or FP64 LJ, FP64 sums.
@@ -1097,10 +1100,14 @@ __device__ __forceinline__ void pair_term(const StepCtx<T>& x, Acc& a, T dx, T d
     a.fz += (double)(w * dz);
     if (x.doE) {
         const double u_ = (double)(sr6 * (A * sr6 - B) - (wall ? x.ucw : x.ucv));
-        if (wall)
+        const double v_ = (double)(w * r2);  // r . f of the pair
+        if (wall) {
             a.ew += u_;
-        else
+            a.ww += v_;
+        } else {
             a.ev += u_;
+            a.wv += v_;
+        }
     }
 }
 
@@ -1230,21 +1237,19 @@ __device__ double atom_epilogue(const PoolDev& P, const StepCtx<T>& x, int i,
 // Workgroup reductions in a fixed order (lane tree, then waves in order):
 // status bits to the system, energies to the brick's partial of slot kk & 1.
 __device__ void step_reduce(const PoolDev& P, const SysParams& sp, int s, int b, int kk, bool doE,
-                            int flags, double ke, double evv, double evw)
+                            int flags, double ke, double evv, double evw, double wvv, double wvw,
+                            Red& red)
 {
-    __shared__ double red[3][kMaxBlock / 64];
     __shared__ int flag_or[kMaxBlock / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
     flags = wave_or(flags);
     if (lane == 0) flag_or[wave] = flags;
     if (doE) {
-        ke = wave_sum(ke);
-        evv = wave_sum(evv);
-        evw = wave_sum(evw);
-        if (lane == 0) {
-            red[0][wave] = ke;
-            red[1][wave] = evv;
-            red[2][wave] = evw;
+        const double v[kPartial] = {ke, evv, evw, wvv, wvw};
+#pragma unroll
+        for (int q = 0; q < kPartial; ++q) {
+            const double t = wave_sum(v[q]);
+            if (lane == 0) red[q][wave] = t;
         }
     }
     __syncthreads();
@@ -1256,16 +1261,12 @@ __device__ void step_reduce(const PoolDev& P, const SysParams& sp, int s, int b,
             if (f & (ST_HALT | ST_NONFINITE | ST_OVERFLOW)) atomicMin(&P.st[s].stop, kk);
         }
         if (doE) {
-            double a = 0.0, bb = 0.0, cc = 0.0;
-            for (int w = 0; w < nwave; ++w) {
-                a += red[0][w];
-                bb += red[1][w];
-                cc += red[2][w];
+            double* pp = P.partial + kPartial * ((size_t)(kk & 1) * P.nbt + sp.pboff + b);
+            for (int q = 0; q < kPartial; ++q) {
+                double t = 0.0;
+                for (int w = 0; w < nwave; ++w) t += red[q][w];
+                pp[q] = t;
             }
-            double* pp = P.partial + 3 * ((size_t)(kk & 1) * P.nbt + sp.pboff + b);
-            pp[0] = a;
-            pp[1] = bb;
-            pp[2] = cc;
         }
     }
 }
@@ -1276,6 +1277,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_step(PoolDev P, int kk)
     using V = typename V4<T>::type;
     extern __shared__ __align__(32) unsigned char smem[];
     __shared__ int lds_scan[17];
+    __shared__ Red red;  // the energy reductions at the start and the end
 
     BrickCtx c;
     if (!brick_ctx(P, c, ST_OVERFLOW | ST_NONFINITE)) return;
@@ -1290,7 +1292,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_step(PoolDev P, int kk)
     // the system's first brick records the previous step's energies
     if (c.b == 0 && kk > 0) {
         const long long kprev = st.step + kk;
-        if (step_records(sp, false, false, kprev)) record_energies(P, sp, s, (kk - 1) & 1, kprev);
+        if (step_records(sp, false, false, kprev)) record_energies(P, sp, s, (kk - 1) & 1, kprev, red);
     }
     const HaloGeo g = halo_geo(sp, c.b);
     Tile<T> tl = tile_of<T>(smem, P);
@@ -1300,13 +1302,13 @@ __global__ void __launch_bounds__(kMaxBlock) k_step(PoolDev P, int kk)
     const int key0 = c.b * sp.bcells;
     const int i0 = P.cstart[sp.coff + key0], i1 = P.cstart[sp.coff + key0 + sp.bcells];
 
-    double ke = 0.0, evv = 0.0, evw = 0.0;
+    double ke = 0.0, evv = 0.0, evw = 0.0, wvv = 0.0, wvw = 0.0;
     int flags = tot < 0 ? (ST_OVERFLOW | ST_TILE) : 0;
     for (int i = i0 + tid; tot >= 0 && i < i1; i += blockDim.x) {
         const V me = x.Lc[i];
         const int nl = P.nlist[i];
         const int nvap = nl & 0xFFFF, nall = nvap + (nl >> 16);
-        Acc a{0.0, 0.0, 0.0, 0.0, 0.0};
+        Acc a{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         // entries come kGroupV (vapour, as kGroupV / 4 chunk loads) or
         // kGroupW<T> (walls) at a time, the next group's loads in flight while
         // the current one is evaluated; vapour partners are read from LDS, wall
@@ -1389,9 +1391,11 @@ __global__ void __launch_bounds__(kMaxBlock) k_step(PoolDev P, int kk)
         if (ne) edge_pass<T>(P, sp, x, tl, i, nvap, nall, ne, ke0, ke1, a);
         evv += 0.5 * a.ev;
         evw += a.ew;
+        wvv += 0.5 * a.wv;
+        wvw += a.ww;
         ke += atom_epilogue<T>(P, x, i, a, flags);
     }
-    step_reduce(P, sp, s, c.b, kk, x.doE, flags, ke, evv, evw);
+    step_reduce(P, sp, s, c.b, kk, x.doE, flags, ke, evv, evw, wvv, wvw, red);
 }
 
 // End of a replay, one workgroup per system: count the steps the replay
@@ -1419,7 +1423,8 @@ __global__ void __launch_bounds__(256) k_commit(PoolDev P, int nslots, int R)
     const int kl = done - 1;  // last step of the replay
     const bool last = !init && kl == st.remaining - 1;
     const long long kstep = init ? st.step : st.step + kl + 1;
-    if (step_records(sp, init, last, kstep)) record_energies(P, sp, s, kl & 1, kstep);
+    __shared__ Red red;
+    if (step_records(sp, init, last, kstep)) record_energies(P, sp, s, kl & 1, kstep, red);
     if (threadIdx.x != 0) return;
     SysState* sw = P.st + s;
     sw->status = st.status | st.status_next;
@@ -1461,9 +1466,9 @@ __global__ void __launch_bounds__(256) k_lambda(PoolDev P, int kk)
         (st.status & (ST_OVERFLOW | ST_NONFINITE | ST_STALL)))
         return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
-    const double* pp = P.partial + 3 * ((size_t)(kk & 1) * P.nbt + sp.pboff);
+    const double* pp = P.partial + kPartial * ((size_t)(kk & 1) * P.nbt + sp.pboff);
     double ke = 0.0;
-    for (int q = tid; q < sp.nbrick; q += blockDim.x) ke += pp[3 * q];
+    for (int q = tid; q < sp.nbrick; q += blockDim.x) ke += pp[kPartial * q];
     ke = wave_sum(ke);
     if (lane == 0) red[wave] = ke;
     __syncthreads();

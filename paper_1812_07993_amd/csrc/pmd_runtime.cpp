@@ -375,7 +375,7 @@ size_t pool_bytes(int precision, int vt, int wt, int ct, int wct, int nbt, int n
     s += 3 * (size_t)ct * 4 + 3 * (size_t)std::max(vt, wt) * 4;
     s += (size_t)vt * cap * 4 + (size_t)vt * 4;            // lists
     s += 3 * (size_t)wt * 8 + (size_t)wt * 4 + (size_t)wct * 4;
-    s += 6 * (size_t)nbt * 8 + (size_t)nslots * erings * sizeof(EnergyRec);
+    s += 2 * kPartial * (size_t)nbt * 8 + (size_t)nslots * erings * sizeof(EnergyRec);
     s += 3 * (size_t)std::max(vt, wt) * 8 + (size_t)nslots * (sizeof(SysParams) + sizeof(SysState));
     return s;
 }
@@ -424,7 +424,7 @@ int pool_allocate(Pool& p)
     CHK(p.alloc(&p.wid, wt));
     CHK(p.alloc(&p.wcstart, std::max(p.wct, 1)));
     HIPCHK(hipMemset(p.wcstart, 0, sizeof(int) * (size_t)std::max(p.wct, 1)));
-    CHK(p.alloc(&p.partial, 6 * (size_t)std::max(p.nbt, 1)));
+    CHK(p.alloc(&p.partial, 2 * kPartial * (size_t)std::max(p.nbt, 1)));
     CHK(p.alloc(&p.erec, (size_t)p.nslots * p.ering_cap));
     CHK(p.alloc(&p.stage, 3 * (size_t)sc));
     CHK(p.alloc(&p.dbg, 16));
@@ -1270,6 +1270,8 @@ static void to_energies(const EnergyRec& r, int64_t nv, pmd_energies* e)
     e->pe_vw = r.pe_vw;
     e->etotal = r.ke + r.pe_vv + r.pe_vw;
     e->temperature = nv > 1 ? 2.0 * r.ke / (3.0 * nv - 3.0) : 0.0;
+    e->virial_vv = r.w_vv;
+    e->virial_vw = r.w_vw;
 }
 
 int pmd_get_energy_history(pmd_system* sys, pmd_energies* out, int64_t cap, int64_t* n_out)

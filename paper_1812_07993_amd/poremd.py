@@ -47,7 +47,8 @@ class pmd_pore(ctypes.Structure):
 class pmd_energies(ctypes.Structure):
     _fields_ = [("step", ctypes.c_int64), ("ke", ctypes.c_double),
                 ("pe_vv", ctypes.c_double), ("pe_vw", ctypes.c_double),
-                ("etotal", ctypes.c_double), ("temperature", ctypes.c_double)]
+                ("etotal", ctypes.c_double), ("temperature", ctypes.c_double),
+                ("virial_vv", ctypes.c_double), ("virial_vw", ctypes.c_double)]
 
 
 class pmd_tuning(ctypes.Structure):
@@ -258,7 +259,7 @@ def pmd_get_wall_positions(h):
 
 def _energy_dict(e):
     return dict(step=e.step, ke=e.ke, pe_vv=e.pe_vv, pe_vw=e.pe_vw, etotal=e.etotal,
-                temperature=e.temperature)
+                temperature=e.temperature, virial_vv=e.virial_vv, virial_vw=e.virial_vw)
 
 
 def pmd_get_energies(h):
@@ -268,9 +269,11 @@ def pmd_get_energies(h):
 
 
 def pmd_get_energy_history(h, cap=1 << 20):
-    """Recorded energies as a structured array (step, ke, pe_vv, pe_vw, etotal, temperature)."""
+    """Recorded energies as a structured array (step, ke, pe_vv, pe_vw, etotal,
+    temperature, virial_vv, virial_vw)."""
     dt = np.dtype([("step", np.int64), ("ke", np.float64), ("pe_vv", np.float64),
-                   ("pe_vw", np.float64), ("etotal", np.float64), ("temperature", np.float64)])
+                   ("pe_vw", np.float64), ("etotal", np.float64), ("temperature", np.float64),
+                   ("virial_vv", np.float64), ("virial_vw", np.float64)])
     out = np.zeros(cap, dtype=dt)
     n = ctypes.c_int64()
     _check(load().pmd_get_energy_history(h, ctypes.c_void_p(out.ctypes.data), cap,

@@ -1,0 +1,49 @@
+"""GPU parity of the virial sums of the pressure formula (Sec. 2) against
+the FP64 oracle at the same positions: at creation and after 30 steps that
+cross rebuilds.  Tolerance: relative 1e-10 (FP64) and 1e-4 (mixed).  The
+mixed bound is looser than the force bound because r . f = w r^2 with
+w = r^-8 (12 A r^-6 - 6 B) cancels near the LJ minimum, where adsorbed
+atoms sit next to the wall lattice: an FP32 pair term there carries an
+absolute error of about 1e-6, and a few hundred of them sum to a few 1e-4
+on a wall virial of about -17."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1812_07993_amd import poremd, synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-10, "mixed": 1e-4}
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("shape", ["cylinder", "slit"])
+def test_virial_sums_match_the_oracle(prec, shape):
+    L = 16.0
+    pore = (synth.Pore("cylinder", 1.0, 8.0, 4.0, 2.5) if shape == "cylinder"
+            else synth.Pore("slit", 1.0, 8.0, 2.0, slit_gap=4.0))
+    walls = synth.wall_sites(pore, (L, L, L))
+    rng = np.random.default_rng(17)
+    x = synth.rsa_place(rng, (L, L, L), 900, walls, 0.9)
+    v = synth.maxwell(rng, 900, 1.2)
+    params = poremd.make_params(L, prec)
+    cp = poremd.make_pore(pore.kind, pore.lattice_a, pore.slab_center_z, pore.slab_thickness,
+                          pore.r0, pore.r1, pore.slit_gap)
+    s = poremd.System(params, cp, x, v, tuning=poremd.make_tuning(energy_every=10, rebin_every=4))
+    op = oracle.make_params(L)
+    e0 = s.energies()
+    wvv, wvw = oracle.virial(x, walls, op)
+    assert e0["virial_vv"] == pytest.approx(wvv, rel=TOL[prec])
+    assert e0["virial_vw"] == pytest.approx(wvw, rel=TOL[prec])
+    s.step(30)
+    X = s.positions()
+    e1 = s.energies()
+    assert e1["step"] == 30
+    wvv, wvw = oracle.virial(X, walls, op)
+    assert e1["virial_vv"] == pytest.approx(wvv, rel=TOL[prec])
+    assert e1["virial_vw"] == pytest.approx(wvw, rel=TOL[prec])
+    # the pressure the paper's formula gives, over the box volume here
+    P = (2.0 * e1["ke"] + e1["virial_vv"]) / (3.0 * L ** 3)
+    assert np.isfinite(P)
+    s.close()
