@@ -1302,13 +1302,16 @@ __global__ void __launch_bounds__(kMaxBlock) k_step(PoolDev P, int kk)
     const int key0 = c.b * sp.bcells;
     const int i0 = P.cstart[sp.coff + key0], i1 = P.cstart[sp.coff + key0 + sp.bcells];
 
-    double ke = 0.0, evv = 0.0, evw = 0.0, wvv = 0.0, wvw = 0.0;
+    double ke = 0.0;
+    // force fields per atom; the energy and virial fields run over all of
+    // this lane's atoms (no second set of sums to keep live in the loops)
+    Acc a{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     int flags = tot < 0 ? (ST_OVERFLOW | ST_TILE) : 0;
     for (int i = i0 + tid; tot >= 0 && i < i1; i += blockDim.x) {
         const V me = x.Lc[i];
         const int nl = P.nlist[i];
         const int nvap = nl & 0xFFFF, nall = nvap + (nl >> 16);
-        Acc a{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        a.fx = a.fy = a.fz = 0.0;
         // entries come kGroupV (vapour, as kGroupV / 4 chunk loads) or
         // kGroupW<T> (walls) at a time, the next group's loads in flight while
         // the current one is evaluated; vapour partners are read from LDS, wall
@@ -1389,13 +1392,10 @@ __global__ void __launch_bounds__(kMaxBlock) k_step(PoolDev P, int kk)
             }
         }
         if (ne) edge_pass<T>(P, sp, x, tl, i, nvap, nall, ne, ke0, ke1, a);
-        evv += 0.5 * a.ev;
-        evw += a.ew;
-        wvv += 0.5 * a.wv;
-        wvw += a.ww;
         ke += atom_epilogue<T>(P, x, i, a, flags);
     }
-    step_reduce(P, sp, s, c.b, kk, x.doE, flags, ke, evv, evw, wvv, wvw, red);
+    // vapour pairs were met from both atoms: half of each sum
+    step_reduce(P, sp, s, c.b, kk, x.doE, flags, ke, 0.5 * a.ev, a.ew, 0.5 * a.wv, a.ww, red);
 }
 
 // End of a replay, one workgroup per system: count the steps the replay
