@@ -67,6 +67,7 @@ struct SysParams {
     double rw2;            // wall-list radius^2, (r_c + skin/2)^2
     float half_skin;       // rebuild threshold on the travelled path
     int thermo;            // 1: Berendsen thermostat on
+    int virial;            // 1: record the virial sums
     double tau_t, t0, dof; // its rise time, target temperature, 3 nv - 3
 };
 
@@ -126,6 +127,7 @@ struct PoolDev {
     int nbt;              // brick capacity (stride of the two energy-partial slots)
     int nslots;           // system slots
     int thermo;           // 1 if a resident system has the thermostat on
+    int virial;           // 1 if a resident system records the virial sums
     // per-atom state, double buffered by SysState::sbuf; SoA with stride vt
     double* X[2];
     double* V[2];

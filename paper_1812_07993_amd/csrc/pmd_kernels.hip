@@ -1087,8 +1087,9 @@ struct Acc {
     double wv, ww;  // virial sums r . f (vapour and wall partners)
 };
 
-// One in-cutoff pair: FP32 (mixed) or FP64 LJ, FP64 sums.
-template <typename T>
+// One in-cutoff pair: FP32 (mixed) or FP64 LJ, FP64 sums; on recording
+// steps also its energy and, with VIR, its r . f.
+template <typename T, bool VIR>
 __device__ __forceinline__ void pair_term(const StepCtx<T>& x, Acc& a, T dx, T dy, T dz, T r2, bool wall)
 {
     const T A = wall ? x.Aw : x.Av, B = wall ? x.Bw : x.Bv;
@@ -1100,20 +1101,23 @@ __device__ __forceinline__ void pair_term(const StepCtx<T>& x, Acc& a, T dx, T d
     a.fz += (double)(w * dz);
     if (x.doE) {
         const double u_ = (double)(sr6 * (A * sr6 - B) - (wall ? x.ucw : x.ucv));
-        const double v_ = (double)(w * r2);  // r . f of the pair
-        if (wall) {
+        if (wall)
             a.ew += u_;
-            a.ww += v_;
-        } else {
+        else
             a.ev += u_;
-            a.wv += v_;
+        if constexpr (VIR) {
+            const double v_ = (double)(w * r2);  // r . f of the pair
+            if (wall)
+                a.ww += v_;
+            else
+                a.wv += v_;
         }
     }
 }
 
 // List entry k of atom i if its FP32 r^2 lies within the band around the
 // cutoff: the pair is decided on the FP64 master positions.
-template <typename T>
+template <typename T, bool VIR>
 __device__ __forceinline__ void edge_entry(const PoolDev& P, const SysParams& sp, const StepCtx<T>& x,
                                            const Tile<T>& tl, int i, int k, int nvap,
                                            const typename V4<T>::type& me, double xi, double yi,
@@ -1145,14 +1149,14 @@ __device__ __forceinline__ void edge_entry(const PoolDev& P, const SysParams& sp
     ex -= sp.L[0] * rint(ex * sp.invL[0]);
     ey -= sp.L[1] * rint(ey * sp.invL[1]);
     ez -= sp.L[2] * rint(ez * sp.invL[2]);
-    if (ex * ex + ey * ey + ez * ez < sp.rc2) pair_term<T>(x, a, dx, dy, dz, r2, wall);
+    if (ex * ex + ey * ey + ez * ez < sp.rc2) pair_term<T, VIR>(x, a, dx, dy, dz, r2, wall);
 }
 
 // The pairs of atom i that the pair loops left out (FP32 r^2 within the band
 // around the cutoff), decided on the FP64 master positions and added in list
 // order.  The loops record the list positions of the first two such entries
 // (ne counts them all); only an atom with more than two rescans its list.
-template <typename T>
+template <typename T, bool VIR>
 __device__ void edge_pass(const PoolDev& P, const SysParams& sp, const StepCtx<T>& x,
                           const Tile<T>& tl, int i, int nvap, int nall, int ne, int k0, int k1,
                           Acc& a)
@@ -1161,11 +1165,11 @@ __device__ void edge_pass(const PoolDev& P, const SysParams& sp, const StepCtx<T
     const typename V4<T>::type me = x.Lc[i];
     const double xi = x.X[i], yi = x.X[vt + i], zi = x.X[2 * vt + i];
     if (ne <= 2) {
-        edge_entry<T>(P, sp, x, tl, i, k0, nvap, me, xi, yi, zi, a);
-        if (ne == 2) edge_entry<T>(P, sp, x, tl, i, k1, nvap, me, xi, yi, zi, a);
+        edge_entry<T, VIR>(P, sp, x, tl, i, k0, nvap, me, xi, yi, zi, a);
+        if (ne == 2) edge_entry<T, VIR>(P, sp, x, tl, i, k1, nvap, me, xi, yi, zi, a);
         return;
     }
-    for (int k = 0; k < nall; ++k) edge_entry<T>(P, sp, x, tl, i, k, nvap, me, xi, yi, zi, a);
+    for (int k = 0; k < nall; ++k) edge_entry<T, VIR>(P, sp, x, tl, i, k, nvap, me, xi, yi, zi, a);
 }
 
 // F3 (second half-kick) and, unless the run ends, F2 of the next step (first
@@ -1271,8 +1275,8 @@ __device__ void step_reduce(const PoolDev& P, const SysParams& sp, int s, int b,
     }
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kMaxBlock) k_step(PoolDev P, int kk)
+template <typename T, bool VIR>
+__device__ __forceinline__ void step_body(PoolDev& P, int kk)
 {
     using V = typename V4<T>::type;
     extern __shared__ __align__(32) unsigned char smem[];
@@ -1354,7 +1358,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_step(PoolDev P, int kk)
                 ke0 = (near && ne == 0) ? k0 + u : ke0;
                 ke1 = (near && ne == 1) ? k0 + u : ke1;
                 ne += near ? 1 : 0;
-                if (live && r2 < x.rc2 && !near) pair_term<T>(x, a, dx, dy, dz, r2, false);
+                if (live && r2 < x.rc2 && !near) pair_term<T, VIR>(x, a, dx, dy, dz, r2, false);
             }
 #pragma unroll
             for (int c = 0; c < NC; ++c) cc[c] = cn[c];
@@ -1385,17 +1389,32 @@ __global__ void __launch_bounds__(kMaxBlock) k_step(PoolDev P, int kk)
                     ke0 = (near && ne == 0) ? k0 + u : ke0;
                     ke1 = (near && ne == 1) ? k0 + u : ke1;
                     ne += near ? 1 : 0;
-                    if (live && r2 < x.rc2 && !near) pair_term<T>(x, a, dx, dy, dz, r2, true);
+                    if (live && r2 < x.rc2 && !near) pair_term<T, VIR>(x, a, dx, dy, dz, r2, true);
                 }
 #pragma unroll
                 for (int u = 0; u < kGroupW<T>; ++u) cw[u] = nw[u];
             }
         }
-        if (ne) edge_pass<T>(P, sp, x, tl, i, nvap, nall, ne, ke0, ke1, a);
+        if (ne) edge_pass<T, VIR>(P, sp, x, tl, i, nvap, nall, ne, ke0, ke1, a);
         ke += atom_epilogue<T>(P, x, i, a, flags);
     }
     // vapour pairs were met from both atoms: half of each sum
     step_reduce(P, sp, s, c.b, kk, x.doE, flags, ke, 0.5 * a.ev, a.ew, 0.5 * a.wv, a.ww, red);
+}
+
+// The step kernel (F1 + F3 + the next F2, see step_body); k_step_virial
+// also sums r . f on recording steps (a pool with a system that asks for
+// the virial), which costs the plain kernel's registers and about 3%.
+template <typename T>
+__global__ void __launch_bounds__(kMaxBlock) k_step(PoolDev P, int kk)
+{
+    step_body<T, false>(P, kk);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kMaxBlock) k_step_virial(PoolDev P, int kk)
+{
+    step_body<T, true>(P, kk);
 }
 
 // End of a replay, one workgroup per system: count the steps the replay
@@ -1544,16 +1563,18 @@ hipError_t launch_step(const PoolDev& P, int kk, int precision, hipStream_t s, h
     const int B = P.block;
     if (G == 0) return hipSuccess;
     const size_t lds = tile_bytes(P, precision);
+    auto kf = P.virial ? k_step_virial<float> : k_step<float>;
+    auto kd = P.virial ? k_step_virial<double> : k_step<double>;
     if (ev0 && ev1) {
         if (precision == 1)
-            hipExtLaunchKernelGGL(k_step<float>, dim3(G), dim3(B), lds, s, ev0, ev1, 0, P, kk);
+            hipExtLaunchKernelGGL(kf, dim3(G), dim3(B), lds, s, ev0, ev1, 0, P, kk);
         else
-            hipExtLaunchKernelGGL(k_step<double>, dim3(G), dim3(B), lds, s, ev0, ev1, 0, P, kk);
+            hipExtLaunchKernelGGL(kd, dim3(G), dim3(B), lds, s, ev0, ev1, 0, P, kk);
     } else {
         if (precision == 1)
-            hipLaunchKernelGGL(k_step<float>, dim3(G), dim3(B), lds, s, P, kk);
+            hipLaunchKernelGGL(kf, dim3(G), dim3(B), lds, s, P, kk);
         else
-            hipLaunchKernelGGL(k_step<double>, dim3(G), dim3(B), lds, s, P, kk);
+            hipLaunchKernelGGL(kd, dim3(G), dim3(B), lds, s, P, kk);
     }
     if (P.thermo) {
         hipLaunchKernelGGL(k_lambda, dim3(P.nslots), dim3(256), 0, s, P, kk);

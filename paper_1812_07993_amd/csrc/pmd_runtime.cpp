@@ -184,6 +184,7 @@ pmd_tuning default_tuning(const pmd_params& p, int64_t nv)
     t.use_graph = 1;
     t.brick_atoms = 0;
     t.brick_order = kDefaultBrickOrder;
+    t.virial = 0;
     return t;
 }
 
@@ -202,6 +203,7 @@ int merge_tuning(const pmd_params& p, int64_t nv, const pmd_tuning* in, pmd_tuni
         d.use_graph = in->use_graph;
         if (in->brick_atoms > 0) d.brick_atoms = in->brick_atoms;
         if (in->brick_order > 0) d.brick_order = in->brick_order;
+        d.virial = in->virial ? 1 : 0;
     }
     if (d.block < 64 || d.block > kMaxBlock || d.block % 64)
         return fail(PMD_EINVAL, "block must be a multiple of 64 from 64 to %d (got %d)", kMaxBlock, d.block);
@@ -225,6 +227,7 @@ struct Pool {
     int cap = 64;
     int vt = 0, wt = 0, ct = 0, wct = 0, nbt = 0, nslots = 0, ering_cap = kDefaultErings;
     int thermo = 0;  // a resident system has the thermostat on
+    int virial = 0;  // a resident system records the virial sums
     size_t bytes = 0;
     // device arrays
     SysParams* d_sp = nullptr;
@@ -334,6 +337,7 @@ struct Pool {
         d.nbt = nbt;
         d.nslots = nslots;
         d.thermo = thermo;
+        d.virial = virial;
         for (int b = 0; b < 2; ++b) {
             d.X[b] = X[b];
             d.V[b] = V[b];
@@ -511,8 +515,12 @@ int pool_layout(Pool& p)
     p.ntile = (int)p.htile.size();
     p.nbrick = (int)p.hbrick.size();
     p.thermo = 0;
+    p.virial = 0;
     for (int s = 0; s < p.nslots; ++s)
-        if (p.hsp[s].active && p.hsp[s].thermo) p.thermo = 1;
+        if (p.hsp[s].active) {
+            if (p.hsp[s].thermo) p.thermo = 1;
+            if (p.hsp[s].virial) p.virial = 1;
+        }
     p.hmax = std::max(hmax, 1);
     const size_t ab = tile_atom_bytes(p.precision);
     const size_t ints = (size_t)(2 * p.hmax + 1) * 4;
@@ -627,6 +635,7 @@ void fill_sys_params(SysParams& sp, const pmd_params& p, const Grid& g, const pm
     sp.half_skin = (float)(0.5 * t.skin * (1.0 - 1e-3));
     sp.energy_every = t.energy_every;
     sp.thermo = p.thermostat_tau > 0 ? 1 : 0;
+    sp.virial = t.virial ? 1 : 0;
     sp.tau_t = p.thermostat_tau;
     sp.t0 = p.thermostat_t0;
     sp.dof = nv > 1 ? 3.0 * nv - 3.0 : 3.0;
@@ -1262,7 +1271,7 @@ int pmd_get_forces(pmd_system* sys, double* out, int64_t n)
     try { return readback(sys, 2, out, n); } catch (...) { return fail(PMD_EHIP, "unexpected exception"); }
 }
 
-static void to_energies(const EnergyRec& r, int64_t nv, pmd_energies* e)
+static void to_energies(const EnergyRec& r, int64_t nv, bool virial, pmd_energies* e)
 {
     e->step = r.step;
     e->ke = r.ke;
@@ -1270,8 +1279,9 @@ static void to_energies(const EnergyRec& r, int64_t nv, pmd_energies* e)
     e->pe_vw = r.pe_vw;
     e->etotal = r.ke + r.pe_vv + r.pe_vw;
     e->temperature = nv > 1 ? 2.0 * r.ke / (3.0 * nv - 3.0) : 0.0;
-    e->virial_vv = r.w_vv;
-    e->virial_vw = r.w_vw;
+    // a pool runs the summing kernel when any of its systems asks for it
+    e->virial_vv = virial ? r.w_vv : 0.0;
+    e->virial_vw = virial ? r.w_vw : 0.0;
 }
 
 int pmd_get_energy_history(pmd_system* sys, pmd_energies* out, int64_t cap, int64_t* n_out)
@@ -1291,7 +1301,8 @@ int pmd_get_energy_history(pmd_system* sys, pmd_energies* out, int64_t cap, int6
                          hipMemcpyDeviceToHost));
         const int64_t take = std::min(avail, cap);
         for (int64_t r = 0; r < take; ++r)
-            to_energies(buf[(size_t)((first + (avail - take) + r) % ring)], sys->nv, out + r);
+            to_energies(buf[(size_t)((first + (avail - take) + r) % ring)], sys->nv, sys->tuning.virial != 0,
+                        out + r);
         *n_out = take;
         return PMD_OK;
     } catch (...) {

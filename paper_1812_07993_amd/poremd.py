@@ -55,7 +55,8 @@ class pmd_tuning(ctypes.Structure):
     _fields_ = [("skin", ctypes.c_double), ("rebin_every", ctypes.c_int32),
                 ("block", ctypes.c_int32), ("list_cap", ctypes.c_int32),
                 ("energy_every", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("brick_atoms", ctypes.c_int32), ("brick_order", ctypes.c_int32)]
+                ("brick_atoms", ctypes.c_int32), ("brick_order", ctypes.c_int32),
+                ("virial", ctypes.c_int32)]
 
 
 _lib = None
@@ -174,11 +175,11 @@ def make_pore(kind="none", lattice_a=1.0, slab_center_z=0.0, slab_thickness=0.0,
 
 
 def make_tuning(skin=0.0, rebin_every=0, block=0, list_cap=0, energy_every=0,
-                use_graph=1, brick_atoms=0, brick_order=0) -> pmd_tuning:
+                use_graph=1, brick_atoms=0, brick_order=0, virial=0) -> pmd_tuning:
     t = pmd_tuning()
     t.skin, t.rebin_every, t.block, t.list_cap = skin, rebin_every, block, list_cap
     t.energy_every, t.use_graph, t.brick_atoms = energy_every, use_graph, brick_atoms
-    t.brick_order = brick_order
+    t.brick_order, t.virial = brick_order, virial
     return t
 
 
@@ -493,6 +494,9 @@ class System:
 
     def set_state(self, pos, vel, step=0):
         pmd_set_state(self.h, pos, vel, step)
+
+    def set_tuning(self, tuning):
+        pmd_set_tuning(self.h, tuning)
 
     def close(self):
         if self.h:

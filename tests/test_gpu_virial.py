@@ -30,7 +30,8 @@ def test_virial_sums_match_the_oracle(prec, shape):
     params = poremd.make_params(L, prec)
     cp = poremd.make_pore(pore.kind, pore.lattice_a, pore.slab_center_z, pore.slab_thickness,
                           pore.r0, pore.r1, pore.slit_gap)
-    s = poremd.System(params, cp, x, v, tuning=poremd.make_tuning(energy_every=10, rebin_every=4))
+    s = poremd.System(params, cp, x, v,
+                      tuning=poremd.make_tuning(energy_every=10, rebin_every=4, virial=1))
     op = oracle.make_params(L)
     e0 = s.energies()
     wvv, wvw = oracle.virial(x, walls, op)
@@ -46,4 +47,21 @@ def test_virial_sums_match_the_oracle(prec, shape):
     # the pressure the paper's formula gives, over the box volume here
     P = (2.0 * e1["ke"] + e1["virial_vv"]) / (3.0 * L ** 3)
     assert np.isfinite(P)
+    # switched off by a retune: the sums read 0 and the trajectory goes on
+    s.set_tuning(poremd.make_tuning(energy_every=10, rebin_every=4))
+    s.step(10)
+    e2 = s.energies()
+    assert e2["step"] == 40 and e2["virial_vv"] == 0.0 and e2["virial_vw"] == 0.0
+    s.close()
+
+
+def test_virial_sums_are_off_by_default():
+    L = 12.0
+    rng = np.random.default_rng(5)
+    x = synth.rsa_place(rng, (L, L, L), 300, np.zeros((0, 3)), 0.9)
+    s = poremd.System(poremd.make_params(L, "mixed"), poremd.make_pore("none"), x,
+                      np.zeros_like(x), tuning=poremd.make_tuning(energy_every=5))
+    s.step(10)
+    e = s.energies()
+    assert e["virial_vv"] == 0.0 and e["virial_vw"] == 0.0 and e["pe_vv"] < 0.0
     s.close()
