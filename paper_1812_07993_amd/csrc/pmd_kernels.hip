@@ -840,54 +840,84 @@ __global__ void __launch_bounds__(kMaxBlock) k_list_build(PoolDev P)
         // this is its only copy in the tile)
         const int hs = halo_cell(g, cx, cy, cz, 13);
         const int aself = t.hoff[hs] + (i - t.hbeg[hs]);
+        // neighbour cells in the order q = (dx+1) + 3 (dy+1) + 9 (dz+1), as
+        // nested z, y, x loops: each level culls with the partial box gap of
+        // the levels above it (a whole plane or row of cells at once) and
+        // carries the atom's coordinate shifted into the neighbour cell's
+        // frame (px = me.x - dx h_x, and so on)
+        const int hstr1 = g.hd[0], hstr2 = g.hd[0] * g.hd[1];
+        const T hx = (T)sp.h[0], hy = (T)sp.h[1], hz = (T)sp.h[2];
         int nv = 0;
-        for (int q = 0; q < 27; ++q) {
-            const int dx = q % 3 - 1, dy = (q / 3) % 3 - 1, dz = q / 9 - 1;
-            const double gx = box_gap(lx, dx, sp.h[0]), gy = box_gap(ly, dy, sp.h[1]),
-                         gz = box_gap(lz, dz, sp.h[2]);
-            if (gx * gx + gy * gy + gz * gz >= cull_v) continue;
-            const T sx = (T)(-dx * sp.h[0]), sy = (T)(-dy * sp.h[1]), sz = (T)(-dz * sp.h[2]);
-            const int h = halo_cell(g, cx, cy, cz, q);
-            const int a1 = t.hoff[h + 1];
-            for (int a = t.hoff[h]; a < a1; a += 4) {
-                V o[4];
+#pragma unroll 1
+        for (int dz = -1; dz <= 1; ++dz) {
+            const double gz = box_gap(lz, dz, sp.h[2]), gz2 = gz * gz;
+            if (gz2 >= cull_v) continue;
+            const T pz = me.z - (T)dz * hz;
+#pragma unroll 1
+            for (int dy = -1; dy <= 1; ++dy) {
+                const double gy = box_gap(ly, dy, sp.h[1]), gyz = fma(gy, gy, gz2);
+                if (gyz >= cull_v) continue;
+                const T py = me.y - (T)dy * hy;
+#pragma unroll 1
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const double gx = box_gap(lx, dx, sp.h[0]);
+                    if (fma(gx, gx, gyz) >= cull_v) continue;
+                    const T px = me.x - (T)dx * hx;
+                    const unsigned code = offset_code((dx + 1) + 3 * (dy + 1) + 9 * (dz + 1)) << kIndexBits;
+                    const int h = hs + dx + dy * hstr1 + dz * hstr2;
+                    const int a1 = t.hoff[h + 1];
+                    for (int a = t.hoff[h]; a < a1; a += 4) {
+                        V o[4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) o[u] = t.pos[min(a + u, a1 - 1)];
+                        for (int u = 0; u < 4; ++u) o[u] = t.pos[min(a + u, a1 - 1)];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const T ex = me.x - o[u].x + sx, ey = me.y - o[u].y + sy, ez = me.z - o[u].z + sz;
-                    if (a + u < a1 && ex * ex + ey * ey + ez * ez < rl2 && a + u != aself) {
-                        if (nv < cap)
-                            P.list[list_at(vt, i, nv)] = (unsigned)(a + u) | (offset_code(q) << kIndexBits);
-                        ++nv;
+                        for (int u = 0; u < 4; ++u) {
+                            const T ex = px - o[u].x, ey = py - o[u].y, ez = pz - o[u].z;
+                            // one branch per candidate (the tests combined
+                            // without short-circuit; the clamped loads make
+                            // all of them safe): the store only when the entry
+                            // is in range and fits
+                            const bool hit = (a + u < a1) & (ex * ex + ey * ey + ez * ez < rl2) & (a + u != aself);
+                            if (hit && nv < cap) P.list[list_at(vt, i, nv)] = (unsigned)(a + u) | code;
+                            nv += hit;
+                        }
                     }
                 }
             }
         }
         int nw = 0;
-        for (int q = 0; q < 27; ++q) {
-            const int dx = q % 3 - 1, dy = (q / 3) % 3 - 1, dz = q / 9 - 1;
-            const double gx = box_gap(lx, dx, sp.h[0]), gy = box_gap(ly, dy, sp.h[1]),
-                         gz = box_gap(lz, dz, sp.h[2]);
-            if (gx * gx + gy * gy + gz * gz >= cull_w) continue;
-            const int h = halo_cell(g, cx, cy, cz, q);
-            const int w0 = wrange[2 * h], w1 = wrange[2 * h + 1];
-            if (w0 >= w1) continue;
-            const T sx = (T)(-dx * sp.h[0]), sy = (T)(-dy * sp.h[1]), sz = (T)(-dz * sp.h[2]);
-            // kWallRound candidates per round, loads issued together (indices
-            // clamped to the cell's last wall)
-            for (int w = w0; w < w1; w += kWallRound) {
-                V o[kWallRound];
+#pragma unroll 1
+        for (int dz = -1; dz <= 1; ++dz) {
+            const double gz = box_gap(lz, dz, sp.h[2]), gz2 = gz * gz;
+            if (gz2 >= cull_w) continue;
+            const T pz = me.z - (T)dz * hz;
+#pragma unroll 1
+            for (int dy = -1; dy <= 1; ++dy) {
+                const double gy = box_gap(ly, dy, sp.h[1]), gyz = fma(gy, gy, gz2);
+                if (gyz >= cull_w) continue;
+                const T py = me.y - (T)dy * hy;
+#pragma unroll 1
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const double gx = box_gap(lx, dx, sp.h[0]);
+                    if (fma(gx, gx, gyz) >= cull_w) continue;
+                    const int h = hs + dx + dy * hstr1 + dz * hstr2;
+                    const int w0 = wrange[2 * h], w1 = wrange[2 * h + 1];
+                    if (w0 >= w1) continue;
+                    const T px = me.x - (T)dx * hx;
+                    const unsigned code = offset_code((dx + 1) + 3 * (dy + 1) + 9 * (dz + 1)) << kIndexBits;
+                    // kWallRound candidates per round, loads issued together
+                    // (indices clamped to the cell's last wall)
+                    for (int w = w0; w < w1; w += kWallRound) {
+                        V o[kWallRound];
 #pragma unroll
-                for (int u = 0; u < kWallRound; ++u) o[u] = Lw[min(w + u, w1 - 1)];
+                        for (int u = 0; u < kWallRound; ++u) o[u] = Lw[min(w + u, w1 - 1)];
 #pragma unroll
-                for (int u = 0; u < kWallRound; ++u) {
-                    const T ex = me.x - o[u].x + sx, ey = me.y - o[u].y + sy, ez = me.z - o[u].z + sz;
-                    if (w + u < w1 && ex * ex + ey * ey + ez * ez < rw2) {
-                        if (nv + nw < cap)
-                            P.list[list_at(vt, i, nv + nw)] =
-                                (unsigned)(w + u) | (offset_code(q) << kIndexBits);
-                        ++nw;
+                        for (int u = 0; u < kWallRound; ++u) {
+                            const T ex = px - o[u].x, ey = py - o[u].y, ez = pz - o[u].z;
+                            const bool hit = (w + u < w1) & (ex * ex + ey * ey + ez * ez < rw2);
+                            if (hit && nv + nw < cap) P.list[list_at(vt, i, nv + nw)] = (unsigned)(w + u) | code;
+                            nw += hit;
+                        }
                     }
                 }
             }
