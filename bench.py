@@ -38,13 +38,13 @@ PEAK_HBM_GBS = 8000.0
 # the lists are rebuilt, not what one step launch reads and writes.  Any
 # other source, workload or tuning reports null.
 MEASURED_TRAFFIC = {
-    ("aa3321b60fb19a0c", 262144, 0.7, 512, 460): 92.43e6,
-    ("aa3321b60fb19a0c", 262144, 0.7, 256, 270): 95.88e6,
-    ("aa3321b60fb19a0c", 262144, 0.7, 256, 256): 98.93e6,
-    ("aa3321b60fb19a0c", 262144, 0.7, 256, 0): 96.84e6,
-    ("aa3321b60fb19a0c", 262144, 1.0, 256, 270): 101.98e6,
-    ("aa3321b60fb19a0c", 262144, 1.0, 512, 460): 92.77e6,
-    ("aa3321b60fb19a0c", 262144, 1.0, 256, 0): 102.79e6,
+    ("345e4388e18ffd19", 262144, 0.7, 512, 460): 92.43e6,
+    ("345e4388e18ffd19", 262144, 0.7, 256, 270): 95.93e6,
+    ("345e4388e18ffd19", 262144, 0.7, 256, 256): 98.87e6,
+    ("345e4388e18ffd19", 262144, 0.7, 256, 0): 96.84e6,
+    ("345e4388e18ffd19", 262144, 1.0, 256, 270): 101.99e6,
+    ("345e4388e18ffd19", 262144, 1.0, 512, 460): 92.76e6,
+    ("345e4388e18ffd19", 262144, 1.0, 256, 0): 102.79e6,
 }
 
 
