@@ -13,6 +13,8 @@ What each function follows in arXiv:1812.07993:
                           paper's F1 visits every pair, Sec. 3);
   * ``forces_subset``  -- eq. 2 for chosen atoms only (sampled checks);
   * ``run``            -- velocity Verlet in the order F2, F1, F3 (Sec. 3);
+  * ``allpairs``       -- the force function as stated in Sec. 3: every
+                          pair, no cutoff, no shift (minimum image);
   * ``wall_lattice``   -- the pore walls (the paper's walls are boundary
                           conditions, Secs. 4-5; the lattice is a reading);
   * ``cell_sort``, ``pairs`` -- the integer work of binning and neighbour
@@ -70,6 +72,7 @@ def _load():
                             i64, i64, vp, d, d]
     lib.orc_run.restype = i64
     lib.orc_virial.argtypes = [i64, vp, i64, vp, P(Params), P(d), P(d)]
+    lib.orc_allpairs.argtypes = [i64, vp, vp, d, d, vp, vp, P(d)]
     lib.orc_wall_lattice.argtypes = [P(Pore), vp, vp, i64]
     lib.orc_wall_lattice.restype = i64
     lib.orc_cell_sort.argtypes = [i64, vp, vp, vp, vp, vp, vp]
@@ -185,6 +188,22 @@ def virial(x, walls, params: Params):
     _load().orc_virial(x.shape[0], _ptr(x), w.shape[0], _ptr(w), ctypes.byref(params),
                        ctypes.byref(wvv), ctypes.byref(wvw))
     return wvv.value, wvw.value
+
+
+def allpairs(x, box, epsilon=1.0, sigma=1.0):
+    """All-pairs Lennard-Jones forces as the paper's force function states
+    them (Sec. 3): every pair, no cutoff, no shift; minimum image on the axes
+    with box[k] > 0.  Returns (forces [n, 3], per-atom half shares of the
+    energy [n], total energy)."""
+    x = _f64(x, (-1, 3))
+    b = _f64(np.asarray(box, dtype=np.float64).reshape(3), (3,))
+    n = x.shape[0]
+    f = np.zeros((n, 3))
+    u = np.zeros(n)
+    e = ctypes.c_double()
+    _load().orc_allpairs(n, _ptr(x), _ptr(b), float(epsilon), float(sigma), _ptr(f), _ptr(u),
+                         ctypes.byref(e))
+    return f, u, e.value
 
 
 def wall_lattice(pore: Pore, box):

@@ -528,3 +528,34 @@ void orc_pairs(int64_t nv, const double *xv, int64_t nw, const double *xw,
     *n_vv = a;
     *n_vw = b;
 }
+
+/* All-pairs Lennard-Jones forces as the paper's force function states them
+ * (Sec. 3): every pair i != j contributes, with no cutoff and no shift;
+ * r_ij = x_i - x_j by the minimum image along each axis with box[k] > 0.
+ * f_i = sum_j 24 eps (2 (s/r)^12 - (s/r)^6) r_ij / r^2; u_i = sum_j u(r_ij) / 2
+ * with u(r) = 4 eps ((s/r)^12 - (s/r)^6); *e = sum_i u_i. */
+void orc_allpairs(int64_t n, const double *x, const double *box, double eps, double sigma,
+                  double *f, double *u, double *e)
+{
+    double tot = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double fi[3] = {0.0, 0.0, 0.0}, ui = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double d[3];
+            for (int k = 0; k < 3; ++k) {
+                d[k] = x[3 * i + k] - x[3 * j + k];
+                if (box[k] > 0.0) d[k] -= box[k] * nearbyint(d[k] / box[k]);
+            }
+            const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            const double sr2 = sigma * sigma / r2, sr6 = sr2 * sr2 * sr2;
+            const double w = 24.0 * eps * sr6 * (2.0 * sr6 - 1.0) / r2;
+            for (int k = 0; k < 3; ++k) fi[k] += w * d[k];
+            ui += 4.0 * eps * sr6 * (sr6 - 1.0);
+        }
+        for (int k = 0; k < 3; ++k) f[3 * i + k] = fi[k];
+        u[i] = 0.5 * ui;
+        tot += u[i];
+    }
+    *e = tot;
+}

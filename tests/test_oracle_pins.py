@@ -527,3 +527,76 @@ def test_forces_subset_matches_full():
     assert np.array_equal(Fs, F[sel])
     allpe = oracle.forces_subset(x, walls, p, np.arange(x.shape[0]))[1]
     assert allpe.sum() == pytest.approx(evv + evw, rel=1e-12)
+
+
+# ---- all-pairs forces (the force function as stated in Sec. 3) -------------
+
+def _lj_closed(r, eps, sig):
+    s6 = (sig / r) ** 6
+    return 4.0 * eps * (s6 * s6 - s6), 24.0 * eps * (2.0 * s6 * s6 - s6) / r
+
+
+def test_allpairs_dimer_closed_form():
+    """Two atoms at distance r (open box): E = 4 eps ((s/r)^12 - (s/r)^6) and
+    the force on the first is -(24 eps / r)(2 (s/r)^12 - (s/r)^6) along the
+    line from the second; at r = 2^(1/6) s the force vanishes and E = -eps."""
+    eps, sig = 0.7, 1.3
+    for r in (1.2, 1.7, 3.9):
+        f, u, e = oracle.allpairs([[0.0, 0.0, 0.0], [r, 0.0, 0.0]], (0, 0, 0), eps, sig)
+        ue, fm = _lj_closed(r, eps, sig)
+        assert e == pytest.approx(ue, rel=1e-13)
+        assert u == pytest.approx([ue / 2, ue / 2], rel=1e-13)
+        assert f[0, 0] == pytest.approx(-fm, rel=1e-13) and f[1, 0] == pytest.approx(fm, rel=1e-13)
+        assert np.all(f[:, 1:] == 0.0)
+    rm = 2.0 ** (1.0 / 6.0) * sig
+    f, _, e = oracle.allpairs([[0.0, 0.0, 0.0], [0.0, rm, 0.0]], (0, 0, 0), eps, sig)
+    assert e == pytest.approx(-eps, rel=1e-13)
+    assert np.abs(f).max() < 1e-12
+
+
+def test_allpairs_is_minus_the_energy_gradient():
+    rng = np.random.default_rng(3)
+    x = synth.rsa_place(rng, (5.0, 5.0, 5.0), 7, np.zeros((0, 3)), 1.0)
+    for box in ((0, 0, 0), (5.0, 5.0, 5.0)):
+        f, _, _ = oracle.allpairs(x, box, 1.1, 0.95)
+        h = 1e-6
+        for i, k in ((0, 0), (3, 1), (6, 2)):
+            xp, xm = x.copy(), x.copy()
+            xp[i, k] += h
+            xm[i, k] -= h
+            g = (oracle.allpairs(xp, box, 1.1, 0.95)[2] - oracle.allpairs(xm, box, 1.1, 0.95)[2]) / (2 * h)
+            assert -g == pytest.approx(f[i, k], rel=1e-6, abs=1e-6)
+
+
+def test_allpairs_newton_third_law_and_energy_split():
+    rng = np.random.default_rng(8)
+    x = synth.rsa_place(rng, (9.0, 9.0, 9.0), 60, np.zeros((0, 3)), 0.9)
+    f, u, e = oracle.allpairs(x, (9.0, 9.0, 9.0))
+    assert np.abs(f.sum(axis=0)).max() < 1e-10 * np.abs(f).max()
+    assert e == pytest.approx(u.sum(), rel=1e-14)
+
+
+def test_allpairs_minimum_image_across_the_boundary():
+    """A pair 1.2 apart through the periodic boundary (8.8 apart inside the
+    box) is the dimer at r = 1.2; with the axis open it is the dimer at 8.8."""
+    x = [[0.3, 5.0, 5.0], [9.1, 5.0, 5.0]]
+    f, _, e = oracle.allpairs(x, (10.0, 10.0, 10.0))
+    ue, fm = _lj_closed(1.2, 1.0, 1.0)
+    assert e == pytest.approx(ue, rel=1e-12)
+    assert f[0, 0] == pytest.approx(fm, rel=1e-12)  # pushed away from the image at -0.9
+    f, _, e = oracle.allpairs(x, (0.0, 10.0, 10.0))
+    ue, fm = _lj_closed(8.8, 1.0, 1.0)
+    assert e == pytest.approx(ue, rel=1e-12)
+    assert f[0, 0] == pytest.approx(-fm, rel=1e-12)
+
+
+def test_allpairs_scaling_with_sigma():
+    """Lengths scaled by s (positions, box and sigma): energies unchanged,
+    forces divided by s."""
+    rng = np.random.default_rng(11)
+    x = synth.rsa_place(rng, (7.0, 7.0, 7.0), 30, np.zeros((0, 3)), 0.9)
+    f1, u1, e1 = oracle.allpairs(x, (7.0, 7.0, 7.0), 1.0, 1.0)
+    s = 1.7
+    f2, u2, e2 = oracle.allpairs(x * s, (7.0 * s,) * 3, 1.0, s)
+    assert e2 == pytest.approx(e1, rel=1e-12)
+    assert np.allclose(f2 * s, f1, rtol=1e-11, atol=1e-11 * np.abs(f1).max())
