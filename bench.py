@@ -181,6 +181,54 @@ def thermostat_leg(poremd, desc, steps, tuning_kw, tau=0.5, t0=1.2):
     return out
 
 
+def allpairs_leg(poremd, n_pores, calls=50):
+    """The force function as the paper states it (every pair, no cutoff, no
+    shift), at the paper's sizes: N_pore molecules in the pore plus an outer
+    space 21 times the pore volume at a fifth of the pore density, N = 5.2
+    N_pore atoms in all; placed uniformly (random sequential addition at
+    density 0.05, minimum image in a periodic cube), which costs the same as
+    the pore geometry for an all-pairs sum.  Times `calls` back-to-back force
+    evaluations per precision with HIP events on the stream they run on."""
+    import torch
+
+    from paper_1812_07993_amd import synth
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    rows = []
+    for npore in n_pores:
+        n = int(round(5.2 * npore))
+        L = (n / 0.05) ** (1.0 / 3.0)
+        x = synth.rsa_place(np.random.default_rng(npore), (L, L, L), n, np.zeros((0, 3)), 0.9)
+        xd = torch.as_tensor(x, dtype=torch.float64, device=dev)
+        f = torch.empty((n, 3), dtype=torch.float64, device=dev)
+        u = torch.empty((n,), dtype=torch.float64, device=dev)
+        e = torch.empty((1,), dtype=torch.float64, device=dev)
+        row = {"n_pore": npore, "n": n}
+        for prec in ("mixed", "fp64"):
+            def call():
+                poremd.pmd_allpairs_forces(prec, n, xd.data_ptr(), (L, L, L), 1.0, 1.0, f.data_ptr(),
+                                           u.data_ptr(), e.data_ptr(), stream.cuda_stream)
+            for _ in range(3):
+                call()
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(calls):
+                call()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / calls
+            row[prec + "_ms"] = ms
+            row[prec + "_pairs_per_s"] = n * (n - 1) / (ms / 1000.0)
+        log("[allpairs] N_pore %d (N = %d): mixed %.3f ms (%.3g pairs/s), fp64 %.3f ms (%.3g pairs/s)"
+            % (npore, n, row["mixed_ms"], row["mixed_pairs_per_s"], row["fp64_ms"],
+               row["fp64_pairs_per_s"]))
+        rows.append(row)
+    return rows
+
+
 def kernel_time(poremd, s, steps):
     """Mean duration of one step-kernel launch, from HIP events around the R
     back-to-back launches of each replay that did R full steps."""
@@ -353,6 +401,8 @@ def main():
     ap.add_argument("--thermostat-steps", type=int, default=2000,
                     help="steps of the 128^3 workload with the Berendsen thermostat on (0: skip)")
     ap.add_argument("--serve-chunk", type=int, default=250)
+    ap.add_argument("--allpairs", default="100,500,1500",
+                    help="pore molecule counts of the all-pairs force leg, or 'none'")
     ap.add_argument("--timing-steps", type=int, default=500)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="before the timed run, one plain device-to-device copy of this many "
@@ -482,6 +532,8 @@ def main():
     if args.thermostat_steps > 0:
         out["thermostat"] = thermostat_leg(poremd, desc, args.thermostat_steps, tuned["mixed"])
         out["thermostat"]["over_nve"] = out["thermostat"]["value"] / out["value"]
+    if args.allpairs != "none":
+        out["allpairs"] = allpairs_leg(poremd, [int(v) for v in args.allpairs.split(",")])
     if args.sweep != "none":
         out["pore_sweep"] = pore_sweep_leg(poremd, args.sweep.split(","), args.sweep_steps,
                                            0 if (args.skin or args.rebin_every)

@@ -313,6 +313,34 @@ int pmd_batch_info(pmd_batch *b, int *resident, size_t *bytes_used,
                    size_t *bytes_budget);
 int pmd_batch_destroy(pmd_batch *b);
 
+/* ---- All-pairs forces (the paper's F1 as printed) ------------------------ */
+
+/* Forces and potential energy of n atoms where every pair i != j interacts:
+ * the force function of Sec. 3 with no cutoff and no shift,
+ *   u(r) = 4 eps ((sigma/r)^12 - (sigma/r)^6),
+ *   f_i  = sum_j 24 eps (2 (sigma/r)^12 - (sigma/r)^6) r_ij / r^2,
+ * with r_ij = x_i - x_j taken by the minimum image along each axis whose
+ * box[k] > 0 (box[k] <= 0: that axis is open).
+ *   precision  1 = FP32 pair terms (from FP64 differences) with FP64 sums,
+ *              2 = FP64 throughout.
+ *   x_dev      device, [n][3] doubles (read).
+ *   box        host, 3 doubles.
+ *   f_dev      device, [n][3] doubles (written).
+ *   u_dev      device, [n] doubles (written): each atom's half share,
+ *              sum_j u(r_ij) / 2.
+ *   e_dev      device, 1 double (written): the sum of u_dev in index order
+ *              (0 for n = 0).
+ *   stream     hipStream_t (NULL = the default stream); queued, no wait.
+ * The caller owns every buffer; the sums are in a fixed order, so repeated
+ * calls give identical results.  Coincident atoms give non-finite values.
+ * Returns PMD_EINVAL for n < 0 or n > 2^24, a null buffer with n > 0, a
+ * precision other than 1 or 2, or a non-finite or non-positive sigma, a
+ * non-finite epsilon or box. */
+int pmd_allpairs_forces(int precision, int64_t n, const double *x_dev,
+                        const double box[3], double epsilon, double sigma,
+                        double *f_dev, double *u_dev, double *e_dev,
+                        void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "../../include/poremd.h"
+#include "pmd_allpairs.h"
 #include "pmd_internal.h"
 
 using namespace pmd;
@@ -1081,6 +1082,27 @@ extern "C" {
 const char* pmd_last_error(void) { return g_err.c_str(); }
 
 int pmd_version(void) { return 100; }
+
+int pmd_allpairs_forces(int precision, int64_t n, const double* x_dev, const double box[3],
+                        double epsilon, double sigma, double* f_dev, double* u_dev, double* e_dev,
+                        void* stream)
+{
+    try {
+        if (precision != 1 && precision != 2) return fail(PMD_EINVAL, "precision must be 1 or 2 (got %d)", precision);
+        if (n < 0 || n > (int64_t)1 << 24) return fail(PMD_EINVAL, "n must be in 0..2^24 (got %lld)", (long long)n);
+        if (!box || !e_dev || !u_dev || (n > 0 && (!x_dev || !f_dev)))
+            return fail(PMD_EINVAL, "need box, e_dev, u_dev, and x_dev, f_dev for n > 0");
+        if (!std::isfinite(sigma) || sigma <= 0 || !std::isfinite(epsilon))
+            return fail(PMD_EINVAL, "need a finite sigma > 0 and a finite epsilon");
+        for (int k = 0; k < 3; ++k)
+            if (!std::isfinite(box[k])) return fail(PMD_EINVAL, "box edges must be finite");
+        HIPCHK(launch_allpairs(precision, (int)n, x_dev, box, epsilon, sigma, f_dev, u_dev, e_dev,
+                               (hipStream_t)stream));
+        return PMD_OK;
+    } catch (...) {
+        return fail(PMD_EHIP, "unexpected exception");
+    }
+}
 
 int pmd_wall_count(const pmd_params* params, const pmd_pore* pore, int64_t* n_wall)
 {

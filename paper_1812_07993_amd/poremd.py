@@ -104,6 +104,7 @@ _SIGS = {
     "pmd_batch_info": (ctypes.c_int, [_vp, _P(ctypes.c_int), _P(ctypes.c_size_t),
                                       _P(ctypes.c_size_t)]),
     "pmd_batch_destroy": (ctypes.c_int, [_vp]),
+    "pmd_allpairs_forces": (ctypes.c_int, [ctypes.c_int, _i64, _vp, _P(_d), _d, _d, _vp, _vp, _vp, _vp]),
 }
 
 
@@ -289,6 +290,16 @@ def pmd_get_step(h):
 def pmd_get_positions_device(h, dev_ptr, n, stream=None):
     _check(load().pmd_get_positions_device(h, ctypes.c_void_p(dev_ptr), int(n),
                                            ctypes.c_void_p(stream) if stream else None))
+
+
+def pmd_allpairs_forces(precision, n, x_ptr, box, epsilon, sigma, f_ptr, u_ptr, e_ptr, stream=None):
+    """All-pairs forces on device buffers given by address (see the header)."""
+    prec = {"mixed": 1, "fp64": 2}.get(precision, precision)
+    b = (ctypes.c_double * 3)(*[float(v) for v in box])
+    _check(load().pmd_allpairs_forces(int(prec), int(n), ctypes.c_void_p(x_ptr or None), b,
+                                      float(epsilon), float(sigma), ctypes.c_void_p(f_ptr or None),
+                                      ctypes.c_void_p(u_ptr or None), ctypes.c_void_p(e_ptr or None),
+                                      ctypes.c_void_p(stream) if stream else None))
 
 
 def pmd_set_tuning(h, tuning):

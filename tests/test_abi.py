@@ -62,3 +62,25 @@ def test_autotune_grid_is_host_only():
     assert skins == [0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 1.0]
     assert periods == [4, 6, 8, 10, 12, 15, 20]
     assert all(t.block in (64, 128, 256) and t.list_cap == 0 for t in grid)
+
+
+def test_allpairs_rejects_bad_arguments_before_any_device_work():
+    """Argument checks of pmd_allpairs_forces run on the host; the buffers
+    passed here are never touched."""
+    dummy = 0x1000
+    cases = [
+        dict(precision=3, n=4, sigma=1.0, eps=1.0, box=(5.0, 5.0, 5.0)),
+        dict(precision="fp64", n=-1, sigma=1.0, eps=1.0, box=(5.0, 5.0, 5.0)),
+        dict(precision="fp64", n=(1 << 24) + 1, sigma=1.0, eps=1.0, box=(5.0, 5.0, 5.0)),
+        dict(precision="mixed", n=4, sigma=0.0, eps=1.0, box=(5.0, 5.0, 5.0)),
+        dict(precision="mixed", n=4, sigma=1.0, eps=float("nan"), box=(5.0, 5.0, 5.0)),
+        dict(precision="mixed", n=4, sigma=1.0, eps=1.0, box=(5.0, float("inf"), 5.0)),
+    ]
+    for c in cases:
+        with pytest.raises(poremd.PmdError) as e:
+            poremd.pmd_allpairs_forces(c["precision"], c["n"], dummy, c["box"], c["eps"], c["sigma"],
+                                       dummy, dummy, dummy)
+        assert e.value.code == poremd.PMD_EINVAL
+    with pytest.raises(poremd.PmdError) as e:
+        poremd.pmd_allpairs_forces("fp64", 4, 0, (5.0, 5.0, 5.0), 1.0, 1.0, dummy, dummy, dummy)
+    assert e.value.code == poremd.PMD_EINVAL
