@@ -14,11 +14,13 @@ struct AllPairsArgs {
     int n;
 };
 
-// One workgroup = one wave = 16 atoms x 4 quarters of the partners: lane l
-// owns atom 16 b + (l & 15) and the partners k = l >> 4 (mod 4) of each
-// 64-atom tile staged in LDS.  The four partial sums of an atom are combined
-// in a fixed order by two shuffles, so results do not depend on timing.
-constexpr int kApAtoms = 16, kApParts = 4, kApTile = kApAtoms * kApParts;
+// One workgroup = one wave = 4 atoms x 16 slices of the partners: lane l
+// owns atom 4 b + (l & 3) and the partners k = l >> 2 (mod 16) of each
+// 64-atom tile staged in LDS, so the paper's sizes (a few thousand atoms)
+// still give the chip thousands of waves.  The sixteen partial sums of an
+// atom are combined in a fixed order by four shuffles, so results do not
+// depend on timing.
+constexpr int kApAtoms = 4, kApParts = 16, kApTile = kApAtoms * kApParts;
 
 template <typename T>
 __global__ void __launch_bounds__(kApTile) k_allpairs(const double* __restrict__ x, AllPairsArgs a,
@@ -57,15 +59,14 @@ __global__ void __launch_bounds__(kApTile) k_allpairs(const double* __restrict__
         }
         __syncthreads();
     }
-    // partial sums of lanes l, l+16, l+32, l+48: (p0 + p2) + (p1 + p3)
-    fx += __shfl_down(fx, 2 * kApAtoms);
-    fy += __shfl_down(fy, 2 * kApAtoms);
-    fz += __shfl_down(fz, 2 * kApAtoms);
-    us += __shfl_down(us, 2 * kApAtoms);
-    fx += __shfl_down(fx, kApAtoms);
-    fy += __shfl_down(fy, kApAtoms);
-    fz += __shfl_down(fz, kApAtoms);
-    us += __shfl_down(us, kApAtoms);
+    // the partial sums of lanes l, l + 4, ..., l + 60, halved four times
+#pragma unroll
+    for (int o = kApTile / 2; o >= kApAtoms; o /= 2) {
+        fx += __shfl_down(fx, o);
+        fy += __shfl_down(fy, o);
+        fz += __shfl_down(fz, o);
+        us += __shfl_down(us, o);
+    }
     if (part == 0 && live) {
         f[3 * (size_t)i] = fx;
         f[3 * (size_t)i + 1] = fy;
