@@ -114,9 +114,16 @@ def autotune(poremd, desc, prec, trial_steps, tuning_kw):
     best2, us2 = poremd.pmd_autotune(params, pore, desc.x, desc.v, cands, trial_steps)
     log("[%s] autotune shapes: %s" % (prec, ", ".join(
         "(%.2f, %d, %d, %d) %.2f" % (c + (u,)) for c, u in zip(combos, us2))))
-    sk, rb, bl, ba = combos[best2]
+    # third stage: the three fastest combinations again, five times longer
+    # each (short trials of close shapes can swap places)
+    fin = [int(i) for i in np.argsort(us2)[:3]]
+    best3, us3 = poremd.pmd_autotune(params, pore, desc.x, desc.v, [cands[i] for i in fin],
+                                     5 * trial_steps)
+    log("[%s] autotune finalists: %s" % (prec, ", ".join(
+        "(%.2f, %d, %d, %d) %.2f" % (combos[i] + (u,)) for i, u in zip(fin, us3))))
+    sk, rb, bl, ba = combos[fin[best3]]
     log("[%s] autotune choice: skin %.2f, rebuild every %d, block %d, atoms per brick %d: %.2f us/step"
-        % (prec, sk, rb, bl, ba, us2[best2]))
+        % (prec, sk, rb, bl, ba, us3[best3]))
     return dict(skin=sk, rebin_every=rb, block=bl, brick_atoms=ba)
 
 
