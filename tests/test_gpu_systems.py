@@ -170,3 +170,45 @@ def test_runs_are_reproducible(prec):
         assert np.array_equal(runs[0][0], runs[1][0])
         assert np.array_equal(runs[0][1], runs[1][1])
         assert runs[0][2] == runs[1][2]
+
+
+def test_batch_with_one_system_asking_for_the_virial():
+    """A pool runs the virial-summing step kernel when any resident system asks
+    for the sums: the other system's trajectory is the same bit for bit as
+    when it runs alone on the plain kernel, and its sums read 0; the asking
+    system's sums match its own run alone (to 1e-12, the batch gate for
+    energies) and the oracle at its positions (1e-10, the FP64 gate)."""
+    descs = _small_systems("fp64")[:2]
+    steps = [30, 44]
+    tuns = [poremd.make_tuning(rebin_every=7, energy_every=1, virial=1),
+            poremd.make_tuning(rebin_every=7, energy_every=1)]
+    alone = []
+    for d, n, t in zip(descs, steps, tuns):
+        s = poremd.System.from_desc(d, tuning=t)
+        s.step(n)
+        alone.append((s.positions(), s.energies()))
+        s.close()
+    b = poremd.pmd_batch_create(0, 4)
+    handles = [poremd.System.from_desc(d, tuning=t) for d, t in zip(descs, tuns)]
+    slots = [poremd.pmd_batch_admit(b, h.h, n) for h, n in zip(handles, steps)]
+    done = set()
+    for _ in range(100):
+        poremd.pmd_batch_advance(b, 9)
+        done |= set(poremd.pmd_batch_poll(b))
+        if len(done) == 2:
+            break
+    assert done == set(slots)
+    for k, (h, sl, (X, E)) in enumerate(zip(handles, slots, alone)):
+        poremd.pmd_batch_release(b, sl)
+        assert np.array_equal(h.positions(), X)
+        e = h.energies()
+        if k == 0:
+            assert e["virial_vv"] == pytest.approx(E["virial_vv"], rel=1e-12)
+            assert e["virial_vw"] == pytest.approx(E["virial_vw"], rel=1e-12, abs=1e-14)
+            wvv, wvw = oracle.virial(X, oracle_walls(descs[0]), oracle.make_params(descs[0].params.box))
+            assert e["virial_vv"] == pytest.approx(wvv, rel=1e-10)
+            assert e["virial_vw"] == pytest.approx(wvw, rel=1e-10, abs=1e-12)
+        else:
+            assert e["virial_vv"] == 0.0 and e["virial_vw"] == 0.0
+        h.close()
+    poremd.pmd_batch_destroy(b)
