@@ -2,6 +2,7 @@
 Sec. 3: every pair, no cutoff, no shift, minimum image) against the FP64
 oracle, through the C interface on device buffers.
 
+Sizes up to N = 7800, the largest the benchmark times (N_pore = 1500).
 Tolerances: FP64 1e-10 of the largest force (elementwise) and of the sum of
 the per-atom energy magnitudes; mixed (FP32 pair terms from FP64
 differences, FP64 sums) 2e-5 of the same scales, from a pair term's FP32
@@ -40,7 +41,7 @@ def _config(n, seed):
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 @pytest.mark.parametrize("periodic", [True, False])
-@pytest.mark.parametrize("n", [1, 2, 17, 64, 65, 1000, 1531])
+@pytest.mark.parametrize("n", [1, 2, 17, 64, 65, 1000, 1531, 7800])
 def test_allpairs_matches_the_oracle(n, periodic, prec):
     x, L = _config(n, 100 + n)
     box = (L, L, L) if periodic else (0.0, 0.0, 0.0)
