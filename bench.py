@@ -74,6 +74,39 @@ def energy_drift(tot, burn):
         np.abs(seg - seg[0]).max() / abs(seg[0]))
 
 
+def force_errors(F, F_ref):
+    """Relative force error ||F - F_ref|| / ||F_ref|| and the per-atom error
+    max_i |F_i - F_ref,i| / rms_i |F_ref,i| at identical positions."""
+    d = np.asarray(F) - np.asarray(F_ref)
+    rms = float(np.sqrt(np.mean(np.sum(F_ref * F_ref, axis=1))))
+    return (float(np.linalg.norm(d) / np.linalg.norm(F_ref)),
+            float(np.sqrt(np.sum(d * d, axis=1)).max() / rms))
+
+
+DRIFT_BURN, DRIFT_WINDOW = 100, 1000
+
+
+def accuracy_run(poremd, desc, prec, tuning_kw):
+    """Untimed: a fresh system from the workload's initial state; its forces
+    at creation (for the force error against the oracle's sample) and the
+    energy drift over DRIFT_WINDOW steps after a DRIFT_BURN-step burn-in,
+    energies recorded every step: the least-squares trend over the window and
+    the largest deviation from its first value, both relative to |E|."""
+    tun = poremd.make_tuning(**dict(tuning_kw, energy_every=1))
+    t0 = time.perf_counter()
+    s = poremd.System.from_desc(desc, precision=prec, tuning=tun)
+    F0 = s.forces()
+    s.step(DRIFT_BURN + DRIFT_WINDOW)
+    E = s.energy_history()
+    s.close()
+    burn = int(np.searchsorted(E["step"], DRIFT_BURN))
+    trend, maxdev = energy_drift(E["etotal"][: burn + DRIFT_WINDOW + 1], burn)
+    log("[accuracy %s %s] drift trend %.3e, max deviation %.3e over steps %d..%d (%.1f s)"
+        % (desc.name, prec, trend, maxdev, DRIFT_BURN, DRIFT_BURN + DRIFT_WINDOW,
+           time.perf_counter() - t0))
+    return dict(F0=F0, drift_trend=trend, drift_max=maxdev)
+
+
 def autotune(poremd, desc, prec, trial_steps, tuning_kw):
     """Skin and rebuild period from the library's autotuner (untimed): every
     candidate of its built-in grid runs trial_steps steps of this workload."""
@@ -247,25 +280,47 @@ def kernel_time(poremd, s, steps):
     return n, mean_ms
 
 
-def cpu_baseline(desc, sample_atoms, seed=0):
+def cpu_baseline(desc, sample_atoms, extra=(), extra_atoms=512, seed=0):
+    """The oracle timed on the host: its F1 sums (every partner, FP64, OpenMP
+    over the host cores) for `sample_atoms` randomly chosen vapour atoms of
+    the headline system, scaled to atom-steps per second (F1 is 99.9% of an
+    oracle step).  The same leg computes the oracle's forces for
+    `extra_atoms` atoms of each system in `extra` ((name, desc) pairs: the
+    4M-atom pores); the sampled forces serve as references for the force
+    error of the GPU paths at the same positions."""
     import oracle
+
+    def walls_of(d):
+        q = d.pore
+        return oracle.wall_lattice(oracle.make_pore(q.kind, q.lattice_a, q.slab_center_z,
+                                                    q.slab_thickness, q.r0, q.r1, q.slit_gap),
+                                   d.params.box)
 
     rng = np.random.default_rng(seed)
     sel = np.sort(rng.choice(desc.n, sample_atoms, replace=False))
     p = oracle.make_params(desc.params.box)
-    walls = oracle.wall_lattice(oracle.make_pore(desc.pore.kind, desc.pore.lattice_a,
-                                                 desc.pore.slab_center_z,
-                                                 desc.pore.slab_thickness, desc.pore.r0,
-                                                 desc.pore.r1, desc.pore.slit_gap),
-                                desc.params.box)
+    walls = walls_of(desc)
     t0 = time.perf_counter()
-    oracle.forces_subset(desc.x, walls, p, sel)
+    Fref, _ = oracle.forces_subset(desc.x, walls, p, sel)
     dt = time.perf_counter() - t0
-    return dict(value=sample_atoms / dt, unit="atom-steps/s", cores=oracle.num_threads(),
+    base = dict(value=sample_atoms / dt, unit="atom-steps/s", cores=oracle.num_threads(),
                 kind="oracle",
                 sample="F1 force sums (all %d partners each, 99.9%% of an oracle step) for %d "
                        "randomly chosen vapour atoms of the same system, %.1f s"
                        % (desc.n + walls.shape[0], sample_atoms, dt))
+    refs = {"headline": (sel, Fref)}
+    for name, d in extra:
+        r = np.random.default_rng(seed + 1)
+        zc, half = d.pore.slab_center_z, 0.5 * d.pore.slab_thickness
+        near = np.flatnonzero(np.abs(d.x[:, 2] - zc) < half + 3.0)
+        k = extra_atoms // 2
+        es = np.unique(np.concatenate([r.choice(d.n, k, replace=False),
+                                       r.choice(near, k, replace=False)]))
+        t1 = time.perf_counter()
+        Fe, _ = oracle.forces_subset(d.x, walls_of(d), oracle.make_params(d.params.box), es)
+        log("oracle sample of %s: %d atoms in %.1f s" % (name, len(es), time.perf_counter() - t1))
+        refs[name] = (es, Fe)
+    return base, refs
 
 
 def serve_leg(n_requests, budget_gb, chunk):
@@ -347,34 +402,52 @@ def batch_leg(poremd, count, steps, alone_steps, tuning_kw):
             "speedup": batched / alone, "nonfinite_systems": bad}
 
 
-def pore_sweep_leg(poremd, kinds, steps, autotune_steps, tuning_kw):
+def pore_sweep_leg(poremd, kinds, steps, autotune_steps, tuning_kw, precisions=("mixed", "fp64"),
+                   accuracy=True):
     """The dense workload: 256 x 256 x 128 box, one 8-thick wall slab with a
     pore (cylinder r = 6, cone 4 -> 12, ink-bottle 3 / 10), 4194304 vapour
-    atoms (density 0.5), mixed precision."""
+    atoms (density 0.5); the mixed path and the plain FP64 path, each with
+    its own tuning, timed over `steps` steps, plus the untimed accuracy run
+    of each.  Returns the figures and the inputs (for the oracle's sample)."""
     import torch
 
     from paper_1812_07993_amd import synth
 
-    out = {}
+    out, keep = {}, {}
     for kind in kinds:
         t0 = time.perf_counter()
         desc = synth.pore_sweep(kind)
         log("[sweep %s] %d vapour atoms generated in %.1f s" % (kind, desc.n, time.perf_counter() - t0))
-        kw = dict(tuning_kw)
-        if autotune_steps > 0:
-            kw.update(autotune(poremd, desc, "mixed", autotune_steps, tuning_kw))
-        r = run_path(poremd, desc, "mixed", steps, max(steps // 10, 10), 10, kw)
-        n_launch, kms = kernel_time(poremd, r["sys"], min(steps, 100))
-        n = desc.n
-        out[kind] = {"value": n * steps / (r["ms"] / 1000.0), "unit": "atom-steps/s",
-                     "ms_per_step": r["ms"] / steps, "steps": steps, "n_vapour": n,
-                     "n_wall": r["sys"].n_wall, "kernel_ms": kms,
-                     "roofline_frac": ALG_BYTES["mixed"] * n / (kms / 1000.0) / 1e9 / PEAK_HBM_GBS,
-                     "rebuilds": r["rebuilds"], "max_list": r["max_list"], "tuning": kw}
-        log("[sweep %s] %.3e atom-steps/s, step kernel %.3f ms" % (kind, out[kind]["value"], kms))
-        r["sys"].close()
-        torch.cuda.synchronize()
-    return out
+        row = {"n_vapour": desc.n, "steps": steps}
+        keep[kind] = {"desc": desc}
+        for prec in precisions:
+            kw = dict(tuning_kw)
+            if autotune_steps > 0:
+                kw.update(autotune(poremd, desc, prec, autotune_steps, tuning_kw))
+            r = run_path(poremd, desc, prec, steps, max(steps // 10, 10), 10, kw)
+            n_launch, kms = kernel_time(poremd, r["sys"], min(steps, 100))
+            n = desc.n
+            fig = {"value": n * steps / (r["ms"] / 1000.0), "unit": "atom-steps/s",
+                   "ms_per_step": r["ms"] / steps, "kernel_ms": kms,
+                   "roofline_frac": ALG_BYTES[prec] * n / (kms / 1000.0) / 1e9 / PEAK_HBM_GBS,
+                   "rebuilds": r["rebuilds"], "max_list": r["max_list"], "tuning": kw}
+            row["n_wall"] = r["sys"].n_wall
+            r["sys"].close()
+            torch.cuda.synchronize()
+            if accuracy:
+                acc = accuracy_run(poremd, desc, prec, kw)
+                fig["drift_trend"], fig["drift_max"] = acc["drift_trend"], acc["drift_max"]
+                keep[kind][prec] = acc["F0"]
+            log("[sweep %s %s] %.3e atom-steps/s, step kernel %.3f ms"
+                % (kind, prec, fig["value"], kms))
+            if prec == "mixed":
+                row.update(fig)  # the mixed figures at the top level of the row
+            else:
+                row[prec] = fig
+        if "mixed" in row and "fp64" in row:
+            row["mixed_over_fp64"] = row["value"] / row["fp64"]["value"]
+        out[kind] = row
+    return out, keep
 
 
 def main():
@@ -433,10 +506,12 @@ def main():
     if args.sweep_only:
         tkw = dict(skin=args.skin, rebin_every=args.rebin_every, block=args.block,
                    brick_atoms=args.brick_atoms, brick_order=args.brick_order)
-        out = {"pore_sweep": pore_sweep_leg(poremd, args.sweep.split(","), args.sweep_steps,
-                                            0 if (args.skin or args.rebin_every)
-                                            else min(args.autotune_steps, 50), tkw)}
-        print(json.dumps(out), flush=True)
+        sweep, _ = pore_sweep_leg(poremd, args.sweep.split(","), args.sweep_steps,
+                                  0 if (args.skin or args.rebin_every)
+                                  else min(args.autotune_steps, 50), tkw,
+                                  precisions=("mixed",) if args.no_fp64 else ("mixed", "fp64"),
+                                  accuracy=False)
+        print(json.dumps({"pore_sweep": sweep}), flush=True)
         return
     if args.copy_mib > 0:
         # an elementwise kernel (not a DMA copy) that reads and writes exactly
@@ -468,11 +543,9 @@ def main():
         r["kernel_ms"] = kms
         r["kernel_launches"] = n_launch
         log("[%s] step kernel mean %.4f ms over %d launches" % (prec, kms, n_launch))
-        E = r["hist"]
-        tot = E["etotal"]
-        burn = max(0, int(np.searchsorted(E["step"], args.warmup + 100)))
-        trend, maxdev = energy_drift(tot, burn)
-        r["drift_trend"], r["drift_max"] = trend, maxdev
+        # accuracy: untimed, from the initial state, independent of --steps
+        acc = accuracy_run(poremd, desc, prec, kw)
+        r["drift_trend"], r["drift_max"], r["F0"] = acc["drift_trend"], acc["drift_max"], acc["F0"]
         res[prec] = r
 
     # force error of the mixed path against the FP64 path at identical positions
@@ -522,7 +595,10 @@ def main():
                      "kernel": "k_step<float>", "kernel_ms": m["kernel_ms"],
                      "alg_bytes_per_atom_step": ALG_BYTES["mixed"]},
         "accuracy": {"mixed_drift_trend": m["drift_trend"], "mixed_drift_max": m["drift_max"],
-                     "force_err_mixed_vs_fp64": eps_f},
+                     "drift_window": "steps %d..%d of an untimed run from the initial state, "
+                                     "energies every step" % (DRIFT_BURN, DRIFT_BURN + DRIFT_WINDOW),
+                     "force_err_mixed_vs_fp64": eps_f,
+                     "force_err_mixed_vs_oracle": None, "force_err_fp64_vs_oracle": None},
         "detail": {"mixed_rebuilds": m["rebuilds"], "mixed_max_list": m["max_list"],
                    "tuning": tuned},
     }
@@ -536,15 +612,18 @@ def main():
         out["mixed_over_fp64"] = out["value"] / out["fp64"]["value"]
     for r in res.values():
         r["sys"].close()
+        r["sys"] = None
     if args.thermostat_steps > 0:
         out["thermostat"] = thermostat_leg(poremd, desc, args.thermostat_steps, tuned["mixed"])
         out["thermostat"]["over_nve"] = out["thermostat"]["value"] / out["value"]
     if args.allpairs != "none":
         out["allpairs"] = allpairs_leg(poremd, [int(v) for v in args.allpairs.split(",")])
+    sweep_keep = {}
     if args.sweep != "none":
-        out["pore_sweep"] = pore_sweep_leg(poremd, args.sweep.split(","), args.sweep_steps,
-                                           0 if (args.skin or args.rebin_every)
-                                           else min(args.autotune_steps, 50), tkw)
+        out["pore_sweep"], sweep_keep = pore_sweep_leg(
+            poremd, args.sweep.split(","), args.sweep_steps,
+            0 if (args.skin or args.rebin_every) else min(args.autotune_steps, 50), tkw,
+            precisions=("mixed",) if args.no_fp64 else ("mixed", "fp64"))
     if args.batch_systems > 0:
         out["batched"] = batch_leg(poremd, args.batch_systems, args.batch_steps, 40,
                                    tuned["mixed"])
@@ -554,7 +633,29 @@ def main():
         out["served_p99_s"] = out["serve"]["p99_s"]
     if not args.no_cpu:
         log("timing the oracle on the host ...")
-        out["cpu_baseline"] = cpu_baseline(desc, args.cpu_sample)
+        out["cpu_baseline"], refs = cpu_baseline(
+            desc, args.cpu_sample, extra=[(k, v["desc"]) for k, v in sweep_keep.items()])
+        # force errors at the initial positions against the oracle's sample
+        sel, Fref = refs["headline"]
+        for prec, r in res.items():
+            e, a = force_errors(r["F0"][sel], Fref)
+            out["accuracy"]["force_err_%s_vs_oracle" % prec] = e
+            out["accuracy"]["force_err_%s_vs_oracle_per_atom" % prec] = a
+            log("[%s] force error vs the oracle's %d-atom sample: %.3e (per atom %.3e)"
+                % (prec, len(sel), e, a))
+        out["accuracy"]["oracle_sample_atoms"] = int(len(sel))
+        for kind, kv in sweep_keep.items():
+            es, Fe = refs[kind]
+            row = out["pore_sweep"][kind]
+            for prec in ("mixed", "fp64"):
+                if prec not in kv:
+                    continue
+                e, a = force_errors(kv[prec][es], Fe)
+                tgt = row if prec == "mixed" else row[prec]
+                tgt["force_err_vs_oracle"], tgt["force_err_vs_oracle_per_atom"] = e, a
+                log("[sweep %s %s] force error vs the oracle's %d-atom sample: %.3e (per atom %.3e)"
+                    % (kind, prec, len(es), e, a))
+            row["oracle_sample_atoms"] = int(len(es))
     print(json.dumps(out), flush=True)
 
 

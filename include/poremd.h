@@ -180,17 +180,23 @@ int pmd_step(pmd_system *sys, int64_t nsteps);
  * non-finite value appeared. */
 int pmd_sync(pmd_system *sys);
 
-/* Readbacks (wait for queued work).  n must equal the system's count. */
+/* Readbacks (wait for queued work).  n must equal the system's count.  The
+ * quantities are the state the paper keeps per particle: coordinates,
+ * velocities and forces (Sec. 3), and the kinetic and potential energies of
+ * the model of Sec. 2.  Host out buffers, owned by the caller; PMD_EINVAL on
+ * a count mismatch or NULL, PMD_ENUMERIC if a non-finite value appeared. */
 int pmd_get_positions(pmd_system *sys, double *out, int64_t n);
 int pmd_get_velocities(pmd_system *sys, double *out, int64_t n);
-/* Forces on the vapour molecules at the current positions, [n][3]. */
+/* Forces on the vapour molecules at the current positions, [n][3]: f_i of
+ * Sec. 2, eq. 2 (pairs with other molecules plus the wall field). */
 int pmd_get_forces(pmd_system *sys, double *out, int64_t n);
-/* Energies at the current step. */
+/* Energies at the current step (ke, pe and their sum, Sec. 2). */
 int pmd_get_energies(pmd_system *sys, pmd_energies *out);
 /* Recorded energies, oldest first; at most cap rows; *n_out = rows written. */
 int pmd_get_energy_history(pmd_system *sys, pmd_energies *out, int64_t cap,
                            int64_t *n_out);
-/* Wall sites in the canonical order of pmd_pore, [n_wall][3]. */
+/* Wall sites in the canonical order of pmd_pore, [n_wall][3] (the fixed
+ * atoms whose field is f^ex of Sec. 2, eq. 2). */
 int pmd_get_wall_positions(pmd_system *sys, double *out, int64_t n_wall);
 int pmd_get_counts(pmd_system *sys, int64_t *n_vapor, int64_t *n_wall);
 int64_t pmd_get_step(pmd_system *sys);
@@ -292,13 +298,18 @@ int pmd_debug_lists(pmd_system *sys, int64_t *rebuilds, int64_t *max_len);
 
 /* A batch advances many systems together: one launch per phase covers all
  * resident systems, and the steps are replayed from captured HIP graphs.
+ * Each resident system takes exactly the steps of Sec. 3 (F2, F1, F3 and,
+ * with a thermostat, F4) that it would take alone, with bit-identical
+ * results; the paper runs one system at a time, so batching is a scheduling
+ * layer with no counterpart there.
  * hbm_budget bounds the device bytes the batch may hold (0 = no bound);
  * max_slots bounds the number of resident systems. */
 int pmd_batch_create(size_t hbm_budget, int max_slots, void *hip_stream,
                      pmd_batch **out);
 /* Move a system into the batch with nsteps steps to run.  Returns
- * PMD_EAGAIN if no slot or budget is free.  The system handle stays valid
- * but may not be stepped or read until released. */
+ * PMD_EAGAIN if no slot or budget is free, or if the batch's wall slots
+ * would exceed the limit of pmd_batch_wall_room.  The system handle stays
+ * valid but may not be stepped or read until released. */
 int pmd_batch_admit(pmd_batch *b, pmd_system *sys, int64_t nsteps, int *slot);
 /* Run chunk_steps steps (or fewer where a system finishes) on every resident
  * system.  Asynchronous. */
@@ -312,6 +323,13 @@ int pmd_batch_release(pmd_batch *b, int slot, pmd_system **sys_out);
 int pmd_batch_info(pmd_batch *b, int *resident, size_t *bytes_used,
                    size_t *bytes_budget);
 int pmd_batch_destroy(pmd_batch *b);
+/* The admission rule for wall atoms (host arithmetic only, no device work):
+ * a neighbour-list entry names a wall by its slot in the batch's pool in 26
+ * bits, so a batch may hold at most 2^26 - 1 wall slots in total.  Returns
+ * PMD_OK if resident_walls + new_walls fits, PMD_EAGAIN if it does not,
+ * PMD_EINVAL for a negative count.  pmd_batch_admit applies it before
+ * admitting a system. */
+int pmd_batch_wall_room(int64_t resident_walls, int64_t new_walls);
 
 /* ---- All-pairs forces (the paper's F1 as printed) ------------------------ */
 
@@ -328,8 +346,9 @@ int pmd_batch_destroy(pmd_batch *b);
  *   f_dev      device, [n][3] doubles (written).
  *   u_dev      device, [n] doubles (written): each atom's half share,
  *              sum_j u(r_ij) / 2.
- *   e_dev      device, 1 double (written): the sum of u_dev in index order
- *              (0 for n = 0).
+ *   e_dev      device, 1 double (written): the sum of u_dev (0 for n = 0),
+ *              in a fixed order that depends only on n (strided partial
+ *              sums, then a fixed tree), not in index order.
  *   stream     hipStream_t (NULL = the default stream); queued, no wait.
  * The caller owns every buffer; the sums are in a fixed order, so repeated
  * calls give identical results.  Coincident atoms give non-finite values.

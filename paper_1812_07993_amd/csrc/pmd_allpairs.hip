@@ -21,6 +21,24 @@ struct AllPairsArgs {
 // shuffles, so results do not depend on timing.
 constexpr int kApLanes = 64;
 
+// 1 / r^2, the one reciprocal a pair needs: in FP32 the hardware estimate
+// refined by one Newton-Raphson step for the reciprocal (y <- y + y (1 - a y),
+// which roughly doubles the correct bits of the estimate), in FP64 one
+// division.
+template <typename T>
+__device__ __forceinline__ T ap_recip(T a);
+template <>
+__device__ __forceinline__ float ap_recip<float>(float a)
+{
+    const float y = __builtin_amdgcn_rcpf(a);
+    return fmaf(y, fmaf(-a, y, 1.0f), y);
+}
+template <>
+__device__ __forceinline__ double ap_recip<double>(double a)
+{
+    return 1.0 / a;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kApLanes) k_allpairs(const double* __restrict__ x, AllPairsArgs a,
                                                       double* __restrict__ f, double* __restrict__ u)
@@ -38,9 +56,10 @@ __global__ void __launch_bounds__(kApLanes) k_allpairs(const double* __restrict_
         if (a.L[2] > 0.0) dz -= a.L[2] * rint(dz * a.iL[2]);
         if (j != i) {
             const T r2 = (T)(dx * dx + dy * dy + dz * dz);
-            const T s2 = sig2 / r2;
+            const T ir2 = ap_recip<T>(r2);
+            const T s2 = sig2 * ir2;
             const T s6 = s2 * s2 * s2;
-            const T w = eps24 * s6 * ((T)2 * s6 - (T)1) / r2;
+            const T w = eps24 * s6 * ((T)2 * s6 - (T)1) * ir2;
             fx += (double)(w * (T)dx);
             fy += (double)(w * (T)dy);
             fz += (double)(w * (T)dz);

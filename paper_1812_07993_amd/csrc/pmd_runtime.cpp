@@ -965,6 +965,21 @@ int make_single_pool(const Pool& like, const SysParams& sp_in, hipStream_t strea
     return PMD_OK;
 }
 
+// A wall neighbour-list entry holds the wall's slot in the whole pool in
+// kIndexBits bits (the neighbour cell's offset code sits above them), so a
+// pool may hold at most kIndexMask wall slots; past that, slots would spill
+// into the code bits and name the wrong wall.
+constexpr int64_t kMaxPoolWalls = (int64_t)kIndexMask;
+
+int check_pool_walls(int64_t resident_walls, int64_t new_walls)
+{
+    if (resident_walls < 0 || new_walls < 0) return fail(PMD_EINVAL, "negative wall count");
+    if (resident_walls + new_walls > kMaxPoolWalls)
+        return fail(PMD_EAGAIN, "wall slots would exceed %lld (%lld resident + %lld new)",
+                    (long long)kMaxPoolWalls, (long long)resident_walls, (long long)new_walls);
+    return PMD_OK;
+}
+
 // Rebuild the batch pool with capacity for its residents plus `extra`, moving
 // every resident system into tightly packed ranges.
 int batch_repack(pmd_batch* b, const Needs& extra, int extra_cap)
@@ -989,8 +1004,10 @@ int batch_repack(pmd_batch* b, const Needs& extra, int extra_cap)
     p.nslots = b->max_slots;
     p.ering_cap = kBatchErings;
     // growth room so that a stream of admissions does not repack every time
+    CHK(check_pool_walls(tot.wt - extra.wt, extra.wt));
     p.vt = round_up((int)(tot.vt * 1.25) + kPad, kPad);
-    p.wt = (int)(tot.wt * 1.25) + 1;
+    // growth room, but never past the slots a list entry can name
+    p.wt = (int)std::min<int64_t>((int64_t)(tot.wt * 1.25) + 1, kMaxPoolWalls);
     p.ct = (int)(tot.ct * 1.25) + 8;
     p.wct = (int)(tot.wct * 1.25) + 8;
     p.nbt = (int)(tot.nbt * 1.25) + 8;
@@ -1057,6 +1074,7 @@ bool batch_bump(pmd_batch* b, const Needs& n, SysParams* sp)
     int nbt = 0;
     for (size_t s = 0; s < b->resident.size(); ++s)
         if (b->resident[s]) nbt += needs_of(p.hsp[s]).nbt;
+    if ((int64_t)wo + n.wt > kMaxPoolWalls) return false;
     if (vo + n.vt > p.vt || wo + n.wt > p.wt || co + n.ct > p.ct || wco + n.wct > p.wct ||
         nbt + n.nbt > p.nbt)
         return false;
@@ -1082,6 +1100,15 @@ extern "C" {
 const char* pmd_last_error(void) { return g_err.c_str(); }
 
 int pmd_version(void) { return 100; }
+
+int pmd_batch_wall_room(int64_t resident_walls, int64_t new_walls)
+{
+    try {
+        return check_pool_walls(resident_walls, new_walls);
+    } catch (...) {
+        return fail(PMD_EHIP, "unexpected exception");
+    }
+}
 
 int pmd_allpairs_forces(int precision, int64_t n, const double* x_dev, const double box[3],
                         double epsilon, double sigma, double* f_dev, double* u_dev, double* e_dev,
@@ -1837,6 +1864,12 @@ int pmd_batch_admit(pmd_batch* b, pmd_system* sys, int64_t nsteps, int* slot)
         }
         SysParams sp = src_sp;
         const Needs n = needs_of(sp);
+        {
+            int64_t resident_walls = 0;
+            for (size_t s = 0; s < b->resident.size(); ++s)
+                if (b->resident[s]) resident_walls += needs_of(b->pool->hsp[s]).wt;
+            CHK(check_pool_walls(resident_walls, n.wt));
+        }
         if (cap > b->pool->cap || !batch_bump(b, n, &sp)) {
             CHK(batch_repack(b, n, cap));
             if (!batch_bump(b, n, &sp)) return fail(PMD_ENOMEM, "batch repack left no room");

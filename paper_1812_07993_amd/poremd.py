@@ -104,6 +104,7 @@ _SIGS = {
     "pmd_batch_info": (ctypes.c_int, [_vp, _P(ctypes.c_int), _P(ctypes.c_size_t),
                                       _P(ctypes.c_size_t)]),
     "pmd_batch_destroy": (ctypes.c_int, [_vp]),
+    "pmd_batch_wall_room": (ctypes.c_int, [_i64, _i64]),
     "pmd_allpairs_forces": (ctypes.c_int, [ctypes.c_int, _i64, _vp, _P(_d), _d, _d, _vp, _vp, _vp, _vp]),
 }
 
@@ -290,6 +291,12 @@ def pmd_get_step(h):
 def pmd_get_positions_device(h, dev_ptr, n, stream=None):
     _check(load().pmd_get_positions_device(h, ctypes.c_void_p(dev_ptr), int(n),
                                            ctypes.c_void_p(stream) if stream else None))
+
+
+def pmd_batch_wall_room(resident_walls, new_walls):
+    """PMD_OK if a batch holding resident_walls wall slots can take
+    new_walls more; raises PmdError (PMD_EAGAIN) if not."""
+    return _check(load().pmd_batch_wall_room(int(resident_walls), int(new_walls)))
 
 
 def pmd_allpairs_forces(precision, n, x_ptr, box, epsilon, sigma, f_ptr, u_ptr, e_ptr, stream=None):

@@ -84,3 +84,19 @@ def test_allpairs_rejects_bad_arguments_before_any_device_work():
     with pytest.raises(poremd.PmdError) as e:
         poremd.pmd_allpairs_forces("fp64", 4, 0, (5.0, 5.0, 5.0), 1.0, 1.0, dummy, dummy, dummy)
     assert e.value.code == poremd.PMD_EINVAL
+
+
+def test_batch_wall_slot_limit():
+    """A batch refuses admissions whose wall slots would not fit the 26-bit
+    index of a neighbour-list entry (the rule pmd_batch_admit applies)."""
+    lim = (1 << 26) - 1
+    assert poremd.pmd_batch_wall_room(0, lim) == poremd.PMD_OK
+    assert poremd.pmd_batch_wall_room(lim - 234_000, 234_000) == poremd.PMD_OK
+    for resident, new in ((0, lim + 1), (lim - 233_999, 234_000), (lim, 1), (256 * 262_144, 1)):
+        with pytest.raises(poremd.PmdError) as e:
+            poremd.pmd_batch_wall_room(resident, new)
+        assert e.value.code == poremd.PMD_EAGAIN
+        assert "wall slots" in poremd.pmd_last_error()
+    with pytest.raises(poremd.PmdError) as e:
+        poremd.pmd_batch_wall_room(-1, 5)
+    assert e.value.code == poremd.PMD_EINVAL

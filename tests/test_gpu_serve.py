@@ -40,3 +40,25 @@ def test_served_results_match_alone():
         s.close()
     summ = serve.summarize(res)
     assert summ["p99_s"] >= summ["p50_s"] > 0
+
+
+def test_served_mix_with_a_large_request_matches_alone():
+    """Three requests, one of them 120,000 vapour atoms, arriving while the
+    others run: each served result equals its run alone bit for bit."""
+    specs = [dict(index=0, arrival=0.0, n=120000, shape="slit", r=3.0, L=106.0, steps=150, precision="mixed"),
+             dict(index=1, arrival=0.005, n=3000, shape="cone", r=2.5, L=31.0, steps=220, precision="mixed"),
+             dict(index=2, arrival=0.01, n=5000, shape="inkbottle", r=3.0, L=37.0, steps=90, precision="fp64")]
+    reqs = []
+    for sp in specs:
+        d = synth.request_system(sp, seed=9)
+        reqs.append(serve.Request(sp["index"], sp["arrival"], sp["precision"], sp["steps"], sp["n"], d))
+    be = serve.PoremdBackend(hbm_budget=0, max_slots=4, keep_positions=True)
+    res = serve.Server(be, chunk_steps=25).run(reqs)
+    assert [r.status for r in res] == ["ok"] * len(reqs)
+    for req, r in zip(reqs, res):
+        s = poremd.System.from_desc(req.payload, precision=req.precision)
+        s.step(req.steps)
+        assert np.array_equal(r.output["positions"], s.positions()), req.index
+        assert np.array_equal(r.output["velocities"], s.velocities()), req.index
+        assert r.output["energies"]["etotal"] == s.energies()["etotal"]
+        s.close()

@@ -12,6 +12,7 @@ import pytest
 
 import oracle
 from paper_1812_07993_amd import poremd, synth
+from forcecheck import check_forces
 
 pytestmark = pytest.mark.gpu
 
@@ -59,33 +60,61 @@ def test_slit_128_sampled_forces(prec):
     p = oracle.make_params(desc.params.box)
     rng = np.random.default_rng(7)
     sel = np.sort(rng.choice(desc.n, 2048, replace=False))
-    tol = 1e-12 if prec == "fp64" else 1e-5
     F = s.forces()
     Fr, _ = oracle.forces_subset(desc.x, walls, p, sel)
-    assert rel(F[sel], Fr) <= tol
+    check_forces(F[sel], Fr, prec, what="slit 128^3 at creation")
     s.step(60)
     X = s.positions()
     F = s.forces()
     Fr, _ = oracle.forces_subset(X, walls, p, sel)
-    assert rel(F[sel], Fr) <= tol
+    check_forces(F[sel], Fr, prec, what="slit 128^3 after 60 steps")
 
 
-def test_pore_sweep_4m_sampled_forces():
-    """4194304 vapour atoms, 8-thick slab with a conical pore, mixed: sampled
-    forces against the oracle and the wall count derived by hand."""
-    desc = synth.pore_sweep("cone")
-    s = poremd.System.from_desc(desc, precision="mixed")
-    assert s.n_wall == 522612
+_SWEEP = {}
+
+
+def _sweep_desc(variant):
+    # one placement of 4194304 atoms per pore variant, shared by both precisions
+    if variant not in _SWEEP:
+        _SWEEP.clear()
+        _SWEEP[variant] = synth.pore_sweep(variant)
+    return _SWEEP[variant]
+
+
+@pytest.mark.parametrize("variant,n_wall,prec",
+                         [(v, nw, p) for v, nw in (("cylinder", 523392), ("cone", 522612),
+                                                   ("inkbottle", 522896))
+                          for p in ("mixed", "fp64")])
+def test_pore_sweep_4m_sampled_forces(variant, n_wall, prec):
+    """4194304 vapour atoms in a 256 x 256 x 128 box with an 8-thick slab and
+    each of the three pores, in both precisions: the wall count derived by
+    hand, and the forces of 256 sampled atoms (half of them drawn from the
+    atoms within 3 sigma of a wall site) against the oracle's all-pairs sums,
+    at creation and after 20 steps, at the GPU's positions."""
+    desc = _sweep_desc(variant)
+    s = poremd.System.from_desc(desc, precision=prec)
+    assert s.n_wall == n_wall
     walls = oracle_walls(desc)
+    assert walls.shape[0] == n_wall
     p = oracle.make_params(desc.params.box)
     rng = np.random.default_rng(3)
-    sel = np.sort(rng.choice(desc.n, 256, replace=False))
+    z = desc.x[:, 2]
+    zc, half = desc.pore.slab_center_z, 0.5 * desc.pore.slab_thickness
+    near = np.flatnonzero(np.abs(z - zc) < half + 3.0)
+    sel = np.unique(np.concatenate([rng.choice(desc.n, 128, replace=False),
+                                    rng.choice(near, 128, replace=False)]))
     F = s.forces()
     Fr, _ = oracle.forces_subset(desc.x, walls, p, sel)
-    assert rel(F[sel], Fr) <= 1e-5
+    check_forces(F[sel], Fr, prec, what="%s 4M at creation" % variant)
     s.step(20)
     e = s.energies()
     assert e["step"] == 20 and np.isfinite(e["etotal"])
+    X = s.positions()
+    assert np.all((X >= 0) & (X < np.asarray(desc.params.box)))
+    F = s.forces()
+    Fr, _ = oracle.forces_subset(X, walls, p, sel)
+    check_forces(F[sel], Fr, prec, what="%s 4M after 20 steps" % variant)
+    s.close()
 
 
 def _small_systems(prec):
@@ -210,5 +239,40 @@ def test_batch_with_one_system_asking_for_the_virial():
             assert e["virial_vw"] == pytest.approx(wvw, rel=1e-10, abs=1e-12)
         else:
             assert e["virial_vv"] == 0.0 and e["virial_vw"] == 0.0
+        h.close()
+    poremd.pmd_batch_destroy(b)
+
+
+def test_batch_of_16_replicas_matches_alone():
+    """16 replicas of the batched workload (vapour N log-uniform in [1k, 64k],
+    cylinder, slit or cone pores), each with its own step count: every
+    system's positions, velocities and energies after the batch equal its
+    run alone bit for bit (the per-atom sums do not depend on the batch)."""
+    specs = synth.replica_specs(count=16, seed=5)
+    assert max(sp["n"] for sp in specs) > 30000
+    descs = [synth.replica(sp, precision="mixed", steps=0, seed=5) for sp in specs]
+    steps = [60 + 13 * k for k in range(len(descs))]
+    tun = poremd.make_tuning(rebin_every=8)
+    alone = []
+    for d, n in zip(descs, steps):
+        s = poremd.System.from_desc(d, tuning=tun)
+        s.step(n)
+        alone.append((s.positions(), s.velocities(), s.energies()["etotal"]))
+        s.close()
+    b = poremd.pmd_batch_create(0, 16)
+    handles = [poremd.System.from_desc(d, tuning=tun) for d in descs]
+    slots = [poremd.pmd_batch_admit(b, h.h, n) for h, n in zip(handles, steps)]
+    done = set()
+    for _ in range(100):
+        poremd.pmd_batch_advance(b, 40)
+        done |= set(poremd.pmd_batch_poll(b))
+        if len(done) == len(descs):
+            break
+    assert done == set(slots)
+    for h, sl, (X, V, E) in zip(handles, slots, alone):
+        poremd.pmd_batch_release(b, sl)
+        assert np.array_equal(h.positions(), X)
+        assert np.array_equal(h.velocities(), V)
+        assert h.energies()["etotal"] == E
         h.close()
     poremd.pmd_batch_destroy(b)
