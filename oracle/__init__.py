@@ -18,7 +18,12 @@ What each function follows in arXiv:1812.07993:
   * ``wall_lattice``   -- the pore walls (the paper's walls are boundary
                           conditions, Secs. 4-5; the lattice is a reading);
   * ``cell_sort``, ``pairs`` -- the integer work of binning and neighbour
-                          search, written as their plain definitions.
+                          search, written as their plain definitions;
+  * ``pm_forces``, ``pm_trace``, ``pm_run`` -- the paper's own pore model
+                          (Secs. 4-5): all-pairs forces in 2D or 3D, a
+                          pore with reflecting walls opening into a
+                          periodic outer space, velocity Verlet F2, F1, F3
+                          and the Berendsen F4.
 """
 from __future__ import annotations
 
@@ -41,6 +46,14 @@ class Params(ctypes.Structure):
                 ("cutoff", ctypes.c_double), ("dt", ctypes.c_double),
                 ("sigma_wall", ctypes.c_double),
                 ("epsilon_wall", ctypes.c_double)]
+
+
+class PmModel(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("lx", ctypes.c_double), ("ly", ctypes.c_double), ("lz", ctypes.c_double),
+                ("k", ctypes.c_double), ("sigma", ctypes.c_double),
+                ("epsilon", ctypes.c_double), ("mass", ctypes.c_double),
+                ("dt", ctypes.c_double), ("tau", ctypes.c_double), ("t0", ctypes.c_double)]
 
 
 class Pore(ctypes.Structure):
@@ -77,6 +90,11 @@ def _load():
     lib.orc_wall_lattice.restype = i64
     lib.orc_cell_sort.argtypes = [i64, vp, vp, vp, vp, vp, vp]
     lib.orc_pairs.argtypes = [i64, vp, i64, vp, vp, d, i64, vp, P(i64), vp, P(i64)]
+    lib.orc_pm_forces.argtypes = [P(PmModel), i64, vp, vp, vp, P(d)]
+    lib.orc_pm_trace.argtypes = [P(PmModel), vp, vp, vp]
+    lib.orc_pm_trace.restype = ctypes.c_int
+    lib.orc_pm_run.argtypes = [P(PmModel), i64, vp, vp, i64, i64, vp]
+    lib.orc_pm_run.restype = i64
     _lib = lib
     return lib
 
@@ -248,3 +266,65 @@ def pairs(x, walls, box, cutoff):
                   float(cutoff), cap, _ptr(vv), ctypes.byref(nvv), _ptr(vw),
                   ctypes.byref(nvw))
     return vv[:nvv.value], vw[:nvw.value]
+
+
+# ---------------------------------------------------------------------------
+# The paper's pore model (Secs. 4-5)
+# ---------------------------------------------------------------------------
+
+def pm_model(dim, lx, ly, lz=0.0, k=1.0, sigma=1.0, epsilon=1.0, mass=1.0, dt=0.005,
+             tau=0.0, t0=0.0) -> PmModel:
+    """The pore [0, lx) x [0, ly) (x [0, lz)) with reflecting walls, open at
+    x = lx into an outer space k lx long and (2k+1) times as wide on each
+    transverse axis, periodic; all-pairs Lennard-Jones forces without
+    cutoff; Berendsen thermostat if tau > 0."""
+    m = PmModel()
+    m.dim, m.lx, m.ly, m.lz, m.k = int(dim), float(lx), float(ly), float(lz), float(k)
+    m.sigma, m.epsilon, m.mass, m.dt = float(sigma), float(epsilon), float(mass), float(dt)
+    m.tau, m.t0 = float(tau), float(t0)
+    return m
+
+
+def pm_forces(model: PmModel, x):
+    """All-pairs forces (plain differences, no images) in model.dim
+    dimensions: (forces [n, d], per-atom half shares [n], total energy)."""
+    d = model.dim
+    x = _f64(x, (-1, d))
+    n = x.shape[0]
+    f = np.zeros((n, d))
+    u = np.zeros(n)
+    e = ctypes.c_double()
+    _load().orc_pm_forces(ctypes.byref(model), n, _ptr(x), _ptr(f), _ptr(u), ctypes.byref(e))
+    return f, u, e.value
+
+
+def pm_trace(model: PmModel, p, dl, v):
+    """One particle carried along the drift dl through the model's
+    boundaries: (new position, new velocity, reflections)."""
+    p3 = np.zeros(3)
+    d3 = np.zeros(3)
+    v3 = np.zeros(3)
+    p3[:model.dim] = p
+    d3[:model.dim] = dl
+    v3[:model.dim] = v
+    r = _load().orc_pm_trace(ctypes.byref(model), _ptr(p3), _ptr(d3), _ptr(v3))
+    if r < 0:
+        raise RuntimeError("drift could not be traced")
+    return p3[:model.dim].copy(), v3[:model.dim].copy(), int(r)
+
+
+def pm_run(model: PmModel, x, v, nsteps: int, every=1):
+    """nsteps velocity-Verlet steps of the pore model (F2 with the boundary
+    trace, F1, F3, and F4 if model.tau > 0).  Returns (x, v, records) with
+    records rows (step, ke, pe, atoms in the pore, reflections so far) at
+    step 0, every `every` steps and the last step."""
+    d = model.dim
+    x = _f64(x, (-1, d)).copy()
+    v = _f64(v, (-1, d)).copy()
+    cap = 2 + (nsteps // every if every > 0 else 0) + 1
+    rec = np.zeros((cap, 5))
+    rows = _load().orc_pm_run(ctypes.byref(model), x.shape[0], _ptr(x), _ptr(v), int(nsteps),
+                              int(every), _ptr(rec))
+    if rows < 0:
+        raise RuntimeError("a drift could not be traced")
+    return x, v, rec[:rows]

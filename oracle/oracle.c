@@ -559,3 +559,246 @@ void orc_allpairs(int64_t n, const double *x, const double *box, double eps, dou
     }
     *e = tot;
 }
+
+/* ---------------------------------------------------------------------- */
+/* The paper's pore model (Secs. 4-5): all-pairs forces, reflecting pore  */
+/* walls, periodic outer space, in two or three dimensions                */
+/* ---------------------------------------------------------------------- */
+
+/* Geometry of the model, in the reading fixed for this repository (the
+ * paper describes it in words and one figure; the reflection rule itself is
+ * in a reference that is not at hand, so specular reflection is taken):
+ *   pore   P = [0, lx) x [0, ly] (x [0, lz] in 3D): walls at x = 0, y = 0,
+ *          y = ly (and z = 0, z = lz) reflect specularly; the face x = lx
+ *          is open (the pore mouth, 0 <= y < ly, 0 <= z < lz);
+ *   outer  O = [lx, (k+1) lx) x [-k ly, (k+1) ly) (x [-k lz, (k+1) lz)):
+ *          periodic along y (and z) with period (2k+1) ly (lz) and along x
+ *          with period k lx, except that a particle crossing x = lx
+ *          leftwards inside the mouth (0 <= y < ly, 0 <= z < lz) enters the
+ *          pore.  The outer space is k (2k+1)^(d-1) pore volumes: 21 for
+ *          the 2D model's k = 3, 9 for the 3D model's k = 1 (Secs. 4, 5).
+ * A particle belongs to the pore iff x < lx. */
+typedef struct {
+    int32_t dim;  /* 2 or 3 */
+    int32_t pad_;
+    double lx, ly, lz, k;
+    double sigma, epsilon, mass, dt;
+    double tau, t0; /* Berendsen thermostat (tau > 0), else NVE */
+} orc_pm_model;
+
+/* All-pairs forces in d dimensions with plain differences (no images: the
+ * model's domain is not a torus): f_i = sum_j 24 eps (2 s^12 - s^6) r_ij / r^2
+ * with s = sigma / r, and per-atom energy shares u_i = sum_j u(r_ij) / 2.
+ * Returns the total energy, summed in ascending atom order. */
+static double pm_forces(int d, int64_t n, const double *x, double sig, double eps, double *f,
+                        double *u)
+{
+    double tot = 0.0;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double fi[3] = {0.0, 0.0, 0.0}, ui = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double dd[3] = {0.0, 0.0, 0.0}, r2 = 0.0;
+            for (int k = 0; k < d; ++k) {
+                dd[k] = x[d * i + k] - x[d * j + k];
+                r2 += dd[k] * dd[k];
+            }
+            const double sr2 = sig * sig / r2, sr6 = sr2 * sr2 * sr2;
+            const double w = 24.0 * eps * sr6 * (2.0 * sr6 - 1.0) / r2;
+            for (int k = 0; k < d; ++k) fi[k] += w * dd[k];
+            ui += 4.0 * eps * sr6 * (sr6 - 1.0);
+        }
+        for (int k = 0; k < d; ++k) f[d * i + k] = fi[k];
+        u[i] = 0.5 * ui;
+    }
+    for (int64_t i = 0; i < n; ++i) tot += u[i];
+    return tot;
+}
+
+void orc_pm_forces(const orc_pm_model *m, int64_t n, const double *x, double *f, double *u,
+                   double *e)
+{
+    *e = pm_forces(m->dim, n, x, m->sigma, m->epsilon, f, u);
+}
+
+/* Carry one particle along the straight drift of one step, p -> p + dl
+ * (dl = v dt + a dt^2 / 2, the paper's F2), through the model's boundaries:
+ * the segment is followed event by event, each event being the first plane
+ * the remaining segment crosses:
+ *   in the pore:  a wall plane (x = 0; y = 0 or ly; z = 0 or lz): the
+ *                 particle stops on the plane, the normal components of the
+ *                 remaining displacement and of v change sign (specular
+ *                 reflection); the mouth plane x = lx crossed rightwards:
+ *                 the particle passes into the outer space;
+ *   in the outer: x = (k+1) lx crossed rightwards: the particle reappears at
+ *                 x = lx; x = lx crossed leftwards: inside the mouth it
+ *                 passes into the pore, elsewhere it reappears at
+ *                 x = (k+1) lx; y (z) leaving [-k l, (k+1) l): it reappears
+ *                 on the opposite face.
+ * Ties between planes go to the lowest axis first.  Returns the number of
+ * wall reflections. */
+int orc_pm_trace(const orc_pm_model *m, double *p, const double *dl_in, double *v)
+{
+    const int d = m->dim;
+    const double L[3] = {m->lx, m->ly, m->lz};
+    double dl[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < d; ++k) dl[k] = dl_in[k];
+    int in_pore = p[0] < m->lx, refl = 0;
+    for (int it = 0; it < 64; ++it) {
+        /* earliest plane crossing of the remaining segment, t in [0, 1] */
+        double tb = 2.0;
+        int ax = -1, kind = 0; /* kind: 1 reflect, 2 mouth out, 3 wrap x right,
+                                  4 cross x = lx leftwards, 5 wrap y/z */
+        double plane = 0.0;
+        for (int k = 0; k < d; ++k) {
+            if (dl[k] == 0.0) continue;
+            double w;
+            int kd;
+            if (in_pore) {
+                if (k == 0) {
+                    if (dl[0] < 0.0) { w = 0.0; kd = 1; }
+                    else { w = m->lx; kd = 2; }
+                } else {
+                    w = dl[k] < 0.0 ? 0.0 : L[k];
+                    kd = 1;
+                }
+            } else {
+                if (k == 0) {
+                    if (dl[0] > 0.0) { w = (m->k + 1.0) * m->lx; kd = 3; }
+                    else { w = m->lx; kd = 4; }
+                } else {
+                    w = dl[k] < 0.0 ? -m->k * L[k] : (m->k + 1.0) * L[k];
+                    kd = 5;
+                }
+            }
+            /* a segment ending exactly on a plane is an event only where the
+             * plane is an excluded upper face (the outer space's periodic
+             * ranges are half-open); the pore is closed in y and z */
+            const int excl = !in_pore && dl[k] > 0.0;
+            const double t = (w - p[k]) / dl[k];
+            if ((t < 1.0 || (excl && t <= 1.0)) && t < tb) {
+                tb = t < 0.0 ? 0.0 : t;
+                ax = k;
+                kind = kd;
+                plane = w;
+            }
+        }
+        if (ax < 0) {
+            for (int k = 0; k < d; ++k) p[k] += dl[k];
+            return refl;
+        }
+        for (int k = 0; k < d; ++k) {
+            if (k == ax) {
+                p[k] = plane;
+            } else {
+                p[k] += tb * dl[k];
+            }
+            dl[k] *= (1.0 - tb);
+        }
+        switch (kind) {
+        case 1:
+            dl[ax] = -dl[ax];
+            v[ax] = -v[ax];
+            ++refl;
+            break;
+        case 2:
+            in_pore = 0;
+            break;
+        case 3:
+            p[0] = m->lx;
+            break;
+        case 4: {
+            int mouth = p[1] >= 0.0 && p[1] < m->ly;
+            if (d == 3) mouth = mouth && p[2] >= 0.0 && p[2] < m->lz;
+            if (mouth)
+                in_pore = 1;
+            else
+                p[0] = (m->k + 1.0) * m->lx;
+            break;
+        }
+        case 5:
+            p[ax] = dl[ax] < 0.0 ? (m->k + 1.0) * L[ax] : -m->k * L[ax];
+            break;
+        }
+    }
+    return -1; /* more events than any step can hold: not a valid drift */
+}
+
+/* Advance n particles of the pore model by nsteps velocity-Verlet steps:
+ *   F2: dl = v dt + a dt^2 / 2, v <- v + a dt / 2, the particle carried
+ *       along dl by orc_pm_trace;
+ *   F1: a = f / m from the all-pairs forces at the new positions;
+ *   F3: v <- v + a dt / 2;
+ *   F4 (tau > 0): v <- lambda v, lambda = sqrt(1 + (dt / tau) (t0 / T - 1)),
+ *       T = 2 K / (d n) from the F3 velocities (the walls break momentum
+ *       conservation, so every degree of freedom counts).
+ * x, v: [n][d], updated in place.  a: [n][d] scratch.  rec, if not NULL,
+ * receives rows (step, ke, pe, n_pore, reflections so far) for step 0,
+ * every step that is a multiple of every, and the last step; returns the
+ * rows written, or -1 if a drift could not be traced. */
+int64_t orc_pm_run(const orc_pm_model *m, int64_t n, double *x, double *v, int64_t nsteps,
+                   int64_t every, double *rec)
+{
+    const int d = m->dim;
+    const double dt = m->dt, ms = m->mass;
+    double *f = (double *)malloc(sizeof(double) * (size_t)(d * (n > 0 ? n : 1)));
+    double *u = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *a = (double *)malloc(sizeof(double) * (size_t)(d * (n > 0 ? n : 1)));
+    int64_t rows = 0, refl = 0;
+    double pe = pm_forces(d, n, x, m->sigma, m->epsilon, f, u);
+    for (int64_t q = 0; q < d * n; ++q) a[q] = f[q] / ms;
+    for (int64_t s = 0; s <= nsteps; ++s) {
+        if (s > 0) {
+            for (int64_t i = 0; i < n; ++i) {
+                double p[3] = {0.0, 0.0, 0.0}, dl[3] = {0.0, 0.0, 0.0}, vv[3] = {0.0, 0.0, 0.0};
+                for (int k = 0; k < d; ++k) {
+                    p[k] = x[d * i + k];
+                    dl[k] = v[d * i + k] * dt + 0.5 * a[d * i + k] * dt * dt;
+                    vv[k] = v[d * i + k] + 0.5 * a[d * i + k] * dt;
+                }
+                const int r = orc_pm_trace(m, p, dl, vv);
+                if (r < 0) {
+                    rows = -1;
+                    goto out;
+                }
+                refl += r;
+                for (int k = 0; k < d; ++k) {
+                    x[d * i + k] = p[k];
+                    v[d * i + k] = vv[k];
+                }
+            }
+            pe = pm_forces(d, n, x, m->sigma, m->epsilon, f, u);
+            for (int64_t q = 0; q < d * n; ++q) {
+                a[q] = f[q] / ms;
+                v[q] += 0.5 * a[q] * dt;
+            }
+        }
+        double ke = 0.0;
+        int64_t np = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            double s2 = 0.0;
+            for (int k = 0; k < d; ++k) s2 += v[d * i + k] * v[d * i + k];
+            ke += 0.5 * ms * s2;
+            np += x[d * i] < m->lx;
+        }
+        if (rec && (s == 0 || s == nsteps || (every > 0 && s % every == 0))) {
+            rec[5 * rows + 0] = (double)s;
+            rec[5 * rows + 1] = ke;
+            rec[5 * rows + 2] = pe;
+            rec[5 * rows + 3] = (double)np;
+            rec[5 * rows + 4] = (double)refl;
+            ++rows;
+        }
+        if (s > 0 && m->tau > 0.0 && n > 0) {
+            const double T = 2.0 * ke / ((double)d * (double)n);
+            const double lam = sqrt(1.0 + (dt / m->tau) * (m->t0 / T - 1.0));
+            for (int64_t q = 0; q < d * n; ++q) v[q] *= lam;
+        }
+    }
+out:
+    free(f);
+    free(u);
+    free(a);
+    return rows;
+}
