@@ -269,6 +269,65 @@ def allpairs_leg(poremd, n_pores, calls=50):
     return rows
 
 
+# The paper's own per-step times (ms) of its full GPU step at N_pore = 100,
+# 200, ..., 1500 molecules in the pore, 128-thread blocks, on its cluster's
+# GPU (Tables 2 and 3, "total GPU time"): context, not a target.
+PAPER_GPU_MS = {
+    2: [1.577, 2.957, 4.371, 5.541, 7.040, 8.317, 9.660, 10.563, 12.675, 13.706, 15.175, 17.212,
+        18.956, 19.767, 21.522],
+    3: [1.042, 1.776, 2.504, 3.374, 4.115, 4.829, 5.571, 6.162, 7.276, 8.175, 9.035, 9.924, 10.501,
+        11.587, 12.434],
+}
+
+
+def paper_model_leg(poremd, dims=(2, 3), n_pores=tuple(range(100, 1501, 100)), steps=2000,
+                    precision="fp64"):
+    """The paper's own workload (Secs. 4-5): its 2D pore (1 um, k = 3, 35 C)
+    and 3D prism (500 x 50 x 50 nm, k = 1, 25 C) with N_pore molecules in the
+    pore and a fifth of the pore density outside, all-pairs forces, reflecting
+    pore walls, periodic outer space, the Berendsen thermostat on (rise time
+    1 ps), dt = 0.016 ps: the full step (F2, F1, F3, F4) timed over `steps`
+    steps with HIP events on the stream, as in Tables 2 and 3."""
+    import torch
+
+    from paper_1812_07993_amd import synth
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    out = {}
+    for dim in dims:
+        rows = []
+        for i, npore in enumerate(n_pores):
+            x, v, geo = synth.paper_model_system(dim, npore)
+            n = x.shape[0]
+            m = poremd.make_pm_model(dim, geo["lx"], geo["ly"], geo["lz"], geo["k"], precision,
+                                     dt=geo["dt"], thermostat_tau=1.0 / synth.PAPER_TAU_PS,
+                                     thermostat_t0=geo["temperature"])
+            xd = torch.as_tensor(x, dtype=torch.float64, device=dev)
+            vd = torch.as_tensor(v, dtype=torch.float64, device=dev)
+            rec = torch.zeros((2, 8), dtype=torch.float64, device=dev)
+            poremd.pmd_pm_run(m, n, xd.data_ptr(), vd.data_ptr(), 0, 20, 0, rec.data_ptr(), 2,
+                              stream.cuda_stream)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            poremd.pmd_pm_run(m, n, xd.data_ptr(), vd.data_ptr(), 0, steps, 0, rec.data_ptr(), 2,
+                              stream.cuda_stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            r = rec.cpu().numpy().view(poremd.PM_RECORD_DTYPE).reshape(2)
+            row = {"n_pore": npore, "n": n, "ms_per_step": ms, "us_per_particle_step": 1000 * ms / n,
+                   "pairs_per_s": n * (n - 1) / (ms / 1000.0), "n_outside": int(r["n_outside"][-1]),
+                   "paper_gpu_ms": PAPER_GPU_MS[dim][i] if len(n_pores) == 15 else None}
+            rows.append(row)
+        log("[paper %dD] ms per step at N_pore %s: %s" % (dim, ",".join(str(r["n_pore"]) for r in rows),
+                                                       ", ".join("%.4f" % r["ms_per_step"] for r in rows)))
+        out["%dd" % dim] = rows
+    return out
+
+
 def kernel_time(poremd, s, steps):
     """Mean duration of one step-kernel launch, from HIP events around the R
     back-to-back launches of each replay that did R full steps."""
@@ -484,6 +543,8 @@ def main():
     ap.add_argument("--allpairs", default="100,500,1500",
                     help="pore molecule counts of the all-pairs force leg, or 'none'")
     ap.add_argument("--timing-steps", type=int, default=500)
+    ap.add_argument("--paper-model", default="fp64",
+                    help="precision of the paper-model table (fp64 or mixed), or 'none'")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="before the timed run, one plain device-to-device copy of this many "
                          "MiB (a known-size kernel to scale the hardware byte counters by)")
@@ -619,6 +680,8 @@ def main():
     if args.allpairs != "none":
         out["allpairs"] = allpairs_leg(poremd, [int(v) for v in args.allpairs.split(",")])
     sweep_keep = {}
+    if args.paper_model != "none":
+        out["paper_model"] = paper_model_leg(poremd, precision=args.paper_model)
     if args.sweep != "none":
         out["pore_sweep"], sweep_keep = pore_sweep_leg(
             poremd, args.sweep.split(","), args.sweep_steps,

@@ -360,6 +360,84 @@ int pmd_allpairs_forces(int precision, int64_t n, const double *x_dev,
                         double *f_dev, double *u_dev, double *e_dev,
                         void *stream);
 
+/* ---- The paper's pore model (Secs. 4-5) --------------------------------- */
+
+/* The model the paper times: N molecules in two (Sec. 4) or three (Sec. 5)
+ * dimensions; every pair interacts through u(r) = 4 eps ((sigma/r)^12 -
+ * (sigma/r)^6) with no cutoff and plain differences r_ij = x_i - x_j (the
+ * domain is not a torus, so no images); no wall atoms.  The domain:
+ *   pore   [0, lx) x [0, ly] (x [0, lz] in 3D), whose walls x = 0, y = 0,
+ *          y = ly (z = 0, z = lz) reflect molecules specularly (Secs. 4, 5:
+ *          reflecting pore walls; the rule is specular reflection of the
+ *          normal velocity component), open at x = lx (the mouth,
+ *          0 <= y < ly, 0 <= z < lz);
+ *   outer  [lx, (k+1) lx) x [-k ly, (k+1) ly) (x [-k lz, (k+1) lz)), its
+ *          faces periodic (Secs. 4, 5), except that a molecule crossing
+ *          x = lx leftwards inside the mouth enters the pore.  Its volume is
+ *          k (2k+1)^(dim-1) pore volumes: 21 at k = 3 in 2D (Sec. 4), 9 at
+ *          k = 1 in 3D (Sec. 5).
+ * A molecule belongs to the pore iff x < lx.  Positions and velocities are
+ * [n][dim] doubles. */
+typedef struct {
+    int32_t dim;          /* 2 or 3 */
+    int32_t precision;    /* 1 = FP32 pair terms (from FP64 differences) with
+                             FP64 sums; 2 = FP64 throughout */
+    double lx, ly, lz;    /* pore edges (lz unused in 2D) */
+    double k;             /* outer-space scale, > 0 */
+    double sigma, epsilon, mass, dt;
+    double thermostat_tau, thermostat_t0;  /* Berendsen F4 if tau > 0 */
+} pmd_pm_model;
+
+/* One energy record of a pore-model run. */
+typedef struct {
+    int64_t step;
+    double ke;            /* (m/2) sum |v|^2 after F3 (before the F4 scaling) */
+    double pe;            /* sum over pairs i < j of u(r_ij) */
+    double etotal;        /* ke + pe */
+    double temperature;   /* 2 ke / (dim n): the reflecting walls break
+                             momentum conservation, so every degree of
+                             freedom counts */
+    int64_t n_pore;       /* molecules with x < lx */
+    int64_t reflections;  /* wall reflections since the run started */
+    int64_t n_outside;    /* molecules outside the domain, plus drifts that
+                             could not be traced; 0 in a valid run */
+} pmd_pm_record;
+
+/* Rows a run of nsteps steps records with energy_every (host arithmetic):
+ * step 0, every multiple of energy_every (if > 0) and the last step. */
+int64_t pmd_pm_record_rows(int64_t nsteps, int64_t energy_every);
+
+/* Advance n molecules of the pore model by nsteps velocity-Verlet steps in
+ * the order of the paper's GPU functions (Sec. 3):
+ *   F2  dl = v dt + a dt^2 / 2, v <- v + a dt / 2, and the molecule carried
+ *       along dl through the walls, the mouth and the periodic faces;
+ *   F1  a = f / m from the all-pairs forces at the new positions;
+ *   F3  v <- v + a dt / 2;
+ *   F4  with thermostat_tau > 0: v <- lambda v, lambda = sqrt(1 + (dt / tau)
+ *       (t0 / T - 1)), T from the F3 velocities (Sec. 2's Berendsen
+ *       thermostat; the paper gives its rise time, not the formula).
+ * The accelerations at the start are computed from x (a run always starts
+ * from positions and velocities alone).
+ *   x_dev, v_dev  device, [n][dim] doubles, updated in place; positions
+ *                 must lie in the domain (a record's n_outside counts any
+ *                 that do not).
+ *   a_dev         device, [n][dim] doubles (NULL = not wanted): receives
+ *                 the accelerations f / m at the final positions.
+ *   rec_dev       device, rec_cap records (NULL = none): step 0, every
+ *                 energy_every-th step and the last step, in order.
+ *   stream        hipStream_t (NULL = the default stream); queued, no wait.
+ * Working memory ((dim + 2) n + 2 doubles) is taken from the stream-ordered
+ * allocator for the call and returned at its end.  Sums are in a fixed
+ * order: repeated runs give identical results.  Returns PMD_EINVAL for a
+ * dim other than 2 or 3, a precision other than 1 or 2, n outside 0..2^20,
+ * a null buffer with n > 0, a non-positive or non-finite length, k, sigma,
+ * mass or dt, a thermostat with tau < dt or t0 <= 0, or rec_cap below
+ * pmd_pm_record_rows; PMD_ENOMEM if the working memory cannot be had. */
+int pmd_pm_run(const pmd_pm_model *model, int64_t n, double *x_dev,
+               double *v_dev, double *a_dev, int64_t nsteps,
+               int64_t energy_every, pmd_pm_record *rec_dev, int64_t rec_cap,
+               void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,50 @@
+// The paper's pore model (all-pairs forces, reflecting pore walls, periodic
+// outer space, 2D or 3D): launch of its steps, called by the C entry points
+// pmd_pm_run and pmd_pm_run_noalloc.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace pmd {
+
+struct PmArgs {
+    int n, dim, precision;  // precision: 1 FP32 pair terms, 2 FP64
+    double lx, ly, lz, k;
+    double sig2, eps4, eps24, mass, inv_mass, dt, hdt, tau, t0;
+};
+
+// Per-run working memory: accelerations [n][dim], per-molecule kinetic
+// energy and pair-energy share [n] each, two counters (wall reflections,
+// drifts that could not be traced).
+struct PmWork {
+    double* acc;
+    double* ke;
+    double* u;
+    long long* counts;
+};
+
+// Same layout as pmd_pm_record of the C interface.
+struct PmRecord {
+    long long step;
+    double ke, pe, etotal, temperature;
+    long long n_pore, reflections, n_outside;
+};
+
+// Doubles of working memory a run of n molecules in dim dimensions needs
+// (the counters included, rounded up).
+inline size_t pm_work_doubles(long long n, int dim) { return (size_t)n * (dim + 2) + 2; }
+
+inline PmWork pm_work_at(double* base, long long n, int dim)
+{
+    PmWork w;
+    w.acc = base;
+    w.ke = base + (size_t)n * dim;
+    w.u = w.ke + n;
+    w.counts = (long long*)(w.u + n);
+    return w;
+}
+
+hipError_t launch_pm_run(const PmArgs& a, double* x, double* v, PmWork w, long long nsteps,
+                         long long every, PmRecord* rec, hipStream_t s);
+
+}  // namespace pmd

@@ -1,0 +1,331 @@
+// The paper's own pore model (Secs. 4-5) on the GPU: N molecules in two or
+// three dimensions, every pair interacting through the Lennard-Jones
+// potential with no cutoff, a pore whose walls reflect molecules specularly
+// and whose open face leads into a periodic outer space; velocity Verlet in
+// the order of the paper's GPU functions (F2 drift and half-kick, F1 forces,
+// F3 half-kick) and the Berendsen F4.
+//
+// One step is two launches:
+//   k_pm_forces  one wave per molecule, its partners split over the 64 lanes
+//                and read straight from memory (a few hundred KB at the
+//                paper's sizes, L2-resident), the lane sums combined by a
+//                fixed tree of shuffles; lane 0 forms the acceleration, the
+//                F3 half-kick, the kinetic energy and the energy share;
+//   k_pm_update  one workgroup: the step's kinetic and potential energies in
+//                a fixed order, the record, the Berendsen factor, and for
+//                every molecule F4 and the next step's F2 with the boundary
+//                trace.
+// This file shares nothing with the cell-list path or the all-pairs entry.
+#include <hip/hip_runtime.h>
+
+#include "pmd_paper.h"
+
+namespace pmd {
+
+constexpr int kPmLanes = 64;
+constexpr int kPmUpdate = 1024;
+
+// 1 / r^2: in FP32 the hardware estimate refined by one Newton-Raphson step
+// for the reciprocal (y + y (1 - a y)), in FP64 one division.
+template <typename T>
+__device__ __forceinline__ T pm_recip(T a);
+template <>
+__device__ __forceinline__ float pm_recip<float>(float a)
+{
+    const float y = __builtin_amdgcn_rcpf(a);
+    return fmaf(y, fmaf(-a, y, 1.0f), y);
+}
+template <>
+__device__ __forceinline__ double pm_recip<double>(double a)
+{
+    return 1.0 / a;
+}
+
+// Forces (F1) at the current positions, then with KICK the F3 half-kick;
+// writes each molecule's acceleration, kinetic energy and half share of the
+// pair energies.
+template <typename T, int D, bool KICK>
+__global__ void __launch_bounds__(kPmLanes) k_pm_forces(const double* __restrict__ x,
+                                                       double* __restrict__ v, PmWork w, PmArgs a)
+{
+    const int lane = threadIdx.x;
+    const int i = blockIdx.x;  // the grid has exactly n workgroups
+    double xi[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) xi[k] = x[(size_t)D * i + k];
+    double f[D], us = 0.0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) f[k] = 0.0;
+    const T sig2 = (T)a.sig2, eps4 = (T)a.eps4, eps24 = (T)a.eps24;
+#pragma unroll 2
+    for (int j = lane; j < a.n; j += kPmLanes) {
+        double d[D];
+        double r2d = 0.0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            d[k] = xi[k] - x[(size_t)D * j + k];
+            r2d += d[k] * d[k];
+        }
+        if (j != i) {
+            const T ir2 = pm_recip<T>((T)r2d);
+            const T s2 = sig2 * ir2;
+            const T s6 = s2 * s2 * s2;
+            const T wf = eps24 * s6 * ((T)2 * s6 - (T)1) * ir2;
+#pragma unroll
+            for (int k = 0; k < D; ++k) f[k] += (double)(wf * (T)d[k]);
+            us += (double)(eps4 * s6 * (s6 - (T)1));
+        }
+    }
+#pragma unroll
+    for (int o = kPmLanes / 2; o >= 1; o /= 2) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) f[k] += __shfl_down(f[k], o);
+        us += __shfl_down(us, o);
+    }
+    if (lane == 0) {
+        double ke = 0.0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            const double ak = f[k] * a.inv_mass;
+            w.acc[(size_t)D * i + k] = ak;
+            double vk = v[(size_t)D * i + k];
+            if (KICK) {
+                vk += a.hdt * ak;
+                v[(size_t)D * i + k] = vk;
+            }
+            ke += vk * vk;
+        }
+        w.ke[i] = 0.5 * a.mass * ke;
+        w.u[i] = 0.5 * us;
+    }
+}
+
+// The drift of one step, p -> p + dl, carried through the model's
+// boundaries event by event (each event the first plane the rest of the
+// segment meets): in the pore, the walls x = 0, y = 0, y = ly (z = 0, z = lz)
+// reflect (the normal components of the rest of dl and of v flip) and the
+// mouth x = lx lets the molecule out; in the outer space, leaving through
+// x = (k+1) lx brings it back at x = lx, crossing x = lx leftwards takes it
+// into the pore inside the mouth and back to x = (k+1) lx elsewhere, and the
+// transverse faces are periodic.  A segment that ends exactly on a plane
+// makes an event only on the outer space's excluded upper faces.  Ties go to
+// the lowest axis.  Returns the reflections, or -1 if the events do not end.
+template <int D>
+__device__ int pm_trace(const PmArgs& a, double* p, double* dl, double* v)
+{
+    const double Lw[3] = {a.lx, a.ly, a.lz};
+    bool pore = p[0] < a.lx;
+    int refl = 0;
+    for (int it = 0; it < 64; ++it) {
+        double tb = 2.0, plane = 0.0;
+        int ax = -1, kind = 0;  // 1 reflect, 2 out of the mouth, 3 wrap x, 4 x = lx leftwards, 5 wrap y/z
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            if (dl[k] == 0.0) continue;
+            double wpl;
+            int kd;
+            if (pore) {
+                if (k == 0) {
+                    wpl = dl[0] < 0.0 ? 0.0 : a.lx;
+                    kd = dl[0] < 0.0 ? 1 : 2;
+                } else {
+                    wpl = dl[k] < 0.0 ? 0.0 : Lw[k];
+                    kd = 1;
+                }
+            } else {
+                if (k == 0) {
+                    wpl = dl[0] > 0.0 ? (a.k + 1.0) * a.lx : a.lx;
+                    kd = dl[0] > 0.0 ? 3 : 4;
+                } else {
+                    wpl = dl[k] < 0.0 ? -a.k * Lw[k] : (a.k + 1.0) * Lw[k];
+                    kd = 5;
+                }
+            }
+            const bool excl = !pore && dl[k] > 0.0;
+            const double t = (wpl - p[k]) / dl[k];
+            if ((t < 1.0 || (excl && t <= 1.0)) && t < tb) {
+                tb = t < 0.0 ? 0.0 : t;
+                ax = k;
+                kind = kd;
+                plane = wpl;
+            }
+        }
+        if (ax < 0) {
+#pragma unroll
+            for (int k = 0; k < D; ++k) p[k] += dl[k];
+            return refl;
+        }
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            p[k] = k == ax ? plane : p[k] + tb * dl[k];
+            dl[k] *= 1.0 - tb;
+        }
+        if (kind == 1) {
+            dl[ax] = -dl[ax];
+            v[ax] = -v[ax];
+            ++refl;
+        } else if (kind == 2) {
+            pore = false;
+        } else if (kind == 3) {
+            p[0] = a.lx;
+        } else if (kind == 4) {
+            bool mouth = p[1] >= 0.0 && p[1] < a.ly;
+            if (D == 3) mouth = mouth && p[D - 1] >= 0.0 && p[D - 1] < a.lz;
+            if (mouth)
+                pore = true;
+            else
+                p[0] = (a.k + 1.0) * a.lx;
+        } else {
+            p[ax] = dl[ax] < 0.0 ? (a.k + 1.0) * Lw[ax] : -a.k * Lw[ax];
+        }
+    }
+    return -1;
+}
+
+// Whether a position lies in the model's domain (pore or outer space).
+template <int D>
+__device__ bool pm_inside(const PmArgs& a, const double* p)
+{
+    const double Lw[3] = {a.lx, a.ly, a.lz};
+    bool in;
+    if (p[0] >= 0.0 && p[0] < a.lx) {
+        in = true;
+#pragma unroll
+        for (int k = 1; k < D; ++k) in = in && p[k] >= 0.0 && p[k] <= Lw[k];
+    } else {
+        in = p[0] >= a.lx && p[0] < (a.k + 1.0) * a.lx;
+#pragma unroll
+        for (int k = 1; k < D; ++k) in = in && p[k] >= -a.k * Lw[k] && p[k] < (a.k + 1.0) * Lw[k];
+    }
+    return in;
+}
+
+// Fixed-order workgroup sum: every thread's partial, then a tree over LDS.
+__device__ double pm_block_sum(double s, double* red)
+{
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = kPmUpdate / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    const double t = red[0];
+    __syncthreads();
+    return t;
+}
+
+// End of step `step` (0 = the initial state): the energies (kinetic energy of
+// the F3 velocities, pair energy at the current positions), the record, and
+// then, for every molecule, F4 (Berendsen scaling, steps >= 1 with a
+// thermostat) and, with drift, the next step's F2: dl = v dt + a dt^2 / 2,
+// v <- v + a dt / 2, the molecule carried along dl through the boundaries.
+template <int D>
+__global__ void __launch_bounds__(kPmUpdate) k_pm_update(double* __restrict__ x, double* __restrict__ v,
+                                                        PmWork w, PmArgs a, long long step, int rec_row,
+                                                        int thermo, int drift, PmRecord* __restrict__ rec)
+{
+    __shared__ double red[kPmUpdate];
+    const int tid = threadIdx.x;
+    double ke = 0.0, pe = 0.0, np = 0.0, out = 0.0;
+    for (int i = tid; i < a.n; i += kPmUpdate) {
+        ke += w.ke[i];
+        pe += w.u[i];
+        double p[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) p[k] = x[(size_t)D * i + k];
+        np += p[0] < a.lx ? 1.0 : 0.0;
+        out += pm_inside<D>(a, p) ? 0.0 : 1.0;
+    }
+    ke = pm_block_sum(ke, red);
+    pe = pm_block_sum(pe, red);
+    np = pm_block_sum(np, red);
+    out = pm_block_sum(out, red);
+    const double T = a.n > 0 ? 2.0 * ke / ((double)D * (double)a.n) : 0.0;
+    if (tid == 0 && rec_row >= 0) {
+        PmRecord r;
+        r.step = step;
+        r.ke = ke;
+        r.pe = pe;
+        r.etotal = ke + pe;
+        r.temperature = T;
+        r.n_pore = (long long)np;
+        r.reflections = step == 0 ? 0LL : w.counts[0];
+        r.n_outside = (long long)out + (step == 0 ? 0LL : w.counts[1]);
+        rec[rec_row] = r;
+    }
+    const double lam = thermo && a.n > 0 ? sqrt(1.0 + (a.dt / a.tau) * (a.t0 / T - 1.0)) : 1.0;
+    double refl = 0.0, bad = 0.0;
+    if (thermo || drift) {
+        for (int i = tid; i < a.n; i += kPmUpdate) {
+            double p[D], vv[D], dl[D];
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                vv[k] = v[(size_t)D * i + k];
+                if (thermo) vv[k] *= lam;
+            }
+            if (drift) {
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    const double ak = w.acc[(size_t)D * i + k];
+                    p[k] = x[(size_t)D * i + k];
+                    dl[k] = vv[k] * a.dt + 0.5 * ak * a.dt * a.dt;
+                    vv[k] += a.hdt * ak;
+                }
+                const int r = pm_trace<D>(a, p, dl, vv);
+                if (r < 0)
+                    bad += 1.0;
+                else
+                    refl += (double)r;
+#pragma unroll
+                for (int k = 0; k < D; ++k) x[(size_t)D * i + k] = p[k];
+            }
+#pragma unroll
+            for (int k = 0; k < D; ++k) v[(size_t)D * i + k] = vv[k];
+        }
+    }
+    refl = pm_block_sum(refl, red);
+    bad = pm_block_sum(bad, red);
+    if (tid == 0) {
+        // the counts start with the run (no memset node: callers may capture)
+        w.counts[0] = (step == 0 ? 0LL : w.counts[0]) + (long long)refl;
+        w.counts[1] = (step == 0 ? 0LL : w.counts[1]) + (long long)bad;
+    }
+}
+
+template <int D>
+static hipError_t pm_run_dim(const PmArgs& a, double* x, double* v, PmWork w, long long nsteps,
+                             long long every, PmRecord* rec, hipStream_t s)
+{
+    const dim3 gf((unsigned)a.n), bf(kPmLanes), gu(1), bu(kPmUpdate);
+    const bool thermo = a.tau > 0.0;
+    int row = 0;
+    if (a.n > 0) {
+        if (a.precision == 1)
+            hipLaunchKernelGGL((k_pm_forces<float, D, false>), gf, bf, 0, s, x, v, w, a);
+        else
+            hipLaunchKernelGGL((k_pm_forces<double, D, false>), gf, bf, 0, s, x, v, w, a);
+    }
+    hipLaunchKernelGGL(k_pm_update<D>, gu, bu, 0, s, x, v, w, a, 0LL, rec ? row++ : -1, 0,
+                       nsteps > 0 ? 1 : 0, rec);
+    for (long long st = 1; st <= nsteps; ++st) {
+        if (a.n > 0) {
+            if (a.precision == 1)
+                hipLaunchKernelGGL((k_pm_forces<float, D, true>), gf, bf, 0, s, x, v, w, a);
+            else
+                hipLaunchKernelGGL((k_pm_forces<double, D, true>), gf, bf, 0, s, x, v, w, a);
+        }
+        const bool record = rec && (st == nsteps || (every > 0 && st % every == 0));
+        hipLaunchKernelGGL(k_pm_update<D>, gu, bu, 0, s, x, v, w, a, st, record ? row++ : -1,
+                           thermo ? 1 : 0, st < nsteps ? 1 : 0, rec);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_pm_run(const PmArgs& a, double* x, double* v, PmWork w, long long nsteps,
+                         long long every, PmRecord* rec, hipStream_t s)
+{
+    return a.dim == 2 ? pm_run_dim<2>(a, x, v, w, nsteps, every, rec, s)
+                      : pm_run_dim<3>(a, x, v, w, nsteps, every, rec, s);
+}
+
+}  // namespace pmd

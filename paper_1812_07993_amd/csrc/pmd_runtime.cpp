@@ -19,6 +19,7 @@
 #include "../../include/poremd.h"
 #include "pmd_allpairs.h"
 #include "pmd_internal.h"
+#include "pmd_paper.h"
 
 using namespace pmd;
 
@@ -1125,6 +1126,98 @@ int pmd_allpairs_forces(int precision, int64_t n, const double* x_dev, const dou
             if (!std::isfinite(box[k])) return fail(PMD_EINVAL, "box edges must be finite");
         HIPCHK(launch_allpairs(precision, (int)n, x_dev, box, epsilon, sigma, f_dev, u_dev, e_dev,
                                (hipStream_t)stream));
+        return PMD_OK;
+    } catch (...) {
+        return fail(PMD_EHIP, "unexpected exception");
+    }
+}
+
+int64_t pmd_pm_record_rows(int64_t nsteps, int64_t energy_every)
+{
+    if (nsteps < 0) return 0;
+    int64_t rows = 1 + (energy_every > 0 ? nsteps / energy_every : 0);
+    if (nsteps > 0 && (energy_every <= 0 || nsteps % energy_every != 0)) ++rows;
+    return rows;
+}
+
+}  // extern "C"
+
+namespace {
+
+static_assert(sizeof(PmRecord) == sizeof(pmd_pm_record), "record layouts differ");
+
+// Checks shared by the pore-model entry points; fills the kernel arguments.
+int pm_check(const pmd_pm_model* m, int64_t n, const double* x_dev, const double* v_dev,
+             int64_t nsteps, int64_t energy_every, const pmd_pm_record* rec_dev, int64_t rec_cap,
+             int64_t n_max, PmArgs* out)
+{
+    if (!m) return fail(PMD_EINVAL, "model must not be NULL");
+    if (m->dim != 2 && m->dim != 3) return fail(PMD_EINVAL, "dim must be 2 or 3 (got %d)", m->dim);
+    if (m->precision != 1 && m->precision != 2)
+        return fail(PMD_EINVAL, "precision must be 1 or 2 (got %d)", m->precision);
+    if (n < 0 || n > n_max) return fail(PMD_EINVAL, "n must be in 0..%lld (got %lld)", (long long)n_max, (long long)n);
+    if (n > 0 && (!x_dev || !v_dev)) return fail(PMD_EINVAL, "need x_dev and v_dev for n > 0");
+    if (nsteps < 0 || nsteps > ((int64_t)1 << 40)) return fail(PMD_EINVAL, "nsteps out of range");
+    if (energy_every < 0) return fail(PMD_EINVAL, "energy_every must be >= 0");
+    if (rec_dev && rec_cap < pmd_pm_record_rows(nsteps, energy_every))
+        return fail(PMD_EINVAL, "rec_cap %lld < %lld records", (long long)rec_cap,
+                    (long long)pmd_pm_record_rows(nsteps, energy_every));
+    const double len[3] = {m->lx, m->ly, m->dim == 3 ? m->lz : 1.0};
+    for (double l : len)
+        if (!std::isfinite(l) || l <= 0.0) return fail(PMD_EINVAL, "pore edges must be finite and > 0");
+    if (!std::isfinite(m->k) || m->k <= 0.0) return fail(PMD_EINVAL, "k must be finite and > 0");
+    if (!std::isfinite(m->sigma) || m->sigma <= 0.0 || !std::isfinite(m->epsilon) ||
+        !std::isfinite(m->mass) || m->mass <= 0.0 || !std::isfinite(m->dt) || m->dt <= 0.0)
+        return fail(PMD_EINVAL, "need finite sigma, mass, dt > 0 and a finite epsilon");
+    if (!std::isfinite(m->thermostat_tau) || m->thermostat_tau < 0.0)
+        return fail(PMD_EINVAL, "thermostat_tau must be finite and >= 0");
+    if (m->thermostat_tau > 0.0 &&
+        (m->thermostat_tau < m->dt || !std::isfinite(m->thermostat_t0) || m->thermostat_t0 <= 0.0))
+        return fail(PMD_EINVAL, "a thermostat needs tau >= dt and t0 > 0");
+    PmArgs a{};
+    a.n = (int)n;
+    a.dim = m->dim;
+    a.precision = m->precision;
+    a.lx = m->lx;
+    a.ly = m->ly;
+    a.lz = m->dim == 3 ? m->lz : 0.0;
+    a.k = m->k;
+    a.sig2 = m->sigma * m->sigma;
+    a.eps4 = 4.0 * m->epsilon;
+    a.eps24 = 24.0 * m->epsilon;
+    a.mass = m->mass;
+    a.inv_mass = 1.0 / m->mass;
+    a.dt = m->dt;
+    a.hdt = 0.5 * m->dt;
+    a.tau = m->thermostat_tau;
+    a.t0 = m->thermostat_t0;
+    *out = a;
+    return PMD_OK;
+}
+
+constexpr int64_t kPmMaxAtoms = (int64_t)1 << 20;
+
+}  // namespace
+
+extern "C" {
+
+int pmd_pm_run(const pmd_pm_model* model, int64_t n, double* x_dev, double* v_dev, double* a_dev,
+               int64_t nsteps, int64_t energy_every, pmd_pm_record* rec_dev, int64_t rec_cap,
+               void* stream)
+{
+    try {
+        PmArgs a;
+        CHK(pm_check(model, n, x_dev, v_dev, nsteps, energy_every, rec_dev, rec_cap, kPmMaxAtoms, &a));
+        const hipStream_t s = (hipStream_t)stream;
+        void* ws = nullptr;
+        HIPCHK(hipMallocAsync(&ws, sizeof(double) * pm_work_doubles(n, a.dim), s));
+        PmWork w = pm_work_at((double*)ws, n, a.dim);
+        if (a_dev) w.acc = a_dev;  // the caller's buffer serves as the accelerations
+        const hipError_t e = launch_pm_run(a, x_dev, v_dev, w, nsteps, energy_every,
+                                           (PmRecord*)rec_dev, s);
+        const hipError_t f = hipFreeAsync(ws, s);
+        HIPCHK(e);
+        HIPCHK(f);
         return PMD_OK;
     } catch (...) {
         return fail(PMD_EHIP, "unexpected exception");

@@ -61,6 +61,27 @@ class pmd_tuning(ctypes.Structure):
 
 _lib = None
 
+class pmd_pm_model(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("lx", ctypes.c_double), ("ly", ctypes.c_double), ("lz", ctypes.c_double),
+                ("k", ctypes.c_double), ("sigma", ctypes.c_double), ("epsilon", ctypes.c_double),
+                ("mass", ctypes.c_double), ("dt", ctypes.c_double),
+                ("thermostat_tau", ctypes.c_double), ("thermostat_t0", ctypes.c_double)]
+
+
+class pmd_pm_record(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_int64), ("ke", ctypes.c_double), ("pe", ctypes.c_double),
+                ("etotal", ctypes.c_double), ("temperature", ctypes.c_double),
+                ("n_pore", ctypes.c_int64), ("reflections", ctypes.c_int64),
+                ("n_outside", ctypes.c_int64)]
+
+
+PM_RECORD_DTYPE = np.dtype([("step", np.int64), ("ke", np.float64), ("pe", np.float64),
+                            ("etotal", np.float64), ("temperature", np.float64),
+                            ("n_pore", np.int64), ("reflections", np.int64),
+                            ("n_outside", np.int64)])
+
+
 # name -> (restype, argtypes)
 _P, _vp, _i64, _i32, _d = ctypes.POINTER, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
 _SIGS = {
@@ -106,6 +127,8 @@ _SIGS = {
     "pmd_batch_destroy": (ctypes.c_int, [_vp]),
     "pmd_batch_wall_room": (ctypes.c_int, [_i64, _i64]),
     "pmd_allpairs_forces": (ctypes.c_int, [ctypes.c_int, _i64, _vp, _P(_d), _d, _d, _vp, _vp, _vp, _vp]),
+    "pmd_pm_record_rows": (_i64, [_i64, _i64]),
+    "pmd_pm_run": (ctypes.c_int, [_P(pmd_pm_model), _i64, _vp, _vp, _vp, _i64, _i64, _vp, _i64, _vp]),
 }
 
 
@@ -526,3 +549,32 @@ class System:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------------
+# The paper's pore model
+# ---------------------------------------------------------------------------
+
+def make_pm_model(dim, lx, ly, lz=0.0, k=1.0, precision="fp64", sigma=1.0, epsilon=1.0,
+                  mass=1.0, dt=0.005, thermostat_tau=0.0, thermostat_t0=0.0) -> pmd_pm_model:
+    m = pmd_pm_model()
+    m.dim = int(dim)
+    m.precision = {"mixed": 1, "fp32": 1, "fp64": 2}[precision] if isinstance(precision, str) \
+        else int(precision)
+    m.lx, m.ly, m.lz, m.k = float(lx), float(ly), float(lz), float(k)
+    m.sigma, m.epsilon, m.mass, m.dt = float(sigma), float(epsilon), float(mass), float(dt)
+    m.thermostat_tau, m.thermostat_t0 = float(thermostat_tau), float(thermostat_t0)
+    return m
+
+
+def pmd_pm_record_rows(nsteps, energy_every):
+    return int(load().pmd_pm_record_rows(int(nsteps), int(energy_every)))
+
+
+def pmd_pm_run(model, n, x_ptr, v_ptr, a_ptr, nsteps, energy_every, rec_ptr, rec_cap, stream=None):
+    """Device pointers in, in place; a_ptr and rec_ptr may be 0 (not wanted)."""
+    return _check(load().pmd_pm_run(ctypes.byref(model), int(n), ctypes.c_void_p(x_ptr or None),
+                                    ctypes.c_void_p(v_ptr or None), ctypes.c_void_p(a_ptr or None),
+                                    int(nsteps), int(energy_every),
+                                    ctypes.c_void_p(rec_ptr or None), int(rec_cap),
+                                    ctypes.c_void_p(stream or None)))

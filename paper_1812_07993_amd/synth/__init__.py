@@ -328,3 +328,71 @@ def request_system(spec, seed=0) -> System:
     return make_system("request-%d" % spec["index"], (L, L, L), pore, spec["n"],
                        spec["precision"], (4, seed, spec["index"]), spec["steps"],
                        meta=dict(spec))
+
+
+# ---------------------------------------------------------------------------
+# The paper's pore model (Secs. 4-5), in reduced units of its own molecule
+# ---------------------------------------------------------------------------
+
+# The paper's Lennard-Jones parameters for water (Sec. 2): sigma = 3.17 A,
+# epsilon = 6.74e-3 eV; molecular mass 18.015 u.  Reduced units follow:
+# tau = sigma sqrt(m / epsilon) = 1.66846 ps, epsilon / k_B = 78.21 K.
+PAPER_SIGMA_NM = 0.317
+PAPER_TAU_PS = 1.66846
+PAPER_EPS_K = 78.21
+
+
+def paper_model_geometry(dim: int):
+    """(lx, ly, lz, k, T*, dt) of the paper's models in reduced units: the
+    2D pore 1 um x 1 um with k = 3 at 35 C (Sec. 4), the 3D prism
+    500 x 50 x 50 nm with an outer prism of 9 pore volumes (k = 1) at 25 C
+    (Sec. 5); dt = 0.016 ps in both."""
+    dt = 0.016 / PAPER_TAU_PS
+    if dim == 2:
+        l = 1000.0 / PAPER_SIGMA_NM
+        return l, l, 0.0, 3.0, 308.15 / PAPER_EPS_K, dt
+    return 500.0 / PAPER_SIGMA_NM, 50.0 / PAPER_SIGMA_NM, 50.0 / PAPER_SIGMA_NM, 1.0, \
+        298.15 / PAPER_EPS_K, dt
+
+
+def pore_model_state(dim, lx, ly, lz, k, n_pore, n_outer, temperature, seed=0,
+                     dmin=0.9, key=5):
+    """Positions [n][dim]: n_pore molecules uniform in the pore, then n_outer
+    uniform in the outer space, redrawn until no two are closer than dmin
+    (plain distance); velocities Gaussian with variance T/m per component,
+    rescaled so that 2 KE / (dim n) = T exactly (the walls break momentum
+    conservation, so the mean is not removed)."""
+    from scipy.spatial import cKDTree
+
+    rng_x, rng_v = _streams(key, dim, n_pore, seed)
+    lo_p = np.array([0.0, 0.0, 0.0])[:dim]
+    hi_p = np.array([lx, ly, lz])[:dim]
+    lo_o = np.array([lx, -k * ly, -k * lz])[:dim]
+    hi_o = np.array([(k + 1) * lx, (k + 1) * ly, (k + 1) * lz])[:dim]
+    n = n_pore + n_outer
+    lo = np.concatenate([np.tile(lo_p, (n_pore, 1)), np.tile(lo_o, (n_outer, 1))]).reshape(n, dim)
+    hi = np.concatenate([np.tile(hi_p, (n_pore, 1)), np.tile(hi_o, (n_outer, 1))]).reshape(n, dim)
+    x = lo + rng_x.random((n, dim)) * (hi - lo)
+    for _ in range(1000):
+        bad = sorted({j for _, j in cKDTree(x).query_pairs(dmin)})
+        if not bad:
+            break
+        x[bad] = lo[bad] + rng_x.random((len(bad), dim)) * (hi[bad] - lo[bad])
+    else:
+        raise RuntimeError("placement failed")
+    v = rng_v.standard_normal((n, dim)) * math.sqrt(temperature)
+    if n:
+        v *= math.sqrt(temperature * dim * n / float(np.sum(v * v)))
+    return x, v
+
+
+def paper_model_system(dim: int, n_pore: int, seed=0):
+    """The paper's workload at one pore population: n_pore molecules in the
+    pore and, at a fifth of the pore's density, k (2k+1)^(dim-1) n_pore / 5
+    in the outer space (1764 for 420 in 2D, 1800 for 1000 in 3D).  Returns
+    (x, v, dict of the model's geometry and state)."""
+    lx, ly, lz, k, T, dt = paper_model_geometry(dim)
+    n_outer = int(round(k * (2 * k + 1) ** (dim - 1) * n_pore / 5.0))
+    x, v = pore_model_state(dim, lx, ly, lz, k, n_pore, n_outer, T, seed)
+    return x, v, dict(dim=dim, lx=lx, ly=ly, lz=lz, k=k, temperature=T, dt=dt,
+                      n_pore=n_pore, n_outer=n_outer)

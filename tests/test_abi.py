@@ -100,3 +100,30 @@ def test_batch_wall_slot_limit():
     with pytest.raises(poremd.PmdError) as e:
         poremd.pmd_batch_wall_room(-1, 5)
     assert e.value.code == poremd.PMD_EINVAL
+
+
+def test_pore_model_record_rows_and_argument_checks():
+    """Host arithmetic and argument checks of the pore-model entry point; the
+    device buffers passed here are never touched."""
+    rows = poremd.pmd_pm_record_rows
+    assert rows(0, 0) == 1 and rows(0, 5) == 1
+    assert rows(10, 0) == 2 and rows(10, 1) == 11 and rows(10, 5) == 3 and rows(11, 5) == 4
+    assert rows(-1, 1) == 0
+    dummy = 0x1000
+    good = dict(dim=2, lx=10.0, ly=5.0, lz=0.0, k=1.0, precision="fp64", dt=0.005)
+    bad = [dict(dim=4), dict(precision=3), dict(lx=0.0), dict(ly=float("nan")), dict(k=-1.0),
+           dict(dt=0.0), dict(dim=3, lz=0.0), dict(thermostat_tau=0.001),
+           dict(thermostat_tau=1.0, thermostat_t0=0.0)]
+    for b in bad:
+        kw = dict(good, **b)
+        m = poremd.make_pm_model(**kw)
+        with pytest.raises(poremd.PmdError) as e:
+            poremd.pmd_pm_run(m, 4, dummy, dummy, 0, 10, 1, dummy, 11)
+        assert e.value.code == poremd.PMD_EINVAL, b
+    m = poremd.make_pm_model(**good)
+    for n, x, steps, every, cap in ((-1, dummy, 1, 1, 2), ((1 << 20) + 1, dummy, 1, 1, 2),
+                                    (4, 0, 1, 1, 2), (4, dummy, -1, 1, 2), (4, dummy, 10, 1, 10),
+                                    (4, dummy, 10, -1, 10)):
+        with pytest.raises(poremd.PmdError) as e:
+            poremd.pmd_pm_run(m, n, x, dummy, 0, steps, every, dummy, cap)
+        assert e.value.code == poremd.PMD_EINVAL, (n, steps, every, cap)
