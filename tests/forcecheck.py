@@ -21,9 +21,11 @@ TOL_ATOM = {"fp64": 1e-11, "mixed": 1e-4}
 
 
 def force_errors(F, F_ref):
-    """(eps_F, per-atom error / rms force) of F against F_ref, both [n][3]."""
-    F = np.asarray(F, dtype=np.float64).reshape(-1, 3)
-    F_ref = np.asarray(F_ref, dtype=np.float64).reshape(-1, 3)
+    """(eps_F, per-atom error / rms force) of F against F_ref, both [n][d]."""
+    F_ref = np.asarray(F_ref, dtype=np.float64)
+    d = F_ref.shape[-1] if F_ref.ndim > 1 else 3
+    F = np.asarray(F, dtype=np.float64).reshape(-1, d)
+    F_ref = F_ref.reshape(-1, d)
     d = F - F_ref
     nref = float(np.linalg.norm(F_ref))
     rms = float(np.sqrt(np.mean(np.sum(F_ref * F_ref, axis=1)))) if F_ref.size else 0.0
