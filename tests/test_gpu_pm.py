@@ -78,12 +78,15 @@ def compare(xg, vg, ag, rg, xo, vo, ro, model_o, prec, what):
 @pytest.mark.parametrize("n_pore,n_outer", [(1, 0), (2, 3), (40, 60), (61, 140)])
 def test_dense_pore_matches_the_oracle(dim, prec, n_pore, n_outer):
     """A small pore crowded enough that molecules interact and hit the walls
-    within 20 steps (dt 0.002, T = 100), also crossing the mouth."""
+    within 40 steps (dt 0.002, T = 9), also crossing the mouth.  The case
+    is well conditioned: the oracle's own total energy moves by under 1%."""
     g, o, base = models(dim, prec)
     x, v = dense_state(dim, n_pore, n_outer, base, seed=n_pore + 7 * dim)
-    v *= 10.0  # fast molecules: walls and the mouth are crossed within the run
-    xg, vg, ag, rg = gpu_run(x, v, g, 20, every=1)
-    xo, vo, ro = oracle.pm_run(o, x, v, 20, every=1)
+    v *= 3.0  # fast molecules: walls and the mouth are crossed within the run
+    xg, vg, ag, rg = gpu_run(x, v, g, 40, every=1)
+    xo, vo, ro = oracle.pm_run(o, x, v, 40, every=1)
+    eo = ro[:, 1] + ro[:, 2]
+    assert np.abs(eo - eo[0]).max() <= 1e-2 * max(abs(eo[0]), ro[0, 1])
     if x.shape[0] > 1:
         compare(xg, vg, ag, rg, xo, vo, ro, o, prec, "dense dim=%d n=%d" % (dim, x.shape[0]))
     else:
