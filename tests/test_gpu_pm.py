@@ -75,24 +75,31 @@ def compare(xg, vg, ag, rg, xo, vo, ro, model_o, prec, what):
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 @pytest.mark.parametrize("dim", [2, 3])
-@pytest.mark.parametrize("n_pore,n_outer", [(1, 0), (2, 3), (40, 60), (61, 140)])
-def test_dense_pore_matches_the_oracle(dim, prec, n_pore, n_outer):
+@pytest.mark.parametrize("n_pore,n_outer,vscale", [(1, 0, 3.0), (2, 3, 3.0), (60, 10, 3.0),
+                                                   (30, 6, 6.0)])
+def test_dense_pore_matches_the_oracle(dim, prec, n_pore, n_outer, vscale):
     """A small pore crowded enough that molecules interact and hit the walls
-    within 40 steps (dt 0.002, T = 9), also crossing the mouth.  The case
-    is well conditioned: the oracle's own total energy moves by under 1%."""
+    within 60 steps (dt 0.002, T = 9 or 36; in the last case a molecule
+    leaves through the mouth), with a sparse outer space: forces use plain
+    differences, so a molecule wrapping through a periodic face can land
+    next to another one, and a dense outer space would make such jumps (and
+    an ill-conditioned comparison) common.  The oracle's own total energy
+    moves by under 1% in every case."""
     g, o, base = models(dim, prec)
     x, v = dense_state(dim, n_pore, n_outer, base, seed=n_pore + 7 * dim)
-    v *= 3.0  # fast molecules: walls and the mouth are crossed within the run
-    xg, vg, ag, rg = gpu_run(x, v, g, 40, every=1)
-    xo, vo, ro = oracle.pm_run(o, x, v, 40, every=1)
+    v *= vscale
+    xg, vg, ag, rg = gpu_run(x, v, g, 60, every=1)
+    xo, vo, ro = oracle.pm_run(o, x, v, 60, every=1)
     eo = ro[:, 1] + ro[:, 2]
     assert np.abs(eo - eo[0]).max() <= 1e-2 * max(abs(eo[0]), ro[0, 1])
     if x.shape[0] > 1:
         compare(xg, vg, ag, rg, xo, vo, ro, o, prec, "dense dim=%d n=%d" % (dim, x.shape[0]))
     else:
         assert np.allclose(xg, xo, rtol=0, atol=1e-12) and np.all(ag == 0.0)
-    if n_pore + n_outer >= 100:
+    if n_pore >= 30:
         assert rg["reflections"][-1] > 0
+    if vscale > 3.0:
+        assert rg["n_pore"].min() < n_pore  # the mouth was crossed
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
