@@ -142,7 +142,7 @@ def test_free_molecules_keep_their_speeds_and_stay_inside(dim):
     periodic wrap keeps |v|, and no molecule leaves the domain."""
     g, o, base = models(dim, "fp64", dt=0.01)
     g.epsilon = 0.0
-    x, v = dense_state(dim, 150, 150, base, seed=4)
+    x, v = dense_state(dim, 60, 150, base, seed=4)
     v *= 3.0
     xg, vg, _, rg = gpu_run(x, v, g, 3000, every=1000)
     assert np.allclose(np.linalg.norm(vg, axis=1), np.linalg.norm(v, axis=1), rtol=1e-13)
