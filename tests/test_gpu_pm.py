@@ -138,16 +138,23 @@ def test_free_gas_thermostat_closed_form(dim):
 
 @pytest.mark.parametrize("dim", [2, 3])
 def test_free_molecules_keep_their_speeds_and_stay_inside(dim):
-    """3000 steps of non-interacting molecules: every wall reflection and
-    periodic wrap keeps |v|, and no molecule leaves the domain."""
+    """3000 steps of non-interacting molecules (epsilon = 0, so the motion is
+    ballistic between boundary events): every wall reflection and periodic
+    wrap keeps |v|, no molecule leaves the domain, and the positions, the
+    pore counts and the number of reflections are the oracle's."""
     g, o, base = models(dim, "fp64", dt=0.01)
     g.epsilon = 0.0
+    o.epsilon = 0.0
     x, v = dense_state(dim, 60, 150, base, seed=4)
     v *= 3.0
     xg, vg, _, rg = gpu_run(x, v, g, 3000, every=1000)
+    xo, vo, ro = oracle.pm_run(o, x, v, 3000, every=1000)
     assert np.allclose(np.linalg.norm(vg, axis=1), np.linalg.norm(v, axis=1), rtol=1e-13)
-    assert np.all(rg["n_outside"] == 0) and rg["reflections"][-1] > 1000
+    assert np.all(rg["n_outside"] == 0) and rg["reflections"][-1] > 300
     assert rg["n_pore"][-1] == int(np.sum(xg[:, 0] < base["lx"]))
+    assert np.array_equal(rg["n_pore"], ro[:, 3].astype(np.int64))
+    assert np.array_equal(rg["reflections"], ro[:, 4].astype(np.int64))
+    assert np.abs(xg - xo).max() <= 1e-9 and np.abs(vg - vo).max() <= 1e-12
 
 
 def test_empty_and_repeatable():
