@@ -438,6 +438,20 @@ int pmd_pm_run(const pmd_pm_model *model, int64_t n, double *x_dev,
                int64_t energy_every, pmd_pm_record *rec_dev, int64_t rec_cap,
                void *stream);
 
+/* pmd_pm_run for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same arguments, steps and results, but the working memory is a static
+ * device array of the library, one per GPU, held until the process ends,
+ * sized for n <= 65536 molecules (2.6 MB).  Makes no allocation of any kind.
+ * Every call on a GPU shares that GPU's array: calls that overlap on one GPU
+ * (on different streams, or from different threads) race and give wrong
+ * results; calls queued on one stream are safe.  Returns PMD_EINVAL for
+ * n > 65536 and for everything pmd_pm_run rejects. */
+int pmd_pm_run_noalloc(const pmd_pm_model *model, int64_t n, double *x_dev,
+                       double *v_dev, double *a_dev, int64_t nsteps,
+                       int64_t energy_every, pmd_pm_record *rec_dev,
+                       int64_t rec_cap, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

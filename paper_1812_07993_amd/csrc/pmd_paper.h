@@ -44,6 +44,16 @@ inline PmWork pm_work_at(double* base, long long n, int dim)
     return w;
 }
 
+// The allocation-free entry point keeps its working memory in a static
+// device array of this many doubles: runs of up to kPmScratchAtoms
+// molecules in three dimensions (2.6 MB).
+constexpr long long kPmScratchAtoms = 65536;
+constexpr size_t kPmScratchDoubles = (size_t)kPmScratchAtoms * (3 + 2) + 2;
+
+// Device address of the current device's static working array (looked up
+// with hipGetSymbolAddress on the first call per device, then cached).
+hipError_t pm_scratch_ptr(double** out);
+
 hipError_t launch_pm_run(const PmArgs& a, double* x, double* v, PmWork w, long long nsteps,
                          long long every, PmRecord* rec, hipStream_t s);
 

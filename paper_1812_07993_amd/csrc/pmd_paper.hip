@@ -18,9 +18,40 @@
 // This file shares nothing with the cell-list path or the all-pairs entry.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "pmd_paper.h"
 
 namespace pmd {
+
+// Working memory of the allocation-free entry point: one array per GPU,
+// held until the process ends.  Host code never uses this name as an
+// address (on the host it is only a stand-in); it uses the device address
+// that pm_scratch_ptr obtains for the current device.
+static __device__ __align__(256) double scratch[kPmScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};
+}  // namespace
+
+hipError_t pm_scratch_ptr(double** out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_dev[dev] = (double*)p;
+    }
+    *out = g_scratch_dev[dev];
+    return hipSuccess;
+}
 
 constexpr int kPmLanes = 64;
 constexpr int kPmUpdate = 1024;

@@ -1224,6 +1224,29 @@ int pmd_pm_run(const pmd_pm_model* model, int64_t n, double* x_dev, double* v_de
     }
 }
 
+int pmd_pm_run_noalloc(const pmd_pm_model* model, int64_t n, double* x_dev, double* v_dev,
+                       double* a_dev, int64_t nsteps, int64_t energy_every, pmd_pm_record* rec_dev,
+                       int64_t rec_cap, void* stream)
+{
+    try {
+        PmArgs a;
+        if (n > kPmScratchAtoms)
+            return fail(PMD_EINVAL, "n = %lld exceeds the static working memory (%lld molecules)",
+                        (long long)n, (long long)kPmScratchAtoms);
+        CHK(pm_check(model, n, x_dev, v_dev, nsteps, energy_every, rec_dev, rec_cap, kPmScratchAtoms,
+                     &a));
+        double* base = nullptr;
+        HIPCHK(pm_scratch_ptr(&base));
+        PmWork w = pm_work_at(base, n, a.dim);
+        if (a_dev) w.acc = a_dev;
+        HIPCHK(launch_pm_run(a, x_dev, v_dev, w, nsteps, energy_every, (PmRecord*)rec_dev,
+                             (hipStream_t)stream));
+        return PMD_OK;
+    } catch (...) {
+        return fail(PMD_EHIP, "unexpected exception");
+    }
+}
+
 int pmd_wall_count(const pmd_params* params, const pmd_pore* pore, int64_t* n_wall)
 {
     try {

@@ -129,6 +129,8 @@ _SIGS = {
     "pmd_allpairs_forces": (ctypes.c_int, [ctypes.c_int, _i64, _vp, _P(_d), _d, _d, _vp, _vp, _vp, _vp]),
     "pmd_pm_record_rows": (_i64, [_i64, _i64]),
     "pmd_pm_run": (ctypes.c_int, [_P(pmd_pm_model), _i64, _vp, _vp, _vp, _i64, _i64, _vp, _i64, _vp]),
+    "pmd_pm_run_noalloc": (ctypes.c_int, [_P(pmd_pm_model), _i64, _vp, _vp, _vp, _i64, _i64, _vp,
+                                          _i64, _vp]),
 }
 
 
@@ -578,3 +580,14 @@ def pmd_pm_run(model, n, x_ptr, v_ptr, a_ptr, nsteps, energy_every, rec_ptr, rec
                                     int(nsteps), int(energy_every),
                                     ctypes.c_void_p(rec_ptr or None), int(rec_cap),
                                     ctypes.c_void_p(stream or None)))
+
+
+def pmd_pm_run_noalloc(model, n, x_ptr, v_ptr, a_ptr, nsteps, energy_every, rec_ptr, rec_cap,
+                       stream=None):
+    """pmd_pm_run with the library's static working memory (n <= 65536)."""
+    return _check(load().pmd_pm_run_noalloc(ctypes.byref(model), int(n),
+                                            ctypes.c_void_p(x_ptr or None),
+                                            ctypes.c_void_p(v_ptr or None),
+                                            ctypes.c_void_p(a_ptr or None), int(nsteps),
+                                            int(energy_every), ctypes.c_void_p(rec_ptr or None),
+                                            int(rec_cap), ctypes.c_void_p(stream or None)))
