@@ -316,13 +316,14 @@ def pm_trace(model: PmModel, p, dl, v):
 def pm_run(model: PmModel, x, v, nsteps: int, every=1):
     """nsteps velocity-Verlet steps of the pore model (F2 with the boundary
     trace, F1, F3, and F4 if model.tau > 0).  Returns (x, v, records) with
-    records rows (step, ke, pe, atoms in the pore, reflections so far) at
-    step 0, every `every` steps and the last step."""
+    records rows (step, ke, pe, atoms in the pore, reflections so far,
+    pressure in the pore) at step 0, every `every` steps and the last
+    step."""
     d = model.dim
     x = _f64(x, (-1, d)).copy()
     v = _f64(v, (-1, d)).copy()
     cap = 2 + (nsteps // every if every > 0 else 0) + 1
-    rec = np.zeros((cap, 5))
+    rec = np.zeros((cap, 6))
     rows = _load().orc_pm_run(ctypes.byref(model), x.shape[0], _ptr(x), _ptr(v), int(nsteps),
                               int(every), _ptr(rec))
     if rows < 0:

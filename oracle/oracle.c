@@ -588,15 +588,18 @@ typedef struct {
 
 /* All-pairs forces in d dimensions with plain differences (no images: the
  * model's domain is not a torus): f_i = sum_j 24 eps (2 s^12 - s^6) r_ij / r^2
- * with s = sigma / r, and per-atom energy shares u_i = sum_j u(r_ij) / 2.
- * Returns the total energy, summed in ascending atom order. */
+ * with s = sigma / r, per-atom energy shares u_i = sum_j u(r_ij) / 2 and,
+ * if w is not NULL, per-atom virial shares w_i = sum_j r_ij . f_ij / 2 (the
+ * pair term of the pressure formula of Sec. 2, split equally between the
+ * two molecules).  Returns the total energy, summed in ascending atom
+ * order. */
 static double pm_forces(int d, int64_t n, const double *x, double sig, double eps, double *f,
-                        double *u)
+                        double *u, double *w)
 {
     double tot = 0.0;
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
-        double fi[3] = {0.0, 0.0, 0.0}, ui = 0.0;
+        double fi[3] = {0.0, 0.0, 0.0}, ui = 0.0, wi = 0.0;
         for (int64_t j = 0; j < n; ++j) {
             if (j == i) continue;
             double dd[3] = {0.0, 0.0, 0.0}, r2 = 0.0;
@@ -608,9 +611,11 @@ static double pm_forces(int d, int64_t n, const double *x, double sig, double ep
             const double w = 24.0 * eps * sr6 * (2.0 * sr6 - 1.0) / r2;
             for (int k = 0; k < d; ++k) fi[k] += w * dd[k];
             ui += 4.0 * eps * sr6 * (sr6 - 1.0);
+            wi += w * r2;
         }
         for (int k = 0; k < d; ++k) f[d * i + k] = fi[k];
         u[i] = 0.5 * ui;
+        if (w) w[i] = 0.5 * wi;
     }
     for (int64_t i = 0; i < n; ++i) tot += u[i];
     return tot;
@@ -619,7 +624,7 @@ static double pm_forces(int d, int64_t n, const double *x, double sig, double ep
 void orc_pm_forces(const orc_pm_model *m, int64_t n, const double *x, double *f, double *u,
                    double *e)
 {
-    *e = pm_forces(m->dim, n, x, m->sigma, m->epsilon, f, u);
+    *e = pm_forces(m->dim, n, x, m->sigma, m->epsilon, f, u, NULL);
 }
 
 /* Carry one particle along the straight drift of one step, p -> p + dl
@@ -733,10 +738,17 @@ int orc_pm_trace(const orc_pm_model *m, double *p, const double *dl_in, double *
  *   F4 (tau > 0): v <- lambda v, lambda = sqrt(1 + (dt / tau) (t0 / T - 1)),
  *       T = 2 K / (d n) from the F3 velocities (the walls break momentum
  *       conservation, so every degree of freedom counts).
- * x, v: [n][d], updated in place.  a: [n][d] scratch.  rec, if not NULL,
- * receives rows (step, ke, pe, n_pore, reflections so far) for step 0,
+ * x, v: [n][d], updated in place.  rec, if not NULL, receives rows (step,
+ * ke, pe, n_pore, reflections so far, pressure in the pore) for step 0,
  * every step that is a multiple of every, and the last step; returns the
- * rows written, or -1 if a drift could not be traced. */
+ * rows written, or -1 if a drift could not be traced.
+ * Pressure in the pore (Sec. 2: the pore volume V, the doubled kinetic
+ * energy and the pair virial, in d dimensions):
+ *   P = (2 K_pore + W_pore) / (d V),  V = lx ly (lz),
+ * K_pore the kinetic energy (after F3) of the molecules in the pore and
+ * W_pore the sum of their virial shares (every pair's r_ij . f_ij split
+ * equally between its molecules, f_ij the force on i from j; the sign of
+ * the printed formula fits the other convention, f = dU/dr). */
 int64_t orc_pm_run(const orc_pm_model *m, int64_t n, double *x, double *v, int64_t nsteps,
                    int64_t every, double *rec)
 {
@@ -745,8 +757,10 @@ int64_t orc_pm_run(const orc_pm_model *m, int64_t n, double *x, double *v, int64
     double *f = (double *)malloc(sizeof(double) * (size_t)(d * (n > 0 ? n : 1)));
     double *u = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
     double *a = (double *)malloc(sizeof(double) * (size_t)(d * (n > 0 ? n : 1)));
+    double *w = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    const double vol = d == 3 ? m->lx * m->ly * m->lz : m->lx * m->ly;
     int64_t rows = 0, refl = 0;
-    double pe = pm_forces(d, n, x, m->sigma, m->epsilon, f, u);
+    double pe = pm_forces(d, n, x, m->sigma, m->epsilon, f, u, w);
     for (int64_t q = 0; q < d * n; ++q) a[q] = f[q] / ms;
     for (int64_t s = 0; s <= nsteps; ++s) {
         if (s > 0) {
@@ -768,26 +782,31 @@ int64_t orc_pm_run(const orc_pm_model *m, int64_t n, double *x, double *v, int64
                     v[d * i + k] = vv[k];
                 }
             }
-            pe = pm_forces(d, n, x, m->sigma, m->epsilon, f, u);
+            pe = pm_forces(d, n, x, m->sigma, m->epsilon, f, u, w);
             for (int64_t q = 0; q < d * n; ++q) {
                 a[q] = f[q] / ms;
                 v[q] += 0.5 * a[q] * dt;
             }
         }
-        double ke = 0.0;
+        double ke = 0.0, kp = 0.0, wp = 0.0;
         int64_t np = 0;
         for (int64_t i = 0; i < n; ++i) {
             double s2 = 0.0;
             for (int k = 0; k < d; ++k) s2 += v[d * i + k] * v[d * i + k];
             ke += 0.5 * ms * s2;
-            np += x[d * i] < m->lx;
+            if (x[d * i] < m->lx) {
+                ++np;
+                kp += 0.5 * ms * s2;
+                wp += w[i];
+            }
         }
         if (rec && (s == 0 || s == nsteps || (every > 0 && s % every == 0))) {
-            rec[5 * rows + 0] = (double)s;
-            rec[5 * rows + 1] = ke;
-            rec[5 * rows + 2] = pe;
-            rec[5 * rows + 3] = (double)np;
-            rec[5 * rows + 4] = (double)refl;
+            rec[6 * rows + 0] = (double)s;
+            rec[6 * rows + 1] = ke;
+            rec[6 * rows + 2] = pe;
+            rec[6 * rows + 3] = (double)np;
+            rec[6 * rows + 4] = (double)refl;
+            rec[6 * rows + 5] = (2.0 * kp + wp) / ((double)d * vol);
             ++rows;
         }
         if (s > 0 && m->tau > 0.0 && n > 0) {
@@ -800,5 +819,6 @@ out:
     free(f);
     free(u);
     free(a);
+    free(w);
     return rows;
 }

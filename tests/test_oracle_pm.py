@@ -228,3 +228,56 @@ def test_berendsen_free_gas_closed_form():
     T1 = float(np.sum(v * v)) / (dim * n)
     s = np.arange(1, 61)
     assert np.allclose(T, t0 + (1 - dt / tau) ** (s - 1) * (T1 - t0), rtol=1e-12)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_pore_pressure_ideal_gas_limit(dim):
+    """epsilon = 0: no virial, so the pore pressure is 2 K_pore / (d V), i.e.
+    rho T over the molecules in the pore (the ideal-gas law)."""
+    rng = np.random.default_rng(6)
+    lx, ly, lz = 7.0, 5.0, 4.0
+    m = oracle.pm_model(dim, lx, ly, lz, k=1.0, epsilon=0.0, dt=0.01)
+    n = 150
+    x = np.empty((n, dim))
+    x[:, 0] = rng.uniform(0.0, 2 * lx, n)
+    inside = x[:, 0] < lx
+    for a, l in ((1, ly), (2, lz))[:dim - 1]:
+        x[:, a] = np.where(inside, rng.uniform(0.0, l, n), rng.uniform(-l, 2 * l, n))
+    v = rng.normal(0.0, 1.3, (n, dim))
+    x1, v1, rec = oracle.pm_run(m, x, v, 50, every=25)
+    V = lx * ly * (lz if dim == 3 else 1.0)
+    for xs, vs, r in ((x, v, rec[0]), (x1, v1, rec[-1])):
+        p = xs[:, 0] < lx
+        T_pore = np.sum(vs[p] ** 2) / (dim * p.sum())
+        assert r[5] == pytest.approx(p.sum() * T_pore / V, rel=1e-13)
+
+
+def test_pore_pressure_of_a_dimer_closed_form():
+    """Two molecules at rest at distance r: inside the pore the pressure is
+    r f(r) / (d V) with r f(r) = 24 eps (2 (s/r)^12 - (s/r)^6); with one of
+    them outside (across the mouth) it is half of that."""
+    lx, ly = 8.0, 6.0
+    m = oracle.pm_model(2, lx, ly, k=1.0, dt=1e-9)
+    for r in (1.0, 1.1, 1.5):
+        rf = 24.0 * (2.0 * r ** -12 - r ** -6)
+        _, _, rec = oracle.pm_run(m, [[3.0, 3.0], [3.0 + r, 3.0]], np.zeros((2, 2)), 0)
+        assert rec[0, 5] == pytest.approx(rf / (2 * lx * ly), rel=1e-13)
+        _, _, rec = oracle.pm_run(m, [[lx - 0.4, 3.0], [lx - 0.4 + r, 3.0]], np.zeros((2, 2)), 0)
+        assert rec[0, 3] == 1
+        assert rec[0, 5] == pytest.approx(0.5 * rf / (2 * lx * ly), rel=1e-13)
+
+
+def test_pore_virial_is_minus_the_scaling_derivative_of_the_energy():
+    """For molecules all in the pore, sum_{i<j} r_ij . f_ij = -dU(lambda x) /
+    d lambda at lambda = 1 (the virial theorem's pair term), so
+    (P - 2 K / (d V)) d V equals minus the derivative by central
+    differences."""
+    rng = np.random.default_rng(12)
+    g = np.stack(np.meshgrid(np.arange(4), np.arange(4), np.arange(3), indexing="ij"), -1)
+    x = 1.0 + 1.1 * g.reshape(-1, 3) + rng.uniform(-0.1, 0.1, (48, 3))
+    m = oracle.pm_model(3, 8.0, 8.0, 8.0, k=1.0, dt=1e-9)
+    _, _, rec = oracle.pm_run(m, x, np.zeros_like(x), 0)
+    W = rec[0, 5] * 3 * 8.0 ** 3
+    h = 1e-6
+    dU = (oracle.pm_forces(m, (1 + h) * x)[2] - oracle.pm_forces(m, (1 - h) * x)[2]) / (2 * h)
+    assert W == pytest.approx(-dU, rel=1e-7)
