@@ -90,6 +90,11 @@ def _load():
     lib.orc_wall_lattice.restype = i64
     lib.orc_cell_sort.argtypes = [i64, vp, vp, vp, vp, vp, vp]
     lib.orc_pairs.argtypes = [i64, vp, i64, vp, vp, d, i64, vp, P(i64), vp, P(i64)]
+    lib.orc_pore_volume.argtypes = [P(Pore), vp]
+    lib.orc_pore_volume.restype = d
+    lib.orc_pore_pressure.argtypes = [i64, vp, vp, P(Params), P(Pore), vp]
+    lib.orc_pore_count.argtypes = [i64, vp, vp, P(Pore)]
+    lib.orc_pore_count.restype = i64
     lib.orc_pm_forces.argtypes = [P(PmModel), i64, vp, vp, vp, P(d)]
     lib.orc_pm_trace.argtypes = [P(PmModel), vp, vp, vp]
     lib.orc_pm_trace.restype = ctypes.c_int
@@ -222,6 +227,34 @@ def allpairs(x, box, epsilon=1.0, sigma=1.0):
     _load().orc_allpairs(n, _ptr(x), _ptr(b), float(epsilon), float(sigma), _ptr(f), _ptr(u),
                          ctypes.byref(e))
     return f, u, e.value
+
+
+def pore_volume(pore: Pore, box):
+    """Volume of the pore's void (closed form per shape; the whole box for
+    no walls, 0 for a plain slab)."""
+    b = _f64(np.broadcast_to(np.asarray(box, dtype=np.float64), (3,)))
+    return float(_load().orc_pore_volume(ctypes.byref(pore), _ptr(b)))
+
+
+def pore_count(x, box, pore: Pore):
+    """How many of the points lie in the pore's void."""
+    x = _f64(x, (-1, 3))
+    b = _f64(np.broadcast_to(np.asarray(box, dtype=np.float64), (3,)))
+    return int(_load().orc_pore_count(x.shape[0], _ptr(x), _ptr(b), ctypes.byref(pore)))
+
+
+def pore_pressure(x, v, params: Params, pore: Pore):
+    """Pressure in the pore by the formula of Sec. 2 with V the pore volume:
+    dict(ke_pore, virial_pore, n_pore, volume, pressure) with
+    P = (2 ke_pore + virial_pore) / (3 V), the virial over vapour pairs
+    inside the cutoff, each pair split equally between its molecules."""
+    x = _f64(x, (-1, 3))
+    v = _f64(v, (-1, 3))
+    out = np.zeros(5)
+    _load().orc_pore_pressure(x.shape[0], _ptr(x), _ptr(v), ctypes.byref(params),
+                              ctypes.byref(pore), _ptr(out))
+    return dict(ke_pore=out[0], virial_pore=out[1], n_pore=int(out[2]), volume=out[3],
+                pressure=out[4])
 
 
 def wall_lattice(pore: Pore, box):

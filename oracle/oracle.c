@@ -822,3 +822,100 @@ out:
     free(w);
     return rows;
 }
+
+/* ---------------------------------------------------------------------- */
+/* Pressure in the pore of the cell-list workloads (Sec. 2)               */
+/* ---------------------------------------------------------------------- */
+
+/* The pore's void, a continuous region (the reading fixed for this
+ * repository: the hole cut through the slab, not the lattice sites):
+ *   cylinder, cone, ink-bottle: z in [z_lo, z_lo + t) of the slab and
+ *     (x - Lx/2)^2 + (y - Ly/2)^2 < r(z)^2, with r(z) the hole's radius at
+ *     that height (the cone's radius linear in z from r0 at z_lo to r1 at
+ *     z_lo + t; the ink-bottle's neck r0 where z - z_lo < t/4 or >= 3t/4,
+ *     its cavity r1 between);
+ *   slit: the gap between the two slabs, z in [c - gap/2, c + gap/2);
+ *   none: the whole box.  A plain slab has no pore.
+ * Returns 1 if the point lies in the pore. */
+static int in_pore(const orc_pore *pp, const double *box, const double *p)
+{
+    const double t = pp->slab_thickness, c = pp->slab_center_z;
+    if (pp->kind == 0) return 1;
+    if (pp->kind == 1) return 0;
+    if (pp->kind == 3) return p[2] >= c - 0.5 * pp->slit_gap && p[2] < c + 0.5 * pp->slit_gap;
+    const double z_lo = c - 0.5 * t, h = p[2] - z_lo;
+    if (h < 0.0 || h >= t) return 0;
+    double r;
+    if (pp->kind == 2)
+        r = pp->r0;
+    else if (pp->kind == 4)
+        r = pp->r0 + (pp->r1 - pp->r0) * (h / t);
+    else
+        r = (h < 0.25 * t || h >= 0.75 * t) ? pp->r0 : pp->r1;
+    const double dx = p[0] - 0.5 * box[0], dy = p[1] - 0.5 * box[1];
+    return dx * dx + dy * dy < r * r;
+}
+
+/* Volume of that region: pi r^2 t (cylinder), the frustum
+ * pi t (r0^2 + r0 r1 + r1^2) / 3 (cone), pi (t/2) (r0^2 + r1^2) (ink-bottle:
+ * two neck quarters and the cavity half), Lx Ly gap (slit), Lx Ly Lz (none);
+ * 0 for a plain slab. */
+double orc_pore_volume(const orc_pore *pp, const double *box)
+{
+    const double t = pp->slab_thickness, pi = 3.14159265358979323846;
+    switch (pp->kind) {
+    case 0: return box[0] * box[1] * box[2];
+    case 2: return pi * pp->r0 * pp->r0 * t;
+    case 3: return box[0] * box[1] * pp->slit_gap;
+    case 4: return pi * t * (pp->r0 * pp->r0 + pp->r0 * pp->r1 + pp->r1 * pp->r1) / 3.0;
+    case 5: return pi * 0.5 * t * (pp->r0 * pp->r0 + pp->r1 * pp->r1);
+    default: return 0.0;
+    }
+}
+
+/* Pressure in the pore by the formula of Sec. 2 with V the pore volume:
+ *   P = (2 K_pore + W_pore) / (3 V),
+ * K_pore the kinetic energy of the vapour molecules in the pore and W_pore
+ * their shares of the vapour pair virials (each pair's r_ij . f_ij inside the
+ * cutoff split equally between its two molecules; f_ij the force on i from
+ * j, minimum image; the wall atoms are not molecules of the formula).
+ * out[5] = {K_pore, W_pore, n_pore, V, P}. */
+void orc_pore_pressure(int64_t nv, const double *xv, const double *v, const orc_params *p,
+                       const orc_pore *pp, double *out)
+{
+    double kp = 0.0, wp = 0.0;
+    int64_t np = 0;
+    const double rc2 = p->cutoff * p->cutoff;
+    for (int64_t i = 0; i < nv; ++i) {
+        if (!in_pore(pp, p->box, xv + 3 * i)) continue;
+        ++np;
+        kp += 0.5 * p->mass * (v[3 * i] * v[3 * i] + v[3 * i + 1] * v[3 * i + 1] +
+                               v[3 * i + 2] * v[3 * i + 2]);
+        double wi = 0.0;
+        for (int64_t j = 0; j < nv; ++j) {
+            if (j == i) continue;
+            double d[3];
+            min_image(xv + 3 * i, xv + 3 * j, p->box, d);
+            const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            if (r2 >= rc2) continue;
+            double u, w;
+            lj_pair(r2, p->sigma, p->epsilon, p->cutoff, &u, &w);
+            wi += w * r2;
+        }
+        wp += 0.5 * wi;
+    }
+    const double V = orc_pore_volume(pp, p->box);
+    out[0] = kp;
+    out[1] = wp;
+    out[2] = (double)np;
+    out[3] = V;
+    out[4] = V > 0.0 ? (2.0 * kp + wp) / (3.0 * V) : 0.0;
+}
+
+/* Number of the n points that lie in the pore (for the volume pins). */
+int64_t orc_pore_count(int64_t n, const double *x, const double *box, const orc_pore *pp)
+{
+    int64_t c = 0;
+    for (int64_t i = 0; i < n; ++i) c += in_pore(pp, box, x + 3 * i);
+    return c;
+}
