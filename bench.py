@@ -305,7 +305,8 @@ def paper_model_leg(poremd, dims=(2, 3), n_pores=tuple(range(100, 1501, 100)), s
                                      thermostat_t0=geo["temperature"])
             xd = torch.as_tensor(x, dtype=torch.float64, device=dev)
             vd = torch.as_tensor(v, dtype=torch.float64, device=dev)
-            rec = torch.zeros((2, 8), dtype=torch.float64, device=dev)
+            rec = torch.zeros((2, poremd.PM_RECORD_DTYPE.itemsize // 8), dtype=torch.float64,
+                              device=dev)
             poremd.pmd_pm_run(m, n, xd.data_ptr(), vd.data_ptr(), 0, 20, 0, rec.data_ptr(), 2,
                               stream.cuda_stream)
             torch.cuda.synchronize()

@@ -104,13 +104,26 @@ typedef struct {
  * pairs; temperature = 2 ke / (3 n - 3).  virial_vv = sum over vapour pairs
  * i<j inside the cutoff of r_ij . f_ij (r_ij = r_i - r_j, minimum image;
  * f_ij the force on i from j, positive when repulsive), virial_vw the same
- * over vapour-wall pairs: the pressure of the formula in Sec. 2 is
- * P = (2 ke + virial_vv) / (3 V) for the caller's volume V (the pore volume
- * in the paper); the wall term is reported beside it. */
+ * over vapour-wall pairs.
+ * The pressure in the pore by the formula of Sec. 2 (P from the doubled
+ * kinetic energy and the pair virial over the pore volume V):
+ *   pressure = (2 ke_pore + virial_pore) / (3 pore_volume),
+ * over the molecules whose position lies in the pore's void (the hole
+ * through the slab, evaluated at each height as the hole's radius there;
+ * the slit's gap; the whole box without walls; nothing for a plain slab),
+ * ke_pore their kinetic energy, virial_pore their shares of the vapour pair
+ * virials (each pair's r_ij . f_ij split equally between its two molecules;
+ * the wall atoms are not molecules of the formula), pore_volume the void's
+ * volume (pmd_pore_volume).  The printed formula's minus sign fits the
+ * other force convention (f = dU/dr). */
 typedef struct {
     int64_t step;
     double ke, pe_vv, pe_vw, etotal, temperature;
     double virial_vv, virial_vw;  /* 0 unless the tuning asks for them */
+    double ke_pore, virial_pore;  /* 0 unless the tuning asks for the virial */
+    int64_t n_pore;               /* molecules in the pore (ditto) */
+    double pore_volume;
+    double pressure;              /* 0 unless the tuning asks for the virial */
 } pmd_energies;
 
 /* Performance knobs; zero fields take the library default.  skin: extra
@@ -151,6 +164,12 @@ int pmd_version(void);
 /* Number of wall sites a pore would generate in a box (host arithmetic
  * only; no device work). */
 int pmd_wall_count(const pmd_params *params, const pmd_pore *pore, int64_t *n_wall);
+
+/* Volume of the pore's void (host arithmetic): pi r0^2 t (cylinder),
+ * pi t (r0^2 + r0 r1 + r1^2) / 3 (cone), pi (t/2) (r0^2 + r1^2) (ink-bottle:
+ * neck quarters and cavity half), Lx Ly slit_gap (slit), Lx Ly Lz (no walls),
+ * 0 (plain slab): the V of the pressure in the pore (Sec. 2). */
+int pmd_pore_volume(const pmd_params *params, const pmd_pore *pore, double *volume);
 
 /* Device bytes a system of n_vapor molecules with this pore occupies in a
  * batch, with the given tuning (NULL = defaults): the figure pmd_batch_admit
@@ -397,6 +416,13 @@ typedef struct {
     double temperature;   /* 2 ke / (dim n): the reflecting walls break
                              momentum conservation, so every degree of
                              freedom counts */
+    double pressure;      /* in the pore, Sec. 2's virial formula with the
+                             pore volume V = lx ly (lz):
+                             P = (2 K + W) / (dim V), K the kinetic energy of
+                             the molecules with x < lx, W their shares of the
+                             pair virials (each pair's r_ij . f_ij split
+                             equally between its molecules, f_ij the force on
+                             i from j, positive when repulsive) */
     int64_t n_pore;       /* molecules with x < lx */
     int64_t reflections;  /* wall reflections since the run started */
     int64_t n_outside;    /* molecules outside the domain, plus drifts that
@@ -426,7 +452,7 @@ int64_t pmd_pm_record_rows(int64_t nsteps, int64_t energy_every);
  *   rec_dev       device, rec_cap records (NULL = none): step 0, every
  *                 energy_every-th step and the last step, in order.
  *   stream        hipStream_t (NULL = the default stream); queued, no wait.
- * Working memory ((dim + 2) n + 2 doubles) is taken from the stream-ordered
+ * Working memory ((dim + 3) n + 2 doubles) is taken from the stream-ordered
  * allocator for the call and returned at its end.  Sums are in a fixed
  * order: repeated runs give identical results.  Returns PMD_EINVAL for a
  * dim other than 2 or 3, a precision other than 1 or 2, n outside 0..2^20,
@@ -442,7 +468,7 @@ int pmd_pm_run(const pmd_pm_model *model, int64_t n, double *x_dev,
  * graph capture, tight serving loops, harnesses that forbid allocation): the
  * same arguments, steps and results, but the working memory is a static
  * device array of the library, one per GPU, held until the process ends,
- * sized for n <= 65536 molecules (2.6 MB).  Makes no allocation of any kind.
+ * sized for n <= 65536 molecules (3.1 MB).  Makes no allocation of any kind.
  * Every call on a GPU shares that GPU's array: calls that overlap on one GPU
  * (on different streams, or from different threads) race and give wrong
  * results; calls queued on one stream are safe.  Returns PMD_EINVAL for

@@ -69,6 +69,12 @@ struct SysParams {
     int thermo;            // 1: Berendsen thermostat on
     int virial;            // 1: record the virial sums
     double tau_t, t0, dof; // its rise time, target temperature, 3 nv - 3
+    // the pore's void, for the pressure in the pore: kind as pmd_pore_kind
+    // (none: the whole box; plain slab: no pore), the z range [pz0, pz1) of
+    // the slab (the gap for a slit), the radii of the hole and its volume
+    int pkind;
+    int pad1;
+    double pz0, pz1, pr0, pr1, pvol;
 };
 
 // Per-system dynamic state, written by kernels.
@@ -96,10 +102,13 @@ struct EnergyRec {
     long long step;
     double ke, pe_vv, pe_vw;
     double w_vv, w_vw;  // virial sums r . f over vapour pairs and vapour-wall pairs
+    double ke_pore, w_pore, n_pore;  // the molecules in the pore: kinetic energy,
+                                     // shares of the vapour pair virials, count
 };
 
-// Energy partials per brick and step slot: ke, pe_vv, pe_vw, w_vv, w_vw.
-constexpr int kPartial = 5;
+// Energy partials per brick and step slot: ke, pe_vv, pe_vw, w_vv, w_vw,
+// ke_pore, w_pore, n_pore.
+constexpr int kPartial = 8;
 
 typedef float f4 __attribute__((ext_vector_type(4)));   // 16 bytes, one 128-bit load
 typedef double d4 __attribute__((ext_vector_type(4)));  // 32 bytes

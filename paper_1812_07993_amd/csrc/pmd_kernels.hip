@@ -1010,6 +1010,9 @@ __device__ void record_energies(const PoolDev& P, const SysParams& sp, int s, in
         r.pe_vw = t[2];
         r.w_vv = t[3];
         r.w_vw = t[4];
+        r.ke_pore = t[5];
+        r.w_pore = t[6];
+        r.n_pore = t[7];
         P.erec[sp.ering_off + (n % sp.ering_cap)] = r;
         sw->nrec = n + 1;
     }
@@ -1268,18 +1271,34 @@ __device__ double atom_epilogue(const PoolDev& P, const StepCtx<T>& x, int i,
     return kei;
 }
 
+// Whether a position lies in the pore's void (the hole through the slab, the
+// slit's gap, the whole box without walls; nothing for a plain slab): the
+// region of the pressure in the pore.
+__device__ __forceinline__ bool in_pore(const SysParams& sp, double x, double y, double z)
+{
+    if (sp.pkind == 0) return true;
+    if (sp.pkind == 1 || z < sp.pz0 || z >= sp.pz1) return false;
+    if (sp.pkind == 3) return true;
+    const double t = sp.pz1 - sp.pz0, h = z - sp.pz0;
+    double r = sp.pr0;
+    if (sp.pkind == 4) r = sp.pr0 + (sp.pr1 - sp.pr0) * (h / t);
+    if (sp.pkind == 5) r = (h < 0.25 * t || h >= 0.75 * t) ? sp.pr0 : sp.pr1;
+    const double dx = x - 0.5 * sp.L[0], dy = y - 0.5 * sp.L[1];
+    return dx * dx + dy * dy < r * r;
+}
+
 // Workgroup reductions in a fixed order (lane tree, then waves in order):
 // status bits to the system, energies to the brick's partial of slot kk & 1.
 __device__ void step_reduce(const PoolDev& P, const SysParams& sp, int s, int b, int kk, bool doE,
                             int flags, double ke, double evv, double evw, double wvv, double wvw,
-                            Red& red)
+                            double kp, double wp, double np, Red& red)
 {
     __shared__ int flag_or[kMaxBlock / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
     flags = wave_or(flags);
     if (lane == 0) flag_or[wave] = flags;
     if (doE) {
-        const double v[kPartial] = {ke, evv, evw, wvv, wvw};
+        const double v[kPartial] = {ke, evv, evw, wvv, wvw, kp, wp, np};
 #pragma unroll
         for (int q = 0; q < kPartial; ++q) {
             const double t = wave_sum(v[q]);
@@ -1338,14 +1357,18 @@ __device__ __forceinline__ void step_body(PoolDev& P, int kk)
 
     double ke = 0.0;
     // force fields per atom; the energy and virial fields run over all of
-    // this lane's atoms (no second set of sums to keep live in the loops)
+    // this lane's atoms (no second set of sums to keep live in the loops),
+    // except that the vapour virial is per atom with VIR (its share goes to
+    // the pore's sum when the atom lies in the pore)
     Acc a{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    double lwv = 0.0, lkp = 0.0, lwp = 0.0, lnp = 0.0;
     int flags = tot < 0 ? (ST_OVERFLOW | ST_TILE) : 0;
     for (int i = i0 + tid; tot >= 0 && i < i1; i += blockDim.x) {
         const V me = x.Lc[i];
         const int nl = P.nlist[i];
         const int nvap = nl & 0xFFFF, nall = nvap + (nl >> 16);
         a.fx = a.fy = a.fz = 0.0;
+        if constexpr (VIR) a.wv = 0.0;
         // entries come kGroupV (vapour, as kGroupV / 4 chunk loads) or
         // kGroupW<T> (walls) at a time, the next group's loads in flight while
         // the current one is evaluated; vapour partners are read from LDS, wall
@@ -1426,10 +1449,23 @@ __device__ __forceinline__ void step_body(PoolDev& P, int kk)
             }
         }
         if (ne) edge_pass<T, VIR>(P, sp, x, tl, i, nvap, nall, ne, ke0, ke1, a);
-        ke += atom_epilogue<T>(P, x, i, a, flags);
+        const double kei = atom_epilogue<T>(P, x, i, a, flags);
+        ke += kei;
+        if constexpr (VIR) {
+            if (x.doE) {
+                lwv += a.wv;
+                if (in_pore(sp, x.X[i], x.X[vt + i], x.X[2 * vt + i])) {
+                    lkp += kei;
+                    lwp += a.wv;
+                    lnp += 1.0;
+                }
+            }
+        }
     }
-    // vapour pairs were met from both atoms: half of each sum
-    step_reduce(P, sp, s, c.b, kk, x.doE, flags, ke, 0.5 * a.ev, a.ew, 0.5 * a.wv, a.ww, red);
+    // vapour pairs were met from both atoms: half of each sum (and each
+    // pair's virial is shared equally by its two molecules)
+    step_reduce(P, sp, s, c.b, kk, x.doE, flags, ke, 0.5 * a.ev, a.ew, 0.5 * (VIR ? lwv : a.wv), a.ww,
+                lkp, 0.5 * lwp, lnp, red);
 }
 
 // The step kernel (F1 + F3 + the next F2, see step_body); k_step_virial

@@ -11,28 +11,30 @@ struct PmArgs {
     int n, dim, precision;  // precision: 1 FP32 pair terms, 2 FP64
     double lx, ly, lz, k;
     double sig2, eps4, eps24, mass, inv_mass, dt, hdt, tau, t0;
+    double vol;  // the pore's volume (area in 2D)
 };
 
 // Per-run working memory: accelerations [n][dim], per-molecule kinetic
-// energy and pair-energy share [n] each, two counters (wall reflections,
-// drifts that could not be traced).
+// energy, pair-energy share and pair-virial share [n] each, two counters
+// (wall reflections, drifts that could not be traced).
 struct PmWork {
     double* acc;
     double* ke;
     double* u;
+    double* vir;
     long long* counts;
 };
 
 // Same layout as pmd_pm_record of the C interface.
 struct PmRecord {
     long long step;
-    double ke, pe, etotal, temperature;
+    double ke, pe, etotal, temperature, pressure;
     long long n_pore, reflections, n_outside;
 };
 
 // Doubles of working memory a run of n molecules in dim dimensions needs
 // (the counters included, rounded up).
-inline size_t pm_work_doubles(long long n, int dim) { return (size_t)n * (dim + 2) + 2; }
+inline size_t pm_work_doubles(long long n, int dim) { return (size_t)n * (dim + 3) + 2; }
 
 inline PmWork pm_work_at(double* base, long long n, int dim)
 {
@@ -40,15 +42,16 @@ inline PmWork pm_work_at(double* base, long long n, int dim)
     w.acc = base;
     w.ke = base + (size_t)n * dim;
     w.u = w.ke + n;
-    w.counts = (long long*)(w.u + n);
+    w.vir = w.u + n;
+    w.counts = (long long*)(w.vir + n);
     return w;
 }
 
 // The allocation-free entry point keeps its working memory in a static
 // device array of this many doubles: runs of up to kPmScratchAtoms
-// molecules in three dimensions (2.6 MB).
+// molecules in three dimensions (3.1 MB).
 constexpr long long kPmScratchAtoms = 65536;
-constexpr size_t kPmScratchDoubles = (size_t)kPmScratchAtoms * (3 + 2) + 2;
+constexpr size_t kPmScratchDoubles = (size_t)kPmScratchAtoms * (3 + 3) + 2;
 
 // Device address of the current device's static working array (looked up
 // with hipGetSymbolAddress on the first call per device, then cached).

@@ -73,8 +73,8 @@ __device__ __forceinline__ double pm_recip<double>(double a)
 }
 
 // Forces (F1) at the current positions, then with KICK the F3 half-kick;
-// writes each molecule's acceleration, kinetic energy and half share of the
-// pair energies.
+// writes each molecule's acceleration, kinetic energy and half shares of the
+// pair energies and of the pair virials r_ij . f_ij.
 template <typename T, int D, bool KICK>
 __global__ void __launch_bounds__(kPmLanes) k_pm_forces(const double* __restrict__ x,
                                                        double* __restrict__ v, PmWork w, PmArgs a)
@@ -84,7 +84,7 @@ __global__ void __launch_bounds__(kPmLanes) k_pm_forces(const double* __restrict
     double xi[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) xi[k] = x[(size_t)D * i + k];
-    double f[D], us = 0.0;
+    double f[D], us = 0.0, ws = 0.0;
 #pragma unroll
     for (int k = 0; k < D; ++k) f[k] = 0.0;
     const T sig2 = (T)a.sig2, eps4 = (T)a.eps4, eps24 = (T)a.eps24;
@@ -105,6 +105,7 @@ __global__ void __launch_bounds__(kPmLanes) k_pm_forces(const double* __restrict
 #pragma unroll
             for (int k = 0; k < D; ++k) f[k] += (double)(wf * (T)d[k]);
             us += (double)(eps4 * s6 * (s6 - (T)1));
+            ws += (double)(wf * (T)r2d);  // r_ij . f_ij of the pair
         }
     }
 #pragma unroll
@@ -112,6 +113,7 @@ __global__ void __launch_bounds__(kPmLanes) k_pm_forces(const double* __restrict
 #pragma unroll
         for (int k = 0; k < D; ++k) f[k] += __shfl_down(f[k], o);
         us += __shfl_down(us, o);
+        ws += __shfl_down(ws, o);
     }
     if (lane == 0) {
         double ke = 0.0;
@@ -128,6 +130,7 @@ __global__ void __launch_bounds__(kPmLanes) k_pm_forces(const double* __restrict
         }
         w.ke[i] = 0.5 * a.mass * ke;
         w.u[i] = 0.5 * us;
+        w.vir[i] = 0.5 * ws;
     }
 }
 
@@ -231,22 +234,37 @@ __device__ bool pm_inside(const PmArgs& a, const double* p)
     return in;
 }
 
-// Fixed-order workgroup sum: every thread's partial, then a tree over LDS.
-__device__ double pm_block_sum(double s, double* red)
+// Fixed-order workgroup sums of K values at once: each wave combines its
+// lanes by a fixed tree of shuffles, then the waves' sums are added in wave
+// order; every thread receives the K totals.
+template <int K>
+__device__ void pm_block_sums(double (&v)[K], double* red)
 {
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int h = kPmUpdate / 2; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
-        __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int kWaves = kPmUpdate / 64;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+#pragma unroll
+        for (int q = 0; q < K; ++q) v[q] += __shfl_down(v[q], o);
     }
-    const double t = red[0];
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < K; ++q) red[q * kWaves + wave] = v[q];
+    }
     __syncthreads();
-    return t;
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        double t = 0.0;
+        for (int w = 0; w < kWaves; ++w) t += red[q * kWaves + w];
+        v[q] = t;
+    }
+    __syncthreads();
 }
 
 // End of step `step` (0 = the initial state): the energies (kinetic energy of
-// the F3 velocities, pair energy at the current positions), the record, and
+// the F3 velocities, pair energy at the current positions), the pressure in
+// the pore (Sec. 2: P = (2 K + W) / (d V) over the molecules in the pore,
+// V the pore's volume, W their shares of the pair virials), the record, and
 // then, for every molecule, F4 (Berendsen scaling, steps >= 1 with a
 // thermostat) and, with drift, the next step's F2: dl = v dt + a dt^2 / 2,
 // v <- v + a dt / 2, the molecule carried along dl through the boundaries.
@@ -255,22 +273,31 @@ __global__ void __launch_bounds__(kPmUpdate) k_pm_update(double* __restrict__ x,
                                                         PmWork w, PmArgs a, long long step, int rec_row,
                                                         int thermo, int drift, PmRecord* __restrict__ rec)
 {
-    __shared__ double red[kPmUpdate];
+    __shared__ double red[6 * (kPmUpdate / 64)];
     const int tid = threadIdx.x;
-    double ke = 0.0, pe = 0.0, np = 0.0, out = 0.0;
+    double ke = 0.0, pe = 0.0, np = 0.0, out = 0.0, kp = 0.0, wp = 0.0;
     for (int i = tid; i < a.n; i += kPmUpdate) {
-        ke += w.ke[i];
+        const double kei = w.ke[i];
+        ke += kei;
         pe += w.u[i];
         double p[D];
 #pragma unroll
         for (int k = 0; k < D; ++k) p[k] = x[(size_t)D * i + k];
-        np += p[0] < a.lx ? 1.0 : 0.0;
+        if (p[0] < a.lx) {
+            np += 1.0;
+            kp += kei;
+            wp += w.vir[i];
+        }
         out += pm_inside<D>(a, p) ? 0.0 : 1.0;
     }
-    ke = pm_block_sum(ke, red);
-    pe = pm_block_sum(pe, red);
-    np = pm_block_sum(np, red);
-    out = pm_block_sum(out, red);
+    double sums[6] = {ke, pe, np, out, kp, wp};
+    pm_block_sums<6>(sums, red);
+    ke = sums[0];
+    pe = sums[1];
+    np = sums[2];
+    out = sums[3];
+    kp = sums[4];
+    wp = sums[5];
     const double T = a.n > 0 ? 2.0 * ke / ((double)D * (double)a.n) : 0.0;
     if (tid == 0 && rec_row >= 0) {
         PmRecord r;
@@ -279,6 +306,7 @@ __global__ void __launch_bounds__(kPmUpdate) k_pm_update(double* __restrict__ x,
         r.pe = pe;
         r.etotal = ke + pe;
         r.temperature = T;
+        r.pressure = (2.0 * kp + wp) / ((double)D * a.vol);
         r.n_pore = (long long)np;
         r.reflections = step == 0 ? 0LL : w.counts[0];
         r.n_outside = (long long)out + (step == 0 ? 0LL : w.counts[1]);
@@ -314,8 +342,10 @@ __global__ void __launch_bounds__(kPmUpdate) k_pm_update(double* __restrict__ x,
             for (int k = 0; k < D; ++k) v[(size_t)D * i + k] = vv[k];
         }
     }
-    refl = pm_block_sum(refl, red);
-    bad = pm_block_sum(bad, red);
+    double cnt[2] = {refl, bad};
+    pm_block_sums<2>(cnt, red);
+    refl = cnt[0];
+    bad = cnt[1];
     if (tid == 0) {
         // the counts start with the run (no memset node: callers may capture)
         w.counts[0] = (step == 0 ? 0LL : w.counts[0]) + (long long)refl;

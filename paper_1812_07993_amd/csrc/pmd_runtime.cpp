@@ -141,6 +141,39 @@ PoreDev pore_dev(const pmd_params& p, const pmd_pore& q)
     return d;
 }
 
+// The pore's void (the region of the pressure in the pore): the hole through
+// the slab (z range of the slab, radii r0, r1), the slit's gap, the whole box
+// without walls, nothing for a plain slab; and its volume in closed form:
+// pi r0^2 t, the cone's frustum pi t (r0^2 + r0 r1 + r1^2) / 3, the
+// ink-bottle's pi (t/2) (r0^2 + r1^2), Lx Ly gap, Lx Ly Lz.
+double pore_void_volume(const pmd_params& p, const pmd_pore& q)
+{
+    const double t = q.slab_thickness, pi = 3.14159265358979323846;
+    switch (q.kind) {
+    case PMD_PORE_NONE: return p.box[0] * p.box[1] * p.box[2];
+    case PMD_PORE_CYLINDER: return pi * q.r0 * q.r0 * t;
+    case PMD_PORE_SLIT: return p.box[0] * p.box[1] * q.slit_gap;
+    case PMD_PORE_CONE: return pi * t * (q.r0 * q.r0 + q.r0 * q.r1 + q.r1 * q.r1) / 3.0;
+    case PMD_PORE_INKBOTTLE: return pi * 0.5 * t * (q.r0 * q.r0 + q.r1 * q.r1);
+    default: return 0.0;
+    }
+}
+
+void set_pore_region(SysParams& sp, const pmd_params& p, const pmd_pore& q)
+{
+    sp.pkind = q.kind;
+    if (q.kind == PMD_PORE_SLIT) {
+        sp.pz0 = q.slab_center_z - 0.5 * q.slit_gap;
+        sp.pz1 = q.slab_center_z + 0.5 * q.slit_gap;
+    } else {
+        sp.pz0 = q.slab_center_z - 0.5 * q.slab_thickness;
+        sp.pz1 = q.slab_center_z + 0.5 * q.slab_thickness;
+    }
+    sp.pr0 = q.r0;
+    sp.pr1 = q.r1;
+    sp.pvol = pore_void_volume(p, q);
+}
+
 // Host count of the wall sites (used to size buffers before generation).
 int64_t host_wall_count(const pmd_params& p, const pmd_pore& q)
 {
@@ -1102,6 +1135,18 @@ const char* pmd_last_error(void) { return g_err.c_str(); }
 
 int pmd_version(void) { return 100; }
 
+int pmd_pore_volume(const pmd_params* params, const pmd_pore* pore, double* volume)
+{
+    try {
+        CHK(check_params(params, pore));
+        if (!volume) return fail(PMD_EINVAL, "volume must not be NULL");
+        *volume = pore_void_volume(*params, *pore);
+        return PMD_OK;
+    } catch (...) {
+        return fail(PMD_EHIP, "unexpected exception");
+    }
+}
+
 int pmd_batch_wall_room(int64_t resident_walls, int64_t new_walls)
 {
     try {
@@ -1191,6 +1236,7 @@ int pm_check(const pmd_pm_model* m, int64_t n, const double* x_dev, const double
     a.hdt = 0.5 * m->dt;
     a.tau = m->thermostat_tau;
     a.t0 = m->thermostat_t0;
+    a.vol = m->lx * m->ly * (m->dim == 3 ? m->lz : 1.0);
     *out = a;
     return PMD_OK;
 }
@@ -1318,6 +1364,7 @@ int pmd_create_system(const pmd_params* params, const pmd_pore* pore, int64_t n_
         p.nslots = 1;
         SysParams sp{};
         fill_sys_params(sp, *params, sys->grid, sys->tuning, (int)n_vapor, (int)nw);
+        set_pore_region(sp, *params, *pore);
         p.vt = sp.vcap;
         p.wt = (int)std::max<int64_t>(nw, 1);
         p.ct = key_capacity(sys->grid);
@@ -1436,7 +1483,8 @@ int pmd_get_forces(pmd_system* sys, double* out, int64_t n)
     try { return readback(sys, 2, out, n); } catch (...) { return fail(PMD_EHIP, "unexpected exception"); }
 }
 
-static void to_energies(const EnergyRec& r, int64_t nv, bool virial, pmd_energies* e)
+static void to_energies(const EnergyRec& r, int64_t nv, bool virial, double pore_volume,
+                        pmd_energies* e)
 {
     e->step = r.step;
     e->ke = r.ke;
@@ -1447,6 +1495,11 @@ static void to_energies(const EnergyRec& r, int64_t nv, bool virial, pmd_energie
     // a pool runs the summing kernel when any of its systems asks for it
     e->virial_vv = virial ? r.w_vv : 0.0;
     e->virial_vw = virial ? r.w_vw : 0.0;
+    e->ke_pore = virial ? r.ke_pore : 0.0;
+    e->virial_pore = virial ? r.w_pore : 0.0;
+    e->n_pore = virial ? (int64_t)r.n_pore : 0;
+    e->pore_volume = pore_volume;
+    e->pressure = virial && pore_volume > 0.0 ? (2.0 * r.ke_pore + r.w_pore) / (3.0 * pore_volume) : 0.0;
 }
 
 int pmd_get_energy_history(pmd_system* sys, pmd_energies* out, int64_t cap, int64_t* n_out)
@@ -1467,7 +1520,7 @@ int pmd_get_energy_history(pmd_system* sys, pmd_energies* out, int64_t cap, int6
         const int64_t take = std::min(avail, cap);
         for (int64_t r = 0; r < take; ++r)
             to_energies(buf[(size_t)((first + (avail - take) + r) % ring)], sys->nv, sys->tuning.virial != 0,
-                        out + r);
+                        pore_void_volume(sys->params, sys->pore), out + r);
         *n_out = take;
         return PMD_OK;
     } catch (...) {
@@ -1554,6 +1607,7 @@ int pmd_set_tuning(pmd_system* sys, const pmd_tuning* tuning)
         SysParams& sp = p.hsp[sys->slot];
         SysParams keep = sp;
         fill_sys_params(sp, sys->params, g, t, (int)sys->nv, (int)sys->nw);
+        set_pore_region(sp, sys->params, sys->pore);
         sp.voff = keep.voff;
         sp.woff = keep.woff;
         sp.coff = keep.coff;

@@ -48,7 +48,10 @@ class pmd_energies(ctypes.Structure):
     _fields_ = [("step", ctypes.c_int64), ("ke", ctypes.c_double),
                 ("pe_vv", ctypes.c_double), ("pe_vw", ctypes.c_double),
                 ("etotal", ctypes.c_double), ("temperature", ctypes.c_double),
-                ("virial_vv", ctypes.c_double), ("virial_vw", ctypes.c_double)]
+                ("virial_vv", ctypes.c_double), ("virial_vw", ctypes.c_double),
+                ("ke_pore", ctypes.c_double), ("virial_pore", ctypes.c_double),
+                ("n_pore", ctypes.c_int64), ("pore_volume", ctypes.c_double),
+                ("pressure", ctypes.c_double)]
 
 
 class pmd_tuning(ctypes.Structure):
@@ -72,13 +75,13 @@ class pmd_pm_model(ctypes.Structure):
 class pmd_pm_record(ctypes.Structure):
     _fields_ = [("step", ctypes.c_int64), ("ke", ctypes.c_double), ("pe", ctypes.c_double),
                 ("etotal", ctypes.c_double), ("temperature", ctypes.c_double),
-                ("n_pore", ctypes.c_int64), ("reflections", ctypes.c_int64),
+                ("pressure", ctypes.c_double), ("n_pore", ctypes.c_int64), ("reflections", ctypes.c_int64),
                 ("n_outside", ctypes.c_int64)]
 
 
 PM_RECORD_DTYPE = np.dtype([("step", np.int64), ("ke", np.float64), ("pe", np.float64),
                             ("etotal", np.float64), ("temperature", np.float64),
-                            ("n_pore", np.int64), ("reflections", np.int64),
+                            ("pressure", np.float64), ("n_pore", np.int64), ("reflections", np.int64),
                             ("n_outside", np.int64)])
 
 
@@ -126,6 +129,7 @@ _SIGS = {
                                       _P(ctypes.c_size_t)]),
     "pmd_batch_destroy": (ctypes.c_int, [_vp]),
     "pmd_batch_wall_room": (ctypes.c_int, [_i64, _i64]),
+    "pmd_pore_volume": (ctypes.c_int, [_P(pmd_params), _P(pmd_pore), _P(_d)]),
     "pmd_allpairs_forces": (ctypes.c_int, [ctypes.c_int, _i64, _vp, _P(_d), _d, _d, _vp, _vp, _vp, _vp]),
     "pmd_pm_record_rows": (_i64, [_i64, _i64]),
     "pmd_pm_run": (ctypes.c_int, [_P(pmd_pm_model), _i64, _vp, _vp, _vp, _i64, _i64, _vp, _i64, _vp]),
@@ -287,7 +291,9 @@ def pmd_get_wall_positions(h):
 
 def _energy_dict(e):
     return dict(step=e.step, ke=e.ke, pe_vv=e.pe_vv, pe_vw=e.pe_vw, etotal=e.etotal,
-                temperature=e.temperature, virial_vv=e.virial_vv, virial_vw=e.virial_vw)
+                temperature=e.temperature, virial_vv=e.virial_vv, virial_vw=e.virial_vw,
+                ke_pore=e.ke_pore, virial_pore=e.virial_pore, n_pore=e.n_pore,
+                pore_volume=e.pore_volume, pressure=e.pressure)
 
 
 def pmd_get_energies(h):
@@ -298,10 +304,13 @@ def pmd_get_energies(h):
 
 def pmd_get_energy_history(h, cap=1 << 20):
     """Recorded energies as a structured array (step, ke, pe_vv, pe_vw, etotal,
-    temperature, virial_vv, virial_vw)."""
+    temperature, virial_vv, virial_vw, ke_pore, virial_pore, n_pore,
+    pore_volume, pressure)."""
     dt = np.dtype([("step", np.int64), ("ke", np.float64), ("pe_vv", np.float64),
                    ("pe_vw", np.float64), ("etotal", np.float64), ("temperature", np.float64),
-                   ("virial_vv", np.float64), ("virial_vw", np.float64)])
+                   ("virial_vv", np.float64), ("virial_vw", np.float64),
+                   ("ke_pore", np.float64), ("virial_pore", np.float64), ("n_pore", np.int64),
+                   ("pore_volume", np.float64), ("pressure", np.float64)])
     out = np.zeros(cap, dtype=dt)
     n = ctypes.c_int64()
     _check(load().pmd_get_energy_history(h, ctypes.c_void_p(out.ctypes.data), cap,
@@ -316,6 +325,12 @@ def pmd_get_step(h):
 def pmd_get_positions_device(h, dev_ptr, n, stream=None):
     _check(load().pmd_get_positions_device(h, ctypes.c_void_p(dev_ptr), int(n),
                                            ctypes.c_void_p(stream) if stream else None))
+
+
+def pmd_pore_volume(params, pore):
+    v = ctypes.c_double()
+    _check(load().pmd_pore_volume(ctypes.byref(params), ctypes.byref(pore), ctypes.byref(v)))
+    return v.value
 
 
 def pmd_batch_wall_room(resident_walls, new_walls):

@@ -8,7 +8,8 @@ tests/forcecheck.py (relative 1e-12 FP64, 1e-5 mixed; per atom 1e-11,
 1e-4); positions and velocities after 10-20 steps within 1e-10 (FP64) and
 1e-6 (mixed) of the oracle's, relative to the largest velocity for v;
 records: energies to 1e-12 (FP64) and 1e-6 (mixed) of the kinetic energy,
-and the integer fields (molecules in the pore, wall reflections, molecules
+the pressure in the pore to the same fraction of its scale, and the integer
+fields (molecules in the pore, wall reflections, molecules
 outside the domain) exactly."""
 import numpy as np
 import pytest
@@ -31,7 +32,7 @@ def gpu_run(x, v, model, nsteps, every=1):
     vd = torch.as_tensor(np.ascontiguousarray(v), dtype=torch.float64, device=dev).clone()
     ad = torch.full((max(n, 1), d), float("nan"), dtype=torch.float64, device=dev)
     rows = poremd.pmd_pm_record_rows(nsteps, every)
-    rec = torch.zeros((rows, 8), dtype=torch.float64, device=dev)  # 64 bytes per record
+    rec = torch.zeros((rows, poremd.PM_RECORD_DTYPE.itemsize // 8), dtype=torch.float64, device=dev)
     s = torch.cuda.current_stream()
     poremd.pmd_pm_run(model, n, xd.data_ptr() if n else 0, vd.data_ptr() if n else 0,
                       ad.data_ptr(), nsteps, every, rec.data_ptr(), rows, s.cuda_stream)
@@ -71,6 +72,10 @@ def compare(xg, vg, ag, rg, xo, vo, ro, model_o, prec, what):
     assert np.array_equal(rg["reflections"], ro[:, 4].astype(np.int64)), what
     assert np.all(rg["n_outside"] == 0), what
     assert np.allclose(rg["temperature"], 2.0 * rg["ke"] / (xg.shape[1] * n), rtol=1e-14)
+    d = xg.shape[1]
+    vol = model_o.lx * model_o.ly * (model_o.lz if d == 3 else 1.0)
+    pscale = np.abs(ro[:, 5]).max() + np.abs(ro[:, 1]).max() / (d * vol)
+    assert np.abs(rg["pressure"] - ro[:, 5]).max() <= TOL_E[prec] * pscale, what
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])

@@ -65,3 +65,44 @@ def test_virial_sums_are_off_by_default():
     e = s.energies()
     assert e["virial_vv"] == 0.0 and e["virial_vw"] == 0.0 and e["pe_vv"] < 0.0
     s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("shape", ["cylinder", "cone", "inkbottle", "slit", "none"])
+def test_pressure_in_the_pore_matches_the_oracle(prec, shape):
+    """The pressure in the pore (Sec. 2's formula with V the pore's void
+    volume, over the molecules inside the void) at creation and after 30
+    steps: molecule count exact, kinetic energy to 1e-12, virial share to the
+    virial tolerance, volume to rounding."""
+    L = 16.0
+    pore = {"cylinder": synth.Pore("cylinder", 1.0, 8.0, 4.0, 3.5),
+            "cone": synth.Pore("cone", 1.0, 8.0, 4.0, 2.0, 5.0),
+            "inkbottle": synth.Pore("inkbottle", 1.0, 8.0, 4.0, 2.0, 5.0),
+            "slit": synth.Pore("slit", 1.0, 8.0, 2.0, slit_gap=4.0),
+            "none": synth.Pore("none")}[shape]
+    walls = synth.wall_sites(pore, (L, L, L))
+    rng = np.random.default_rng(23)
+    x = synth.rsa_place(rng, (L, L, L), 1000, walls, 0.9)
+    v = synth.maxwell(rng, 1000, 1.2)
+    params = poremd.make_params(L, prec)
+    cp = poremd.make_pore(pore.kind, pore.lattice_a, pore.slab_center_z, pore.slab_thickness,
+                          pore.r0, pore.r1, pore.slit_gap)
+    op = oracle.make_params(L)
+    oq = oracle.make_pore(pore.kind, pore.lattice_a, pore.slab_center_z, pore.slab_thickness,
+                          pore.r0, pore.r1, pore.slit_gap)
+    V = poremd.pmd_pore_volume(params, cp)
+    assert V == pytest.approx(oracle.pore_volume(oq, (L, L, L)), rel=1e-15)
+    s = poremd.System(params, cp, x, v,
+                      tuning=poremd.make_tuning(energy_every=10, rebin_every=4, virial=1))
+    for nsteps in (0, 30):
+        if nsteps:
+            s.step(nsteps)
+        X, Vv, e = s.positions(), s.velocities(), s.energies()
+        r = oracle.pore_pressure(X, Vv, op, oq)
+        assert e["n_pore"] == r["n_pore"] > 10
+        assert e["pore_volume"] == pytest.approx(r["volume"], rel=1e-15)
+        assert e["ke_pore"] == pytest.approx(r["ke_pore"], rel=1e-12)
+        assert e["virial_pore"] == pytest.approx(r["virial_pore"], rel=TOL[prec], abs=1e-12)
+        scale = (2 * r["ke_pore"] + abs(r["virial_pore"])) / (3 * r["volume"])
+        assert abs(e["pressure"] - r["pressure"]) <= TOL[prec] * scale
+    s.close()

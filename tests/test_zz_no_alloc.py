@@ -19,7 +19,7 @@ def _run(fn, model, x, v, nsteps, every):
     vd = torch.as_tensor(v, dtype=torch.float64, device=dev).clone()
     ad = torch.full((n, d), float("nan"), dtype=torch.float64, device=dev)
     rows = poremd.pmd_pm_record_rows(nsteps, every)
-    rec = torch.zeros((rows, 8), dtype=torch.float64, device=dev)
+    rec = torch.zeros((rows, poremd.PM_RECORD_DTYPE.itemsize // 8), dtype=torch.float64, device=dev)
     s = torch.cuda.current_stream()
     fn(model, n, xd.data_ptr(), vd.data_ptr(), ad.data_ptr(), nsteps, every, rec.data_ptr(), rows,
        s.cuda_stream)
