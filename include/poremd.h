@@ -129,7 +129,7 @@ typedef struct {
 /* Performance knobs; zero fields take the library default.  skin: extra
  * radius of the neighbour lists beyond the cutoff; rebin_every: steps
  * between neighbour-list rebuilds (a rebuild also happens early whenever an
- * atom has travelled more than skin/2 since the last one); block: threads
+ * atom has moved more than skin/2 from its position at the last one); block: threads
  * per workgroup of the force kernels (a multiple of 64 from 64 to 1024; each
  * workgroup owns one brick of cells, sized to hold about 0.8 x block atoms
  * unless brick_atoms says otherwise); list_cap:

@@ -27,7 +27,7 @@ enum Phase : int {
 };
 
 enum Status : int {
-    ST_HALT = 1,       // an atom travelled more than skin/2 since the last rebuild
+    ST_HALT = 1,       // an atom moved more than skin/2 away from its position at the last rebuild
     ST_OVERFLOW = 2,   // a neighbour list exceeded its capacity
     ST_NONFINITE = 4,  // a non-finite force or position appeared
     ST_TILE = 8,       // a brick's halo did not fit the LDS tile
@@ -65,7 +65,7 @@ struct SysParams {
     double rc2, rl2;       // cutoff^2, neighbour-list radius^2
     double dt, mass, inv_mass;
     double rw2;            // wall-list radius^2, (r_c + skin/2)^2
-    float half_skin;       // rebuild threshold on the travelled path
+    float half_skin;       // rebuild threshold on the displacement since the last rebuild
     int thermo;            // 1: Berendsen thermostat on
     int virial;            // 1: record the virial sums
     double tau_t, t0, dof; // its rise time, target temperature, 3 nv - 3
@@ -142,7 +142,9 @@ struct PoolDev {
     double* V[2];
     int* id[2];
     double* A;            // accelerations at rest (stride vt)
-    float* travel;        // path length since the last rebuild
+    f4* lref;             // FP32 cell-local position at the last rebuild (w unused):
+                          // the displacement since then is the step's new local
+                          // position minus this, both from the same cell origin
     int* cref;            // packed cell (cx | cy << 10 | cz << 20) at the last rebuild
     int* cell_lin;        // linear cell index cx + nx (cy + ny cz) at the last rebuild
     void* L[2];           // local coordinates (f4 or d4), vt + wt entries; walls at vt + w

@@ -9,7 +9,8 @@
 // Forces (Sec. 2, eq. 2) are short-ranged Lennard-Jones sums over Verlet
 // neighbour lists of radius r_c + skin, rebuilt from a cell grid (cells of
 // edge >= r_c + skin) at the start of every graph replay and whenever an
-// atom has travelled more than skin/2.  The rebuild is five launches: drift
+// atom has moved more than skin/2 away from its position at the last
+// rebuild (then every pair within r_c is still in the lists).  The rebuild is five launches: drift
 // and bin count, per-system scan, arrival scatter, stable placement (atoms
 // ordered by cell, then by caller index), list build.
 //
@@ -592,20 +593,22 @@ __global__ void k_bin_place(PoolDev P)
     Vd[vt + d] = Vs[vt + o];
     Vd[2 * vt + d] = Vs[2 * vt + o];
     P.id[st.ibuf][d] = myid;
-    P.travel[d] = 0.0f;
     V* Lc = (V*)P.L[st.lbuf];
     if (cell < sp.nkey) {
         int cx, cy, cz;
         key_cell(sp, cell, cx, cy, cz);
         P.cref[d] = cx | (cy << 10) | (cz << 20);
         P.cell_lin[d] = cx + sp.nc[0] * (cy + sp.nc[1] * cz);
-        Lc[d] = make4<T>(local_axis(x, cx, sp.h[0], sp.L[0], sp.invL[0]),
-                         local_axis(y, cy, sp.h[1], sp.L[1], sp.invL[1]),
-                         local_axis(z, cz, sp.h[2], sp.L[2], sp.invL[2]));
+        const double lx = local_axis(x, cx, sp.h[0], sp.L[0], sp.invL[0]);
+        const double ly = local_axis(y, cy, sp.h[1], sp.L[1], sp.invL[1]);
+        const double lz = local_axis(z, cz, sp.h[2], sp.L[2], sp.invL[2]);
+        Lc[d] = make4<T>(lx, ly, lz);
+        P.lref[d] = make4<float>(lx, ly, lz);
     } else {
         P.cref[d] = 0;
         P.cell_lin[d] = -1;
         Lc[d] = make4<T>(0.0, 0.0, 0.0);
+        P.lref[d] = make4<float>(0.0, 0.0, 0.0);
     }
     // final cell table for the list build and the readbacks
     for (int q = c.li; q < sp.nkey + 2; q += sp.vcap) P.cstart[sp.coff + q] = cell_begin(P, sp, q);
@@ -1206,8 +1209,9 @@ __device__ void edge_pass(const PoolDev& P, const SysParams& sp, const StepCtx<T
 }
 
 // F3 (second half-kick) and, unless the run ends, F2 of the next step (first
-// half-kick, drift, wrap, local coordinates, travelled path).  Returns the
-// kinetic energy at the full step; raises halt and non-finite bits.
+// half-kick, drift, wrap, local coordinates, displacement since the last
+// rebuild).  Returns the kinetic energy at the full step; raises halt and
+// non-finite bits.
 template <typename T>
 __device__ double atom_epilogue(const PoolDev& P, const StepCtx<T>& x, int i,
                                 const Acc& a, int& flags)
@@ -1259,12 +1263,15 @@ __device__ double atom_epilogue(const PoolDev& P, const StepCtx<T>& x, int i,
             const int cr = P.cref[i];
             const int cx = cr & 1023, cy = (cr >> 10) & 1023, cz = cr >> 20;
             V* Ln = (V*)P.L[x.lbuf ^ 1];
-            Ln[i] = make4<T>(local_axis(xx, cx, x.h[0], x.L[0], x.invL[0]),
-                             local_axis(yy, cy, x.h[1], x.L[1], x.invL[1]),
-                             local_axis(zz, cz, x.h[2], x.L[2], x.invL[2]));
-            const float tr = P.travel[i] + (float)(sqrt(vx * vx + vy * vy + vz * vz) * x.dt);
-            P.travel[i] = tr;
-            if (tr > x.half_skin) flags |= ST_HALT;
+            const double lx = local_axis(xx, cx, x.h[0], x.L[0], x.invL[0]);
+            const double ly = local_axis(yy, cy, x.h[1], x.L[1], x.invL[1]);
+            const double lz = local_axis(zz, cz, x.h[2], x.L[2], x.invL[2]);
+            Ln[i] = make4<T>(lx, ly, lz);
+            // displacement since the last rebuild: both local positions are
+            // measured from the same cell origin (minimum image)
+            const f4 r = P.lref[i];
+            const float ex = (float)lx - r.x, ey = (float)ly - r.y, ez = (float)lz - r.z;
+            if (ex * ex + ey * ey + ez * ez > x.half_skin * x.half_skin) flags |= ST_HALT;
         }
     }
     if (!isfinite(a.fx + a.fy + a.fz) || !isfinite(kei)) flags |= ST_NONFINITE;
@@ -1324,6 +1331,189 @@ __device__ void step_reduce(const PoolDev& P, const SysParams& sp, int s, int b,
     }
 }
 
+// Shift -d h of every 6-bit cell-offset code (2 bits per axis, d + 1 in
+// {0, 1, 2}; code 3 does not occur): one LDS read per list entry instead of
+// decoding the three fields.
+template <typename T>
+__device__ __forceinline__ typename V4<T>::type shift_lut_entry(int q, T hx, T hy, T hz)
+{
+    typename V4<T>::type v;
+    v.x = fma(-(T)(q & 3), hx, hx);
+    v.y = fma(-(T)((q >> 2) & 3), hy, hy);
+    v.z = fma(-(T)((q >> 4) & 3), hz, hz);
+    v.w = (T)0;
+    return v;
+}
+
+// Shift of a list entry's cell-offset code: from the LDS table in FP32 (one
+// read), decoded arithmetically in FP64 (where a table of double4 would hold
+// too many registers per group of entries).
+template <typename T>
+__device__ __forceinline__ typename V4<T>::type shift_at(const typename V4<T>::type* lut, unsigned e,
+                                                         const StepCtx<T>& x)
+{
+    if constexpr (sizeof(T) == 4) {
+        return lut[e >> kIndexBits];
+    } else {
+        typename V4<T>::type v;
+        v.x = shift_of<T>(e, 0, x.hx);
+        v.y = shift_of<T>(e, 2, x.hy);
+        v.z = shift_of<T>(e, 4, x.hz);
+        v.w = (T)0;
+        return v;
+    }
+}
+
+// A list entry in the band around the cutoff: counted, and the first two
+// list positions kept for the pass that decides them in FP64.
+__device__ __forceinline__ void note_edge(int& ne, int& k0, int& k1, int k)
+{
+    k0 = ne == 0 ? k : k0;
+    k1 = ne == 1 ? k : k1;
+    ++ne;
+}
+
+// One list entry's pair with no branch: w (and the energy) is masked to 0
+// unless `in` (a live entry inside the cutoff and outside the band), and r^2
+// is replaced by 1 where masked, so no infinity or NaN is formed; adding
+// the masked zero leaves every sum exactly as a skipped pair would.
+template <typename T, bool VIR, bool DOE>
+__device__ __forceinline__ void pair_masked(const StepCtx<T>& x, Acc& a, T dx, T dy, T dz, T r2, bool in,
+                                            bool wall)
+{
+    const T sr2 = inv_of<T>(in ? r2 : (T)1);
+    const T sr6 = sr2 * sr2 * sr2;
+    const T wf = sr2 * sr6 * ((wall ? x.A12w : x.A12v) * sr6 - (wall ? x.B6w : x.B6v));
+    const T w = in ? wf : (T)0;
+    a.fx += (double)(w * dx);
+    a.fy += (double)(w * dy);
+    a.fz += (double)(w * dz);
+    if constexpr (DOE) {
+        const T u = sr6 * ((wall ? x.Aw : x.Av) * sr6 - (wall ? x.Bw : x.Bv)) - (wall ? x.ucw : x.ucv);
+        const double ud = (double)(in ? u : (T)0);
+        if (wall)
+            a.ew += ud;
+        else
+            a.ev += ud;
+        if constexpr (VIR) {
+            const double vd = (double)(w * r2);  // r . f of the pair
+            if (wall)
+                a.ww += vd;
+            else
+                a.wv += vd;
+        }
+    }
+}
+
+// The brick's atoms, one lane each: the pair loops, the rare cutoff-band
+// pass, the epilogue (F3 and the next F2); DOE: a recording step (energies,
+// with VIR the virial sums and the pore's sums too).
+template <typename T, bool VIR, bool DOE>
+__device__ __forceinline__ void step_atoms(PoolDev& P, const SysParams& sp, const StepCtx<T>& x,
+                                           const Tile<T>& tl, const typename V4<T>::type* lut, int i0,
+                                           int i1, Acc& a, double& ke, double& lwv, double& lkp,
+                                           double& lwp, double& lnp, int& flags)
+{
+    using V = typename V4<T>::type;
+    const int vt = P.vt;
+    for (int i = i0 + (int)threadIdx.x; i < i1; i += blockDim.x) {
+        const V me = x.Lc[i];
+        const int nl = P.nlist[i];
+        const int nvap = nl & 0xFFFF, nall = nvap + (nl >> 16);
+        a.fx = a.fy = a.fz = 0.0;
+        if constexpr (VIR) a.wv = 0.0;
+        // entries come kGroupV (vapour, as kGroupV / 4 chunk loads) or
+        // kGroupW<T> (walls) at a time, the next group's loads in flight while
+        // the current one is evaluated; a group's partner positions (from LDS
+        // for vapour, from global memory for walls) and shifts are all read
+        // before any is used.  Pairs whose FP32 r^2 lies within a narrow band
+        // around the cutoff are left out here and decided in FP64 after the
+        // whole list (a rare slow path: a few atoms per step).  Every load is
+        // unconditional, with indices clamped to valid memory (list chunks
+        // past the end of this atom's list exist up to the capacity; their
+        // values are not used), so the code is straight-line and each wait
+        // covers only the loads it needs
+        int ne = 0, ke0 = 0, ke1 = 0;  // cutoff-band entries: count, first two list positions
+        const int lastrow = P.cap - 1, lastchunk = P.cap / 4 - 1;
+        const uint4* lst4 = (const uint4*)P.list + i;  // chunk c of this atom at lst4[c * vt]
+        static_assert(kGroupV == 4, "the vapour loop takes one 16-byte chunk per group");
+        // one group of four vapour entries (one chunk) at list position k
+        auto vapour_group = [&](const uint4 c, int k) {
+            const unsigned ec[4] = {c.x, c.y, c.z, c.w};
+            V o[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) o[u] = tl.pos[k + u < nvap ? (int)(ec[u] & kIndexMask) : 0];
+            V sh[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) sh[u] = shift_at<T>(lut, ec[u], x);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const bool live = k + u < nvap;
+                const T dx = me.x - o[u].x + sh[u].x;
+                const T dy = me.y - o[u].y + sh[u].y;
+                const T dz = me.z - o[u].z + sh[u].z;
+                const T r2 = dx * dx + dy * dy + dz * dz;
+                const bool near = live && sizeof(T) == 4 && fabs(r2 - x.rc2) < x.band;
+                if (near) note_edge(ne, ke0, ke1, k + u);
+                pair_masked<T, VIR, DOE>(x, a, dx, dy, dz, r2, live && r2 < x.rc2 && !near, false);
+            }
+        };
+        // two chunks per trip in alternating registers: the next chunk's
+        // load is in flight while the current one is evaluated (the empty
+        // asm with a memory clobber keeps the compiler from folding the
+        // prefetched load and the first one into a single load at the top)
+        uint4 ca = lst4[0], cb;
+        for (int k0 = 0; k0 < nvap; k0 += 8) {
+            cb = lst4[(size_t)min((k0 >> 2) + 1, lastchunk) * vt];
+            asm volatile("" ::: "memory");
+            vapour_group(ca, k0);
+            if (k0 + 4 >= nvap) break;
+            ca = lst4[(size_t)min((k0 >> 2) + 2, lastchunk) * vt];
+            asm volatile("" ::: "memory");
+            vapour_group(cb, k0 + 4);
+        }
+        if (nall > nvap) {
+            unsigned cw[kGroupW<T>];
+#pragma unroll
+            for (int u = 0; u < kGroupW<T>; ++u) cw[u] = P.list[list_at(vt, i, min(nvap + u, lastrow))];
+            for (int k0 = nvap; k0 < nall; k0 += kGroupW<T>) {
+                V ow[kGroupW<T>];
+#pragma unroll
+                for (int u = 0; u < kGroupW<T>; ++u) ow[u] = x.Lc[vt + (k0 + u < nall ? (int)(cw[u] & kIndexMask) : 0)];
+                unsigned nw[kGroupW<T>];
+#pragma unroll
+                for (int u = 0; u < kGroupW<T>; ++u)
+                    nw[u] = P.list[list_at(vt, i, min(k0 + kGroupW<T> + u, lastrow))];
+#pragma unroll
+                for (int u = 0; u < kGroupW<T>; ++u) {
+                    const bool live = k0 + u < nall;
+                    const V sw = shift_at<T>(lut, cw[u], x);
+                    const T dx = me.x - ow[u].x + sw.x;
+                    const T dy = me.y - ow[u].y + sw.y;
+                    const T dz = me.z - ow[u].z + sw.z;
+                    const T r2 = dx * dx + dy * dy + dz * dz;
+                    const bool near = live && sizeof(T) == 4 && fabs(r2 - x.rc2) < x.band;
+                    if (near) note_edge(ne, ke0, ke1, k0 + u);
+                    pair_masked<T, VIR, DOE>(x, a, dx, dy, dz, r2, live && r2 < x.rc2 && !near, true);
+                }
+#pragma unroll
+                for (int u = 0; u < kGroupW<T>; ++u) cw[u] = nw[u];
+            }
+        }
+        if (ne) edge_pass<T, VIR>(P, sp, x, tl, i, nvap, nall, ne, ke0, ke1, a);
+        const double kei = atom_epilogue<T>(P, x, i, a, flags);
+        ke += kei;
+        if constexpr (VIR && DOE) {
+            lwv += a.wv;
+            if (in_pore(sp, x.X[i], x.X[vt + i], x.X[2 * vt + i])) {
+                lkp += kei;
+                lwp += a.wv;
+                lnp += 1.0;
+            }
+        }
+    }
+}
+
 template <typename T, bool VIR>
 __device__ __forceinline__ void step_body(PoolDev& P, int kk)
 {
@@ -1338,7 +1528,7 @@ __device__ __forceinline__ void step_body(PoolDev& P, int kk)
     const SysParams& sp = P.sp[s];
     const SysState st = P.st[s];
     // step kk of the replay runs unless the run ends earlier or an earlier
-    // step of the replay raised a stop (travel beyond skin/2, non-finite)
+    // step of the replay raised a stop (displacement beyond skin/2, non-finite)
     if (kk >= st.remaining || kk > st.stop) return;
     const int tid = threadIdx.x;
     const StepCtx<T> x = step_ctx<T>(P, sp, st, kk);
@@ -1349,9 +1539,11 @@ __device__ __forceinline__ void step_body(PoolDev& P, int kk)
     }
     const HaloGeo g = halo_geo(sp, c.b);
     Tile<T> tl = tile_of<T>(smem, P);
+    // shift of each cell-offset code (made visible by the staging's barriers)
+    __shared__ V lut[sizeof(T) == 4 ? 64 : 1];
+    if (sizeof(T) == 4 && tid < 64) lut[tid] = shift_lut_entry<T>(tid, x.hx, x.hy, x.hz);
     const int tot = stage_halo<T>(P, sp, g, tl, x.Lc, true, lds_scan);
 
-    const int vt = P.vt;
     const int key0 = c.b * sp.bcells;
     const int i0 = P.cstart[sp.coff + key0], i1 = P.cstart[sp.coff + key0 + sp.bcells];
 
@@ -1363,104 +1555,13 @@ __device__ __forceinline__ void step_body(PoolDev& P, int kk)
     Acc a{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     double lwv = 0.0, lkp = 0.0, lwp = 0.0, lnp = 0.0;
     int flags = tot < 0 ? (ST_OVERFLOW | ST_TILE) : 0;
-    for (int i = i0 + tid; tot >= 0 && i < i1; i += blockDim.x) {
-        const V me = x.Lc[i];
-        const int nl = P.nlist[i];
-        const int nvap = nl & 0xFFFF, nall = nvap + (nl >> 16);
-        a.fx = a.fy = a.fz = 0.0;
-        if constexpr (VIR) a.wv = 0.0;
-        // entries come kGroupV (vapour, as kGroupV / 4 chunk loads) or
-        // kGroupW<T> (walls) at a time, the next group's loads in flight while
-        // the current one is evaluated; vapour partners are read from LDS, wall
-        // partners from global memory.  Pairs whose FP32 r^2 lies within a
-        // narrow band around the cutoff are left out here and decided in FP64
-        // after the whole list (a rare slow path: a few atoms per step), so
-        // the per-pair code has no branch.  Every load is unconditional, with
-        // indices clamped to valid memory (list chunks past the end of this
-        // atom's list exist up to the capacity; their values are not used), so
-        // the code is straight-line and each wait covers only the loads it needs
-        int ne = 0, ke0 = 0, ke1 = 0;  // cutoff-band entries: count, first two list positions
-        const int lastrow = P.cap - 1, lastchunk = P.cap / 4 - 1;
-        const uint4* lst4 = (const uint4*)P.list + i;  // chunk c of this atom at lst4[c * vt]
-        constexpr int NC = kGroupV / 4;
-        uint4 cc[NC];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) cc[c] = lst4[(size_t)min(c, lastchunk) * vt];
-        for (int k0 = 0; k0 < nvap; k0 += kGroupV) {
-            uint4 cn[NC];
-#pragma unroll
-            for (int c = 0; c < NC; ++c) cn[c] = lst4[(size_t)min((k0 >> 2) + NC + c, lastchunk) * vt];
-            unsigned ec[kGroupV];
-#pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                ec[4 * c] = cc[c].x;
-                ec[4 * c + 1] = cc[c].y;
-                ec[4 * c + 2] = cc[c].z;
-                ec[4 * c + 3] = cc[c].w;
-            }
-#pragma unroll
-            for (int u = 0; u < kGroupV; ++u) {
-                const bool live = k0 + u < nvap;
-                const unsigned e = ec[u];
-                const V o = tl.pos[live ? (int)(e & kIndexMask) : 0];
-                const T dx = me.x - o.x + shift_of<T>(e, 0, x.hx);
-                const T dy = me.y - o.y + shift_of<T>(e, 2, x.hy);
-                const T dz = me.z - o.z + shift_of<T>(e, 4, x.hz);
-                const T r2 = dx * dx + dy * dy + dz * dz;
-                const bool near = live && sizeof(T) == 4 && fabs(r2 - x.rc2) < x.band;
-                ke0 = (near && ne == 0) ? k0 + u : ke0;
-                ke1 = (near && ne == 1) ? k0 + u : ke1;
-                ne += near ? 1 : 0;
-                if (live && r2 < x.rc2 && !near) pair_term<T, VIR>(x, a, dx, dy, dz, r2, false);
-            }
-#pragma unroll
-            for (int c = 0; c < NC; ++c) cc[c] = cn[c];
-        }
-        if (nall > nvap) {
-            unsigned cw[kGroupW<T>];
-#pragma unroll
-            for (int u = 0; u < kGroupW<T>; ++u) cw[u] = P.list[list_at(vt, i, min(nvap + u, lastrow))];
-            for (int k0 = nvap; k0 < nall; k0 += kGroupW<T>) {
-                V ow[kGroupW<T>];
-#pragma unroll
-                for (int u = 0; u < kGroupW<T>; ++u)
-                    ow[u] = x.Lc[vt + (k0 + u < nall ? (int)(cw[u] & kIndexMask) : 0)];
-                unsigned nw[kGroupW<T>];
-#pragma unroll
-                for (int u = 0; u < kGroupW<T>; ++u)
-                    nw[u] = P.list[list_at(vt, i, min(k0 + kGroupW<T> + u, lastrow))];
-#pragma unroll
-                for (int u = 0; u < kGroupW<T>; ++u) {
-                    const bool live = k0 + u < nall;
-                    const unsigned e = cw[u];
-                    const V o = ow[u];
-                    const T dx = me.x - o.x + shift_of<T>(e, 0, x.hx);
-                    const T dy = me.y - o.y + shift_of<T>(e, 2, x.hy);
-                    const T dz = me.z - o.z + shift_of<T>(e, 4, x.hz);
-                    const T r2 = dx * dx + dy * dy + dz * dz;
-                    const bool near = live && sizeof(T) == 4 && fabs(r2 - x.rc2) < x.band;
-                    ke0 = (near && ne == 0) ? k0 + u : ke0;
-                    ke1 = (near && ne == 1) ? k0 + u : ke1;
-                    ne += near ? 1 : 0;
-                    if (live && r2 < x.rc2 && !near) pair_term<T, VIR>(x, a, dx, dy, dz, r2, true);
-                }
-#pragma unroll
-                for (int u = 0; u < kGroupW<T>; ++u) cw[u] = nw[u];
-            }
-        }
-        if (ne) edge_pass<T, VIR>(P, sp, x, tl, i, nvap, nall, ne, ke0, ke1, a);
-        const double kei = atom_epilogue<T>(P, x, i, a, flags);
-        ke += kei;
-        if constexpr (VIR) {
-            if (x.doE) {
-                lwv += a.wv;
-                if (in_pore(sp, x.X[i], x.X[vt + i], x.X[2 * vt + i])) {
-                    lkp += kei;
-                    lwp += a.wv;
-                    lnp += 1.0;
-                }
-            }
-        }
+    // energies (and virial sums) only on recording steps: a workgroup-uniform
+    // choice between two builds of the pair loops
+    if (tot >= 0) {
+        if (x.doE)
+            step_atoms<T, VIR, true>(P, sp, x, tl, lut, i0, i1, a, ke, lwv, lkp, lwp, lnp, flags);
+        else
+            step_atoms<T, VIR, false>(P, sp, x, tl, lut, i0, i1, a, ke, lwv, lkp, lwp, lnp, flags);
     }
     // vapour pairs were met from both atoms: half of each sum (and each
     // pair's virial is shared equally by its two molecules)
@@ -1567,7 +1668,7 @@ __global__ void __launch_bounds__(256) k_lambda(PoolDev P, int kk)
 
 // Per atom: v <- lambda v on the full-step velocities that k_step stored,
 // then (unless this is the run's last step) v += a dt/2, x += v dt, wrap, new
-// local coordinates and travelled path, exactly as the fused step epilogue
+// local coordinates and displacement test, exactly as the fused step epilogue
 // does without the thermostat.
 template <typename T>
 __global__ void k_thermo(PoolDev P, int kk)
@@ -1608,12 +1709,13 @@ __global__ void k_thermo(PoolDev P, int kk)
     const int cr = P.cref[i];
     const int cx = cr & 1023, cy = (cr >> 10) & 1023, cz = cr >> 20;
     V* Ln = (V*)P.L[st.lbuf ^ (kk & 1) ^ 1];
-    Ln[i] = make4<T>(local_axis(xx, cx, sp.h[0], sp.L[0], sp.invL[0]),
-                     local_axis(yy, cy, sp.h[1], sp.L[1], sp.invL[1]),
-                     local_axis(zz, cz, sp.h[2], sp.L[2], sp.invL[2]));
-    const float tr = P.travel[i] + (float)(sqrt(vx * vx + vy * vy + vz * vz) * sp.dt);
-    P.travel[i] = tr;
-    int f = tr > sp.half_skin ? ST_HALT : 0;
+    const double lx = local_axis(xx, cx, sp.h[0], sp.L[0], sp.invL[0]);
+    const double ly = local_axis(yy, cy, sp.h[1], sp.L[1], sp.invL[1]);
+    const double lz = local_axis(zz, cz, sp.h[2], sp.L[2], sp.invL[2]);
+    Ln[i] = make4<T>(lx, ly, lz);
+    const f4 r = P.lref[i];
+    const float ex = (float)lx - r.x, ey = (float)ly - r.y, ez = (float)lz - r.z;
+    int f = ex * ex + ey * ey + ez * ez > sp.half_skin * sp.half_skin ? ST_HALT : 0;
     if (!isfinite(xx + yy + zz + vx + vy + vz)) f |= ST_NONFINITE;
     if (f) {
         // rare: an early rebuild (or a failure) after this step
@@ -1846,7 +1948,7 @@ __global__ void k_copy_in(PoolDev P, int slot, const double* pos, const double* 
     }
     P.A[i] = P.A[vt + i] = P.A[2 * vt + i] = 0.0;
     P.id[st.ibuf][i] = p;
-    P.travel[i] = 0.0f;
+    P.lref[i] = make4<float>(0.0, 0.0, 0.0);
 }
 
 hipError_t launch_copy_in(const PoolDev& P, int slot, const double* pos, const double* vel, int n,

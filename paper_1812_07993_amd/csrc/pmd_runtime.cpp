@@ -274,7 +274,7 @@ struct Pool {
     double* V[2] = {nullptr, nullptr};
     int* id[2] = {nullptr, nullptr};
     double* A = nullptr;
-    float* travel = nullptr;
+    f4* lref = nullptr;
     int* cref = nullptr;
     int* cell_lin = nullptr;
     void* L[2] = {nullptr, nullptr};
@@ -380,7 +380,7 @@ struct Pool {
             d.L[b] = L[b];
         }
         d.A = A;
-        d.travel = travel;
+        d.lref = lref;
         d.cref = cref;
         d.cell_lin = cell_lin;
         d.count = count;
@@ -409,7 +409,8 @@ size_t pool_bytes(int precision, int vt, int wt, int ct, int wct, int nbt, int n
 {
     size_t s = 0;
     s += 2 * 2 * 3 * (size_t)vt * 8 + 3 * (size_t)vt * 8;  // X, V double-buffered, A
-    s += 2 * (size_t)vt * 4 + 3 * (size_t)vt * 4;          // id x2, travel, cref, cell_lin
+    s += 2 * (size_t)vt * 4 + 2 * (size_t)vt * 4;          // id x2, cref, cell_lin
+    s += (size_t)vt * 16;                                  // reference positions
     s += 2 * (size_t)(vt + wt) * lsize(precision);         // local coordinates x2
     s += 3 * (size_t)ct * 4 + 3 * (size_t)std::max(vt, wt) * 4;
     s += (size_t)vt * cap * 4 + (size_t)vt * 4;            // lists
@@ -447,7 +448,7 @@ int pool_allocate(Pool& p)
         p.L[b] = l;
     }
     CHK(p.alloc(&p.A, 3 * (size_t)vt));
-    CHK(p.alloc(&p.travel, vt));
+    CHK(p.alloc(&p.lref, vt));
     CHK(p.alloc(&p.cref, vt));
     CHK(p.alloc(&p.cell_lin, vt));
     CHK(p.alloc(&p.count, p.ct));
@@ -471,7 +472,7 @@ int pool_allocate(Pool& p)
     HIPCHK(hipMemset(p.d_st, 0, sizeof(SysState) * (size_t)p.nslots));
     HIPCHK(hipMemset(p.d_sp, 0, sizeof(SysParams) * (size_t)p.nslots));
     HIPCHK(hipMemset(p.nlist, 0, sizeof(int) * (size_t)vt));
-    HIPCHK(hipMemset(p.travel, 0, sizeof(float) * (size_t)vt));
+    HIPCHK(hipMemset(p.lref, 0, sizeof(f4) * (size_t)vt));
     for (int b = 0; b < 2; ++b) {
         HIPCHK(hipMemset(p.L[b], 0, lsize(p.precision) * ((size_t)vt + wt)));
         HIPCHK(hipMemset(p.X[b], 0, sizeof(double) * 3 * (size_t)vt));
@@ -900,7 +901,7 @@ int move_system(Pool& src, int sslot, Pool& dst, int dslot)
                              (size_t)a.nw * 8, hipMemcpyDeviceToDevice));
     }
     HIPCHK(hipMemcpy(dst.id[0] + b.voff, src.id[st.ibuf] + a.voff, nv * 4, hipMemcpyDeviceToDevice));
-    HIPCHK(hipMemcpy(dst.travel + b.voff, src.travel + a.voff, nv * 4, hipMemcpyDeviceToDevice));
+    HIPCHK(hipMemcpy(dst.lref + b.voff, src.lref + a.voff, nv * sizeof(f4), hipMemcpyDeviceToDevice));
     HIPCHK(hipMemcpy(dst.cref + b.voff, src.cref + a.voff, nv * 4, hipMemcpyDeviceToDevice));
     HIPCHK(hipMemcpy(dst.cell_lin + b.voff, src.cell_lin + a.voff, nv * 4, hipMemcpyDeviceToDevice));
     HIPCHK(hipMemset(dst.nlist + b.voff, 0, nv * 4));
