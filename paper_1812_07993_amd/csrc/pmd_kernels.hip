@@ -1208,6 +1208,30 @@ __device__ void edge_pass(const PoolDev& P, const SysParams& sp, const StepCtx<T
     for (int k = 0; k < nall; ++k) edge_entry<T, VIR>(P, sp, x, tl, i, k, nvap, me, xi, yi, zi, a);
 }
 
+// What a lane reads of its atom before the pair loops: the local position,
+// the list lengths and the first list chunk.  They are independent loads,
+// issued together; for a lane's first atom they are issued before the halo
+// staging and arrive while it runs.  (Preloading the epilogue's position and
+// velocity too holds 12 more registers through the pair loops, which spill.)
+template <typename T>
+struct AtomIn {
+    typename V4<T>::type me;
+    int nl;
+    uint4 c0;
+};
+
+template <typename T>
+__device__ __forceinline__ AtomIn<T> atom_in(const PoolDev& P, const StepCtx<T>& x, int i)
+{
+    const int vt = P.vt;
+    AtomIn<T> r;
+    r.me = x.Lc[i];
+    r.nl = P.nlist[i];
+    r.c0 = ((const uint4*)P.list)[i];  // chunk 0 of slot i
+    (void)vt;
+    return r;
+}
+
 // F3 (second half-kick) and, unless the run ends, F2 of the next step (first
 // half-kick, drift, wrap, local coordinates, displacement since the last
 // rebuild).  Returns the kinetic energy at the full step; raises halt and
@@ -1411,14 +1435,15 @@ __device__ __forceinline__ void pair_masked(const StepCtx<T>& x, Acc& a, T dx, T
 template <typename T, bool VIR, bool DOE>
 __device__ __forceinline__ void step_atoms(PoolDev& P, const SysParams& sp, const StepCtx<T>& x,
                                            const Tile<T>& tl, const typename V4<T>::type* lut, int i0,
-                                           int i1, Acc& a, double& ke, double& lwv, double& lkp,
-                                           double& lwp, double& lnp, int& flags)
+                                           int i1, const AtomIn<T>& first, Acc& a, double& ke, double& lwv,
+                                           double& lkp, double& lwp, double& lnp, int& flags)
 {
     using V = typename V4<T>::type;
     const int vt = P.vt;
     for (int i = i0 + (int)threadIdx.x; i < i1; i += blockDim.x) {
-        const V me = x.Lc[i];
-        const int nl = P.nlist[i];
+        const AtomIn<T> in = i == i0 + (int)threadIdx.x ? first : atom_in<T>(P, x, i);
+        const V me = in.me;
+        const int nl = in.nl;
         const int nvap = nl & 0xFFFF, nall = nvap + (nl >> 16);
         a.fx = a.fy = a.fz = 0.0;
         if constexpr (VIR) a.wv = 0.0;
@@ -1462,7 +1487,7 @@ __device__ __forceinline__ void step_atoms(PoolDev& P, const SysParams& sp, cons
         // load is in flight while the current one is evaluated (the empty
         // asm with a memory clobber keeps the compiler from folding the
         // prefetched load and the first one into a single load at the top)
-        uint4 ca = lst4[0], cb;
+        uint4 ca = in.c0, cb;
         for (int k0 = 0; k0 < nvap; k0 += 8) {
             cb = lst4[(size_t)min((k0 >> 2) + 1, lastchunk) * vt];
             asm volatile("" ::: "memory");
@@ -1542,10 +1567,12 @@ __device__ __forceinline__ void step_body(PoolDev& P, int kk)
     // shift of each cell-offset code (made visible by the staging's barriers)
     __shared__ V lut[sizeof(T) == 4 ? 64 : 1];
     if (sizeof(T) == 4 && tid < 64) lut[tid] = shift_lut_entry<T>(tid, x.hx, x.hy, x.hz);
-    const int tot = stage_halo<T>(P, sp, g, tl, x.Lc, true, lds_scan);
-
     const int key0 = c.b * sp.bcells;
     const int i0 = P.cstart[sp.coff + key0], i1 = P.cstart[sp.coff + key0 + sp.bcells];
+    // the lane's first atom: its loads are in flight during the staging
+    AtomIn<T> first{};
+    if (i0 + tid < i1) first = atom_in<T>(P, x, i0 + tid);
+    const int tot = stage_halo<T>(P, sp, g, tl, x.Lc, true, lds_scan);
 
     double ke = 0.0;
     // force fields per atom; the energy and virial fields run over all of
@@ -1559,9 +1586,9 @@ __device__ __forceinline__ void step_body(PoolDev& P, int kk)
     // choice between two builds of the pair loops
     if (tot >= 0) {
         if (x.doE)
-            step_atoms<T, VIR, true>(P, sp, x, tl, lut, i0, i1, a, ke, lwv, lkp, lwp, lnp, flags);
+            step_atoms<T, VIR, true>(P, sp, x, tl, lut, i0, i1, first, a, ke, lwv, lkp, lwp, lnp, flags);
         else
-            step_atoms<T, VIR, false>(P, sp, x, tl, lut, i0, i1, a, ke, lwv, lkp, lwp, lnp, flags);
+            step_atoms<T, VIR, false>(P, sp, x, tl, lut, i0, i1, first, a, ke, lwv, lkp, lwp, lnp, flags);
     }
     // vapour pairs were met from both atoms: half of each sum (and each
     // pair's virial is shared equally by its two molecules)
