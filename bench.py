@@ -383,61 +383,129 @@ def cpu_baseline(desc, sample_atoms, extra=(), extra_atoms=512, seed=0):
     return base, refs
 
 
-def serve_leg(n_requests, budget_gb, chunk):
+def _request_payload(spec):
+    from paper_1812_07993_amd import synth
+
+    return synth.request_system(spec)
+
+
+def serve_leg(n_requests, budget_gb, chunk, workers=2):
     """Served trace: Poisson arrivals at 200 requests/s, vapour N log-uniform in
     [2k, 500k], pore from {cylinder, slit, cone, ink-bottle}, 1k-20k steps,
     mixed or FP64 with probability 1/2; one batch per precision, each bounded
-    by the device budget."""
+    by the device budget.  The requests' initial states (the clients' data)
+    are generated before the trace starts, by host worker threads (the
+    placement runs in C through ctypes, which releases the GIL); creating
+    each system on the device (upload, first forces) is part of its latency
+    and runs on `workers` threads beside the tick loop."""
+    from concurrent.futures import ThreadPoolExecutor
+
     from paper_1812_07993_amd import serve, synth
 
     t0 = time.perf_counter()
     specs = synth.request_trace(n_requests)
-    reqs = [serve.Request(s["index"], s["arrival"], s["precision"], s["steps"], s["n"],
-                          synth.request_system(s)) for s in specs]
-    log("serve: %d requests generated in %.1f s (%.2e atom-steps offered)"
-        % (len(reqs), time.perf_counter() - t0, sum(r.n * r.steps for r in reqs)))
+    nproc = max(1, min(16, (os.cpu_count() or 1)))
+    with ThreadPoolExecutor(max_workers=nproc) as ex:
+        payloads = list(ex.map(_request_payload, specs))
+    reqs = [serve.Request(s["index"], s["arrival"], s["precision"], s["steps"], s["n"], p)
+            for s, p in zip(specs, payloads)]
+    log("serve: %d requests generated in %.1f s on %d threads (%.2e atom-steps offered)"
+        % (len(reqs), time.perf_counter() - t0, nproc, sum(r.n * r.steps for r in reqs)))
     be = serve.PoremdBackend(hbm_budget=int(budget_gb * 2 ** 30), max_slots=256)
-    res = serve.Server(be, chunk_steps=chunk).run(reqs)
+    res = serve.Server(be, chunk_steps=chunk, create_workers=workers).run(reqs)
     s = serve.summarize(res)
     span_arrivals = max(r.arrival for r in reqs) - min(r.arrival for r in reqs)
     s["offered_req_per_s"] = (len(reqs) - 1) / span_arrivals if span_arrivals > 0 else None
+    s["offered_atom_steps"] = float(sum(r.n * r.steps for r in reqs))
     s["budget_gb_per_precision"] = budget_gb
+    s["chunk_steps"] = chunk
+    s["create_workers"] = workers
+    by = {}
+    for p in ("mixed", "fp64"):
+        rs = [r for r in res if r.precision == p]
+        if rs:
+            lat = np.array([r.latency for r in rs])
+            by[p] = {"requests": len(rs), "p50_s": float(np.percentile(lat, 50)),
+                     "p99_s": float(np.percentile(lat, 99))}
+    s["by_precision"] = by
     log("serve: p50 %.3f s, p99 %.3f s, %.3e atom-steps/s over %.2f s"
         % (s["p50_s"], s["p99_s"], s["atom_steps_per_s"], s["makespan_s"]))
     return s
 
 
-def batch_leg(poremd, count, steps, alone_steps, tuning_kw):
+def batch_autotune(poremd, descs, trial_steps, stream):
+    """Tuning of the replica batch on the batch itself: the library's
+    autotuner ranks (skin, rebuild period) on the median replica, then the
+    three best pairs times two workgroup shapes are each timed on all the
+    replicas resident in one batch (trial_steps steps, wall clock), and the
+    fastest is kept.  The systems are created once at the smallest skin (the
+    largest cell grid) and retuned per candidate."""
+    import torch
+
+    med = sorted(descs, key=lambda d: d.n)[len(descs) // 2]
+    params, pore = poremd.params_of(med, "mixed")
+    grid = poremd.pmd_autotune_grid(params, med.n)
+    best, us = poremd.pmd_autotune(params, pore, med.x, med.v, grid, trial_steps)
+    pairs = []
+    for i in np.argsort(us):
+        sr = (float(grid[i].skin), int(grid[i].rebin_every))
+        if np.isfinite(us[i]) and sr not in pairs:
+            pairs.append(sr)
+        if len(pairs) == 3:
+            break
+    cands = [dict(skin=sk, rebin_every=rb, block=bl, brick_atoms=ba)
+             for sk, rb in pairs for bl, ba in ((256, 0), (512, 460))]
+    smin = min(c["skin"] for c in cands)
+    hs = [poremd.System.from_desc(d, tuning=poremd.make_tuning(skin=smin), stream=stream.cuda_stream)
+          for d in descs]
+    times = []
+    for c in cands:
+        for h in hs:
+            h.set_tuning(poremd.make_tuning(**c))
+        b = poremd.pmd_batch_create(0, len(hs), stream.cuda_stream)
+        slots = [poremd.pmd_batch_admit(b, h.h, trial_steps) for h in hs]
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        poremd.pmd_batch_advance(b, trial_steps)
+        while len(poremd.pmd_batch_poll(b)) < len(hs):
+            poremd.pmd_batch_advance(b, max(trial_steps // 10, 1))
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - w0) / trial_steps * 1e6)
+        for sl in slots:
+            poremd.pmd_batch_release(b, sl)
+        poremd.pmd_batch_destroy(b)
+    for h in hs:
+        h.close()
+    k = int(np.argmin(times))
+    log("batch autotune: %s" % ", ".join("(%.2f, %d, %d, %d) %.1f us/step" % (
+        c["skin"], c["rebin_every"], c["block"], c["brick_atoms"], t) for c, t in zip(cands, times)))
+    return cands[k], [dict(c, us_per_step=t) for c, t in zip(cands, times)]
+
+
+def batch_leg(poremd, count, steps, autotune_steps):
     """Replica batch: `count` independent systems (vapour N log-uniform in
-    [1k, 64k], pore from {cylinder, slit, cone}, box at density 0.1) resident
-    in one batch and advanced together, against the same systems stepped one
-    at a time.  Both in vapour atom-steps per second, mixed precision."""
+    [1k, 64k], pore from {cylinder, slit, cone}, box at density 0.1),
+    mixed precision, tuned on the batch itself, resident in one batch and
+    advanced together for `steps` steps each; against the same systems
+    stepped one at a time (one after another on one stream, the same steps,
+    one wait at the end).  Energies are recorded every 10 steps, and every
+    system's drift (trend over steps 100..1100 and largest deviation) is
+    reported."""
     import torch
 
     from paper_1812_07993_amd import synth
 
     t0 = time.perf_counter()
     descs = [synth.replica(sp, "mixed", steps) for sp in synth.replica_specs(count)]
-    tun = poremd.make_tuning(**{k: v for k, v in tuning_kw.items() if k != "brick_atoms"})
-    stream = torch.cuda.Stream()
-    handles = [poremd.System.from_desc(d, tuning=tun, stream=stream.cuda_stream) for d in descs]
     natoms = sum(d.n for d in descs)
-    log("batch: %d systems, %d vapour atoms, created in %.1f s"
-        % (count, natoms, time.perf_counter() - t0))
-    # one at a time (each system on its own, the same stream)
-    for h in handles:
-        h.step(alone_steps // 4)
-        h.sync()
-    torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    for h in handles:
-        h.step(alone_steps)
-        h.sync()
-    torch.cuda.synchronize()
-    alone = natoms * alone_steps / (time.perf_counter() - w0)
+    stream = torch.cuda.Stream()
+    log("batch: %d systems, %d vapour atoms, generated in %.1f s" % (count, natoms, time.perf_counter() - t0))
+    tkw, cand_times = batch_autotune(poremd, descs, autotune_steps, stream)
+    tun = poremd.make_tuning(energy_every=10, **tkw)
     # all in one batch: every system runs exactly `steps` steps; the timed
     # region spans the first advance to the last system finishing (one graph
     # capture and the replays re-queued after early rebuilds included)
+    handles = [poremd.System.from_desc(d, tuning=tun, stream=stream.cuda_stream) for d in descs]
     b = poremd.pmd_batch_create(0, count, stream.cuda_stream)
     slots = [poremd.pmd_batch_admit(b, h.h, steps) for h in handles]
     torch.cuda.synchronize()
@@ -450,16 +518,42 @@ def batch_leg(poremd, count, steps, alone_steps, tuning_kw):
     batched = natoms * steps / wall
     for sl in slots:
         poremd.pmd_batch_release(b, sl)
-    E = [h.energies() for h in handles]
     poremd.pmd_batch_destroy(b)
+    trends, maxes, bad = [], [], 0
     for h in handles:
+        E = h.energy_history()
+        burn = int(np.searchsorted(E["step"], DRIFT_BURN))
+        end = int(np.searchsorted(E["step"], DRIFT_BURN + DRIFT_WINDOW, side="right"))
+        tr, mx = energy_drift(E["etotal"][:end], burn)
+        bad += not np.all(np.isfinite(E["etotal"]))
+        trends.append(tr)
+        maxes.append(mx)
         h.close()
-    bad = sum(not np.isfinite(e["etotal"]) for e in E)
-    log("batch: %.3e atom-steps/s batched (%d steps, %.3f s), %.3e one at a time"
-        % (batched, steps, wall, alone))
+    # one at a time: the same systems from the same start, each stepped alone
+    # in turn on one stream, the host waiting once at the end
+    alone_h = [poremd.System.from_desc(d, tuning=tun, stream=stream.cuda_stream) for d in descs]
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for h in alone_h:
+        h.step(steps)
+    for h in alone_h:
+        h.sync()
+    torch.cuda.synchronize()
+    alone = natoms * steps / (time.perf_counter() - w0)
+    for h in alone_h:
+        h.close()
+    trends = np.array(trends)
+    maxes = np.array(maxes)
+    log("batch: %.3e atom-steps/s batched (%d steps, %.3f s), %.3e one at a time; drift trend "
+        "median %.2e max %.2e" % (batched, steps, wall, alone, np.median(trends), trends.max()))
     return {"systems": count, "vapour_atoms": natoms, "steps": steps, "value": batched,
-            "unit": "atom-steps/s", "one_at_a_time": alone, "one_at_a_time_steps": alone_steps,
-            "speedup": batched / alone, "nonfinite_systems": bad}
+            "unit": "atom-steps/s", "tuning": tkw, "autotune": cand_times,
+            "one_at_a_time": alone, "one_at_a_time_steps": steps, "speedup": batched / alone,
+            "nonfinite_systems": bad,
+            "drift_trend_median": float(np.median(trends)), "drift_trend_max": float(trends.max()),
+            "drift_max_median": float(np.median(maxes)), "drift_max_max": float(maxes.max()),
+            "drift_window": "steps %d..%d of the batched run, energies every 10 steps"
+                            % (DRIFT_BURN, DRIFT_BURN + DRIFT_WINDOW)}
 
 
 def pore_sweep_leg(poremd, kinds, steps, autotune_steps, tuning_kw, precisions=("mixed", "fp64"),
@@ -526,12 +620,12 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=65536)
-    ap.add_argument("--serve-requests", type=int, default=24,
+    ap.add_argument("--serve-requests", type=int, default=256,
                     help="requests of the served trace (0 = skip the serving leg)")
     ap.add_argument("--serve-budget-gb", type=float, default=2.0)
     ap.add_argument("--batch-systems", type=int, default=256,
                     help="replica systems of the batched leg (0 = skip it)")
-    ap.add_argument("--batch-steps", type=int, default=1000)
+    ap.add_argument("--batch-steps", type=int, default=5000)
     ap.add_argument("--sweep", default="cylinder,cone,inkbottle",
                     help="pores of the 4M-atom leg, comma separated (cylinder,cone,inkbottle); "
                          "'none' skips it")
@@ -689,8 +783,10 @@ def main():
             0 if (args.skin or args.rebin_every) else min(args.autotune_steps, 50), tkw,
             precisions=("mixed",) if args.no_fp64 else ("mixed", "fp64"))
     if args.batch_systems > 0:
-        out["batched"] = batch_leg(poremd, args.batch_systems, args.batch_steps, 40,
-                                   tuned["mixed"])
+        out["batched"] = batch_leg(poremd, args.batch_systems, args.batch_steps,
+                                   min(args.autotune_steps, 200) if args.autotune_steps > 0 else 200)
+        if "fp64" in out:
+            out["batched"]["over_single_system_fp64"] = out["batched"]["value"] / out["fp64"]["value"]
     if args.serve_requests > 0:
         out["serve"] = serve_leg(args.serve_requests, args.serve_budget_gb, args.serve_chunk)
         out["served_p50_s"] = out["serve"]["p50_s"]

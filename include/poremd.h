@@ -335,7 +335,12 @@ int pmd_batch_admit(pmd_batch *b, pmd_system *sys, int64_t nsteps, int *slot);
 int pmd_batch_advance(pmd_batch *b, int64_t chunk_steps);
 /* Slots whose systems have finished their steps (waits for queued work). */
 int pmd_batch_poll(pmd_batch *b, int *done_slots, int cap, int *n_done);
-/* Non-blocking variant: reports only what is known complete. */
+/* Non-blocking variant: reports the systems that had finished by the end
+ * of the newest chunk of pmd_batch_advance that the device has completed
+ * (each chunk leaves a copy of the systems' states in pinned host memory,
+ * with an event), while later chunks may still run; it waits for nothing.
+ * Where that state shows a system needing the host (a list or tile to
+ * grow), it does what pmd_batch_poll does. */
 int pmd_batch_poll_async(pmd_batch *b, int *done_slots, int cap, int *n_done);
 /* Take a system out of the batch; its handle becomes usable again. */
 int pmd_batch_release(pmd_batch *b, int slot, pmd_system **sys_out);

@@ -773,6 +773,19 @@ struct pmd_system {
     Grid grid{};
 };
 
+// A copy of the per-system state taken after a chunk of steps: queued on
+// the batch's stream behind the chunk, into pinned host memory, with an
+// event, so that the host can learn which systems finished while later
+// chunks run.
+struct StateSnap {
+    hipEvent_t ev = nullptr;
+    SysState* host = nullptr;  // [max_slots], pinned
+    long long seq = -1;        // issue number; -1 = unused
+    bool done = false;         // its event has completed
+};
+
+constexpr int kSnaps = 4;
+
 struct pmd_batch {
     std::unique_ptr<Pool> pool;
     size_t budget = 0;
@@ -783,6 +796,9 @@ struct pmd_batch {
     int R = 10;
     pmd_tuning tuning{};
     bool configured = false;
+    StateSnap snap[kSnaps];
+    long long snap_seq = 0;             // next issue number
+    std::vector<long long> admit_seq;   // by slot: first snapshot that can see its system
 };
 
 namespace {
@@ -1973,7 +1989,12 @@ int pmd_batch_create(size_t hbm_budget, int max_slots, void* hip_stream, pmd_bat
         b->max_slots = max_slots;
         b->resident.assign(max_slots, nullptr);
         b->steps_wanted.assign(max_slots, 0);
+        b->admit_seq.assign(max_slots, 0);
         b->user_stream = (hipStream_t)hip_stream;
+        for (auto& sn : b->snap) {
+            HIPCHK(hipEventCreateWithFlags(&sn.ev, hipEventDisableTiming));
+            HIPCHK(hipHostMalloc((void**)&sn.host, sizeof(SysState) * (size_t)max_slots));
+        }
         *out = b.release();
         return PMD_OK;
     } catch (...) {
@@ -2055,6 +2076,7 @@ int pmd_batch_admit(pmd_batch* b, pmd_system* sys, int64_t nsteps, int* slot)
         CHK(pool_layout(p));
         b->resident[free_slot] = sys;
         b->steps_wanted[free_slot] = nsteps;
+        b->admit_seq[free_slot] = b->snap_seq;
         sys->own.reset();
         sys->pool = &p;
         sys->slot = free_slot;
@@ -2075,10 +2097,53 @@ int pmd_batch_advance(pmd_batch* b, int64_t chunk_steps)
         if (!b) return fail(PMD_EINVAL, "NULL batch");
         if (!b->configured || chunk_steps <= 0) return PMD_OK;
         const int R = b->R;
-        return pool_enqueue(*b->pool, R, b->tuning.use_graph, (chunk_steps + R - 1) / R);
+        CHK(pool_enqueue(*b->pool, R, b->tuning.use_graph, (chunk_steps + R - 1) / R));
+        // the state after this chunk, for pmd_batch_poll_async; the ring's
+        // oldest entry is reused (waiting for it only if four chunks are
+        // still queued ahead of this one)
+        StateSnap& sn = b->snap[b->snap_seq % kSnaps];
+        if (sn.seq >= 0 && !sn.done) HIPCHK(hipEventSynchronize(sn.ev));
+        Pool& p = *b->pool;
+        HIPCHK(hipMemcpyAsync(sn.host, p.d_st, sizeof(SysState) * (size_t)p.nslots, hipMemcpyDeviceToHost,
+                              p.stream));
+        HIPCHK(hipEventRecord(sn.ev, p.stream));
+        sn.seq = b->snap_seq++;
+        sn.done = false;
+        return PMD_OK;
     } catch (...) {
         return fail(PMD_EHIP, "unexpected exception");
     }
+}
+
+// Non-blocking poll: the newest state snapshot whose chunk has completed
+// names the systems that finished (a snapshot taken before a system was
+// admitted says nothing about it).  A snapshot that shows a system needing
+// the host (list overflow, tile overflow, a stall) hands over to the
+// blocking poll, which fixes it.
+static int batch_poll_snap(pmd_batch* b, int* done, int cap, int* n_done, bool* need_host)
+{
+    *need_host = false;
+    const StateSnap* best = nullptr;
+    for (auto& sn : b->snap) {
+        if (sn.seq < 0) continue;
+        if (!sn.done) {
+            const hipError_t q = hipEventQuery(sn.ev);
+            if (q == hipErrorNotReady) continue;
+            HIPCHK(q);
+            sn.done = true;
+        }
+        if (!best || sn.seq > best->seq) best = &sn;
+    }
+    if (!best) return PMD_OK;
+    const Pool& p = *b->pool;
+    for (int s = 0; s < p.nslots; ++s) {
+        if (!b->resident[s] || best->seq < b->admit_seq[s]) continue;
+        const SysState& st = best->host[s];
+        if (st.status & (ST_TILE | ST_OVERFLOW | ST_STALL)) *need_host = true;
+        const bool finished = st.remaining <= 0 || (st.status & ST_NONFINITE);
+        if (finished && *n_done < cap) done[(*n_done)++] = s;
+    }
+    return PMD_OK;
 }
 
 static int batch_poll_impl(pmd_batch* b, int* done, int cap, int* n_done, bool wait)
@@ -2088,9 +2153,10 @@ static int batch_poll_impl(pmd_batch* b, int* done, int cap, int* n_done, bool w
     if (!b->configured) return PMD_OK;
     Pool& p = *b->pool;
     if (!wait) {
-        hipError_t q = hipStreamQuery(p.stream);
-        if (q == hipErrorNotReady) return PMD_OK;
-        HIPCHK(q);
+        bool need_host = false;
+        CHK(batch_poll_snap(b, done, cap, n_done, &need_host));
+        if (!need_host) return PMD_OK;
+        *n_done = 0;
     }
     std::vector<SysState> st((size_t)p.nslots);
     HIPCHK(hipMemcpyAsync(st.data(), p.d_st, sizeof(SysState) * st.size(), hipMemcpyDeviceToHost, p.stream));
@@ -2177,6 +2243,10 @@ int pmd_batch_destroy(pmd_batch* b)
     try {
         for (int s = 0; s < b->max_slots; ++s)
             if (b->resident[s]) CHK(pmd_batch_release(b, s, nullptr));
+        for (auto& sn : b->snap) {
+            if (sn.ev) (void)hipEventDestroy(sn.ev);
+            if (sn.host) (void)hipHostFree(sn.host);
+        }
         delete b;
         return PMD_OK;
     } catch (...) {

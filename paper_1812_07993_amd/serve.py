@@ -2,17 +2,15 @@
 
 Requests (a system and a number of steps) arrive over time.  The server keeps
 one batch per precision resident on the device, each on its own HIP stream
-so their work overlaps; every tick it
-
-  1. admits arrived requests, oldest first, as slots and device memory free
-     up (admission by footprint: the batch's budget bounds its bytes; a
-     request that does not fit waits, later ones that fit may pass it);
-  2. advances every batch by a chunk of steps (asynchronous);
-  3. polls for finished systems, reads them back and frees their slots.
+so their work overlaps, creates systems for arrived requests (on worker
+threads if asked: upload and first force evaluation off the tick path),
+admits them by device footprint as slots and memory free up, keeps every
+busy batch a chunk or two ahead, and reads finished systems back as soon as
+a completed chunk shows them done, without waiting for queued work.
 
 Latency of a request = time its results were read back - its arrival time.
 All simulation work runs in the library's kernels; this module only
-schedules.
+schedules (the Server class documents the loop).
 """
 from __future__ import annotations
 
@@ -52,7 +50,9 @@ class Result:
 
 
 class PoremdBackend:
-    """The library through its C interface (one batch per precision)."""
+    """The library through its C interface (one batch per precision, each on
+    its own HIP stream).  Systems are created on library-owned streams, so a
+    worker thread can create one while the batches run."""
 
     def __init__(self, hbm_budget: int = 0, max_slots: int = 256, tuning=None,
                  keep_positions: bool = False):
@@ -60,6 +60,7 @@ class PoremdBackend:
 
         from . import poremd
 
+        self.torch = torch
         self.pm = poremd
         self.pm.load()
         self.budget = hbm_budget
@@ -67,10 +68,13 @@ class PoremdBackend:
         self.tuning = tuning
         self.keep_positions = keep_positions
         self._streams = {p: torch.cuda.Stream() for p in ("mixed", "fp64")}
+        self._events: Dict[int, deque] = {}
 
     def new_batch(self, precision: str):
-        return self.pm.pmd_batch_create(self.budget, self.max_slots,
-                                        self._streams[precision].cuda_stream)
+        b = self.pm.pmd_batch_create(self.budget, self.max_slots,
+                                     self._streams[precision].cuda_stream)
+        self._events[id(b)] = (self._streams[precision], deque())
+        return b
 
     def footprint(self, req: Request) -> int:
         params, pore = self.pm.params_of(req.payload, req.precision)
@@ -85,9 +89,20 @@ class PoremdBackend:
 
     def advance(self, batch, chunk: int) -> None:
         self.pm.pmd_batch_advance(batch, chunk)
+        stream, evs = self._events[id(batch)]
+        ev = self.torch.cuda.Event()
+        ev.record(stream)
+        evs.append(ev)
 
-    def poll(self, batch) -> List[int]:
-        return self.pm.pmd_batch_poll(batch)
+    def queued(self, batch) -> int:
+        """Chunks of this batch the device has not finished yet."""
+        _, evs = self._events[id(batch)]
+        while evs and evs[0].query():
+            evs.popleft()
+        return len(evs)
+
+    def poll(self, batch, wait: bool = True) -> List[int]:
+        return self.pm.pmd_batch_poll(batch) if wait else self.pm.pmd_batch_poll_async(batch)
 
     def release(self, batch, slot: int, handle):
         self.pm.pmd_batch_release(batch, slot)
@@ -104,17 +119,38 @@ class PoremdBackend:
         handle.close()
 
     def destroy_batch(self, batch) -> None:
+        self._events.pop(id(batch), None)
         self.pm.pmd_batch_destroy(batch)
 
 
 class Server:
+    """Continuous batching.  Every tick it
+
+      1. starts creating arrived requests, oldest first, whose device
+         footprint fits the precision's budget beside the systems already
+         resident, ready or being created (a request that does not fit
+         waits; later ones that fit may pass it); with create_workers > 0
+         the creation (upload and first force evaluation) runs on worker
+         threads, off the tick path;
+      2. admits created systems into their precision's batch;
+      3. keeps up to max_queued chunks of chunk_steps steps queued on each
+         batch that holds systems, so the device never waits for the host;
+      4. polls each batch without waiting (the systems that had finished by
+         the end of the newest completed chunk), reads the finished systems
+         back and frees their slots.
+    """
+
     def __init__(self, backend, chunk_steps: int = 250,
                  clock: Callable[[], float] = time.perf_counter,
-                 sleep: Callable[[float], None] = time.sleep):
+                 sleep: Callable[[float], None] = time.sleep,
+                 create_workers: int = 0, max_queued: int = 2, idle_sleep: float = 0.0005):
         self.backend = backend
         self.chunk = chunk_steps
         self.clock = clock
         self.sleep = sleep
+        self.workers = create_workers
+        self.max_queued = max_queued
+        self.idle_sleep = idle_sleep
         self.batches: Dict[str, Any] = {}
         self.log: List[str] = []
 
@@ -124,64 +160,126 @@ class Server:
         return self.batches[precision]
 
     def run(self, requests: List[Request]) -> List[Result]:
+        from concurrent.futures import ThreadPoolExecutor
+
+        be = self.backend
+        pool = ThreadPoolExecutor(max_workers=self.workers) if self.workers > 0 else None
         pending = deque(sorted(requests, key=lambda r: r.arrival))
-        waiting: List[Request] = []
+        arrived: List[Request] = []
+        creating: List[tuple] = []          # (req, future)
+        ready: deque = deque()              # (req, handle or exception)
         resident: Dict[tuple, tuple] = {}   # (precision, slot) -> (req, handle, admitted)
+        held = {}                           # precision -> [bytes, systems] not yet released
         results: List[Result] = []
+        budget = getattr(be, "budget", 0)
+        fp_cache: Dict[int, int] = {}
+
+        def fp(req):
+            if req.index not in fp_cache:
+                fp_cache[req.index] = be.footprint(req)
+            return fp_cache[req.index]
+
         t0 = self.clock()
-        while pending or waiting or resident:
-            now = self.clock() - t0
-            while pending and pending[0].arrival <= now:
-                waiting.append(pending.popleft())
-            # 1. admission, oldest first; a cheap footprint check first so no
-            #    system is created on the device only to be turned away
-            still = []
-            for req in waiting:
-                b = self._batch(req.precision)
-                fp = self.backend.footprint(req)
-                used = sum(self.backend.footprint(r) for (p, _), (r, _, _) in resident.items()
-                           if p == req.precision)
-                count = sum(1 for (p, _) in resident if p == req.precision)
-                budget = getattr(self.backend, "budget", 0)
-                if count >= self.backend.max_slots or (budget and used + fp > budget):
-                    still.append(req)
+        try:
+            while pending or arrived or creating or ready or resident:
+                now = self.clock() - t0
+                while pending and pending[0].arrival <= now:
+                    arrived.append(pending.popleft())
+                progress = False
+                # 1. creations, oldest first, within the budget and the slots
+                still = []
+                for req in arrived:
+                    used, count = held.get(req.precision, (0, 0))
+                    f = fp(req)
+                    if count >= be.max_slots or (budget and used + f > budget):
+                        if count == 0 and budget and f > budget:
+                            raise RuntimeError("request %d cannot fit an empty batch" % req.index)
+                        still.append(req)
+                        continue
+                    held[req.precision] = (used + f, count + 1)
+                    if pool is not None:
+                        creating.append((req, pool.submit(be.create, req)))
+                    else:
+                        try:
+                            ready.append((req, be.create(req)))
+                        except Exception as e:  # a failing request must not stop the others
+                            ready.append((req, e))
+                    progress = True
+                arrived = still
+                # 2. finished creations, then admission in arrival order
+                keep = []
+                for req, fut in creating:
+                    if fut.done():
+                        try:
+                            ready.append((req, fut.result()))
+                        except Exception as e:
+                            ready.append((req, e))
+                        progress = True
+                    else:
+                        keep.append((req, fut))
+                creating = keep
+                unadmitted = deque()
+                while ready:
+                    req, h = ready.popleft()
+                    if isinstance(h, Exception):
+                        t = self.clock() - t0
+                        results.append(Result(req.index, req.arrival, t, t, req.steps, req.n,
+                                              req.precision, "error", {"error": str(h)}))
+                        used, count = held[req.precision]
+                        held[req.precision] = (used - fp(req), count - 1)
+                        continue
+                    slot = be.admit(self._batch(req.precision), h, req.steps)
+                    if slot is None:
+                        unadmitted.append((req, h))
+                        continue
+                    resident[(req.precision, slot)] = (req, h, self.clock() - t0)
+                    progress = True
+                ready = unadmitted
+                if not resident:
+                    if not (creating or ready):
+                        if pending:
+                            self.sleep(max(0.0, pending[0].arrival - (self.clock() - t0)))
+                            continue
+                        if arrived:
+                            raise RuntimeError("request %d cannot be admitted" % arrived[0].index)
+                        break
+                    if not progress:
+                        self.sleep(self.idle_sleep)
                     continue
-                h = self.backend.create(req)
-                slot = self.backend.admit(b, h, req.steps)
-                if slot is None:
-                    self.backend.destroy(h)
-                    still.append(req)
-                    continue
-                resident[(req.precision, slot)] = (req, h, self.clock() - t0)
-            waiting = still
-            if not resident:
-                if pending:
-                    self.sleep(max(0.0, pending[0].arrival - (self.clock() - t0)))
-                    continue
-                if waiting:
-                    raise RuntimeError("request %d cannot fit an empty batch" % waiting[0].index)
-                break
-            # 2. advance every batch holding systems (their streams overlap)
-            active = sorted({p for (p, _) in resident})
-            for p in active:
-                self.backend.advance(self.batches[p], self.chunk)
-            # 3. collect finished systems
-            for p in active:
-                for slot in self.backend.poll(self.batches[p]):
-                    req, h, t_adm = resident.pop((p, slot))
-                    self.backend.release(self.batches[p], slot, h)
-                    try:
-                        out = self.backend.finish(h)
-                        status = "ok"
-                    except Exception as e:  # a failing request must not stop the others
-                        out, status = {"error": str(e)}, "error"
-                    t_fin = self.clock() - t0
-                    results.append(Result(req.index, req.arrival, t_adm, t_fin, req.steps,
-                                          req.n, p, status, out))
-                    self.backend.destroy(h)
-        for b in self.batches.values():
-            self.backend.destroy_batch(b)
-        self.batches = {}
+                # 3. keep the batches busy
+                active = sorted({p for (p, _) in resident})
+                for p in active:
+                    b = self.batches[p]
+                    if be.queued(b) < self.max_queued:
+                        be.advance(b, self.chunk)
+                        progress = True
+                # 4. finished systems (no wait)
+                for p in active:
+                    for slot in be.poll(self.batches[p], wait=False):
+                        if (p, slot) not in resident:
+                            continue
+                        req, h, t_adm = resident.pop((p, slot))
+                        be.release(self.batches[p], slot, h)
+                        try:
+                            out = be.finish(h)
+                            status = "ok"
+                        except Exception as e:  # a failing request must not stop the others
+                            out, status = {"error": str(e)}, "error"
+                        t_fin = self.clock() - t0
+                        results.append(Result(req.index, req.arrival, t_adm, t_fin, req.steps,
+                                              req.n, p, status, out))
+                        be.destroy(h)
+                        used, count = held[p]
+                        held[p] = (used - fp(req), count - 1)
+                        progress = True
+                if not progress:
+                    self.sleep(self.idle_sleep)
+        finally:
+            if pool is not None:
+                pool.shutdown(wait=True)
+            for b in self.batches.values():
+                be.destroy_batch(b)
+            self.batches = {}
         return sorted(results, key=lambda r: r.index)
 
 
@@ -245,7 +343,10 @@ class FakeBackend:
         for h in live:
             h["done"] = min(h["req"].steps, h["done"] + chunk)
 
-    def poll(self, b):
+    def queued(self, b):
+        return 0  # a chunk completes in virtual time when it is advanced
+
+    def poll(self, b, wait=True):
         return [s for s, h in b["slots"].items() if h["done"] >= h["req"].steps]
 
     def release(self, b, slot, h):

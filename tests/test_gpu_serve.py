@@ -53,7 +53,7 @@ def test_served_mix_with_a_large_request_matches_alone():
         d = synth.request_system(sp, seed=9)
         reqs.append(serve.Request(sp["index"], sp["arrival"], sp["precision"], sp["steps"], sp["n"], d))
     be = serve.PoremdBackend(hbm_budget=0, max_slots=4, keep_positions=True)
-    res = serve.Server(be, chunk_steps=25).run(reqs)
+    res = serve.Server(be, chunk_steps=25, create_workers=2).run(reqs)
     assert [r.status for r in res] == ["ok"] * len(reqs)
     for req, r in zip(reqs, res):
         s = poremd.System.from_desc(req.payload, precision=req.precision)

@@ -65,3 +65,14 @@ def test_request_larger_than_budget_is_reported():
     srv = Server(be, chunk_steps=10, clock=be.clock, sleep=be.sleep)
     with pytest.raises(RuntimeError):
         srv.run(reqs([(0.0, "mixed", 10, 5)]))
+
+
+def test_creation_on_worker_threads():
+    """With creation on worker threads the same requests all complete, in the
+    same admission order constraints."""
+    be = FakeBackend(budget=100_000, max_slots=4, cost_per_atom_step=1e-6)
+    srv = Server(be, chunk_steps=10, clock=be.clock, sleep=be.sleep, create_workers=2)
+    r = srv.run(reqs([(0.0, "mixed", 100, 5), (0.0, "fp64", 50, 5), (0.01, "mixed", 30, 5)]))
+    assert [x.status for x in r] == ["ok"] * 3
+    assert all(x.output["steps"] == x.steps for x in r)
+    assert all(x.finished >= x.admitted >= x.arrival for x in r)
