@@ -438,8 +438,8 @@ def batch_autotune(poremd, descs, trial_steps, stream):
     autotuner ranks (skin, rebuild period) on the median replica, then the
     three best pairs times two workgroup shapes are each timed on all the
     replicas resident in one batch (trial_steps steps, wall clock), and the
-    fastest is kept.  The systems are created once at the smallest skin (the
-    largest cell grid) and retuned per candidate."""
+    fastest is kept.  The systems are created once per workgroup shape at the
+    smallest skin (the largest cell grid) and retuned per (skin, period)."""
     import torch
 
     med = sorted(descs, key=lambda d: d.n)[len(descs) // 2]
@@ -453,29 +453,34 @@ def batch_autotune(poremd, descs, trial_steps, stream):
             pairs.append(sr)
         if len(pairs) == 3:
             break
-    cands = [dict(skin=sk, rebin_every=rb, block=bl, brick_atoms=ba)
-             for sk, rb in pairs for bl, ba in ((256, 0), (512, 460))]
-    smin = min(c["skin"] for c in cands)
-    hs = [poremd.System.from_desc(d, tuning=poremd.make_tuning(skin=smin), stream=stream.cuda_stream)
-          for d in descs]
-    times = []
-    for c in cands:
+    smin = min(sk for sk, _ in pairs)
+    cands, times = [], []
+    for bl, ba in ((256, 0), (512, 460)):
+        # the replicas are created once per workgroup shape (a shape sizes the
+        # cell tables), at the smallest skin, and retuned per (skin, period)
+        hs = [poremd.System.from_desc(d, tuning=poremd.make_tuning(skin=smin, block=bl, brick_atoms=ba),
+                                      stream=stream.cuda_stream) for d in descs]
+        # ascending skin: a system released from a batch keeps cell tables
+        # sized for its last grid, which fit every coarser one
+        for sk, rb in sorted(pairs):
+            c = dict(skin=sk, rebin_every=rb, block=bl, brick_atoms=ba)
+            for h in hs:
+                h.set_tuning(poremd.make_tuning(**c))
+            b = poremd.pmd_batch_create(0, len(hs), stream.cuda_stream)
+            slots = [poremd.pmd_batch_admit(b, h.h, trial_steps) for h in hs]
+            torch.cuda.synchronize()
+            w0 = time.perf_counter()
+            poremd.pmd_batch_advance(b, trial_steps)
+            while len(poremd.pmd_batch_poll(b)) < len(hs):
+                poremd.pmd_batch_advance(b, max(trial_steps // 10, 1))
+            torch.cuda.synchronize()
+            cands.append(c)
+            times.append((time.perf_counter() - w0) / trial_steps * 1e6)
+            for sl in slots:
+                poremd.pmd_batch_release(b, sl)
+            poremd.pmd_batch_destroy(b)
         for h in hs:
-            h.set_tuning(poremd.make_tuning(**c))
-        b = poremd.pmd_batch_create(0, len(hs), stream.cuda_stream)
-        slots = [poremd.pmd_batch_admit(b, h.h, trial_steps) for h in hs]
-        torch.cuda.synchronize()
-        w0 = time.perf_counter()
-        poremd.pmd_batch_advance(b, trial_steps)
-        while len(poremd.pmd_batch_poll(b)) < len(hs):
-            poremd.pmd_batch_advance(b, max(trial_steps // 10, 1))
-        torch.cuda.synchronize()
-        times.append((time.perf_counter() - w0) / trial_steps * 1e6)
-        for sl in slots:
-            poremd.pmd_batch_release(b, sl)
-        poremd.pmd_batch_destroy(b)
-    for h in hs:
-        h.close()
+            h.close()
     k = int(np.argmin(times))
     log("batch autotune: %s" % ", ".join("(%.2f, %d, %d, %d) %.1f us/step" % (
         c["skin"], c["rebin_every"], c["block"], c["brick_atoms"], t) for c, t in zip(cands, times)))

@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -26,6 +27,14 @@ using namespace pmd;
 namespace {
 
 thread_local std::string g_err = "no error";
+
+// One lock for the calls that capture HIP graphs, allocate or free device
+// memory, or copy synchronously: HIP's thread-local capture mode does not
+// keep such calls on other threads (a server creating systems on worker
+// threads while its tick thread re-captures a batch's graph) from breaking
+// the capture.  Recursive, because some of these calls make others.
+std::recursive_mutex g_gpu_mu;
+#define GPU_LOCK std::lock_guard<std::recursive_mutex> gpu_lock_(g_gpu_mu)
 
 int fail(int code, const char* fmt, ...)
 {
@@ -683,6 +692,7 @@ void fill_sys_params(SysParams& sp, const pmd_params& p, const Grid& g, const pm
 // Capture `reps` replays of [rebuild, R steps] into one graph.
 int pool_capture(Pool& p, int R, int reps)
 {
+    GPU_LOCK;
     if (p.gexec) {
         HIPCHK(hipGraphExecDestroy(p.gexec));
         p.gexec = nullptr;
@@ -1348,6 +1358,7 @@ int pmd_create_system(const pmd_params* params, const pmd_pore* pore, int64_t n_
                       pmd_system** out)
 {
     try {
+        GPU_LOCK;
         if (!out) return fail(PMD_EINVAL, "out must not be NULL");
         *out = nullptr;
         CHK(check_params(params, pore));
@@ -1604,6 +1615,7 @@ int pmd_get_positions_device(pmd_system* sys, double* dev_out, int64_t n, void* 
 int pmd_set_tuning(pmd_system* sys, const pmd_tuning* tuning)
 {
     try {
+        GPU_LOCK;
         CHK(check_free(sys));
         CHK(sys_sync(sys));
         pmd_tuning t;
@@ -1663,6 +1675,7 @@ int pmd_get_tuning(pmd_system* sys, pmd_tuning* out)
 int pmd_set_state(pmd_system* sys, const double* pos, const double* vel, int64_t n, int64_t step)
 {
     try {
+        GPU_LOCK;
         CHK(check_free(sys));
         if (!pos || !vel) return fail(PMD_EINVAL, "pos and vel must not be NULL");
         if (n != sys->nv) return fail(PMD_EINVAL, "n = %lld, system has %lld vapour atoms",
@@ -1711,6 +1724,7 @@ int pmd_autotune(const pmd_params* params, const pmd_pore* pore, int64_t n_vapor
                  double* us_per_step, int32_t* best)
 {
     try {
+        GPU_LOCK;
         if (!candidates || n_candidates < 1 || !best)
             return fail(PMD_EINVAL, "need candidates and best");
         if (trial_steps < 1 || trial_steps > 100000) return fail(PMD_EINVAL, "trial_steps out of range");
@@ -1786,6 +1800,7 @@ int pmd_destroy(pmd_system* sys)
 {
     if (!sys) return PMD_OK;
     try {
+        GPU_LOCK;
         if (sys->batch) return fail(PMD_ESTATE, "system is resident in a batch; release it first");
         delete sys;
         return PMD_OK;
@@ -2005,6 +2020,7 @@ int pmd_batch_create(size_t hbm_budget, int max_slots, void* hip_stream, pmd_bat
 int pmd_batch_admit(pmd_batch* b, pmd_system* sys, int64_t nsteps, int* slot)
 {
     try {
+        GPU_LOCK;
         if (!b || !sys || !slot) return fail(PMD_EINVAL, "NULL argument");
         if (sys->batch) return fail(PMD_ESTATE, "system already resident in a batch");
         if (nsteps < 0 || nsteps > (int64_t)1 << 30) return fail(PMD_EINVAL, "nsteps out of range");
@@ -2198,6 +2214,7 @@ int pmd_batch_poll_async(pmd_batch* b, int* done_slots, int cap, int* n_done)
 int pmd_batch_release(pmd_batch* b, int slot, pmd_system** sys_out)
 {
     try {
+        GPU_LOCK;
         if (!b || slot < 0 || slot >= b->max_slots || !b->resident[slot])
             return fail(PMD_EINVAL, "no system in slot %d", slot);
         pmd_system* sys = b->resident[slot];
@@ -2241,6 +2258,7 @@ int pmd_batch_destroy(pmd_batch* b)
 {
     if (!b) return PMD_OK;
     try {
+        GPU_LOCK;
         for (int s = 0; s < b->max_slots; ++s)
             if (b->resident[s]) CHK(pmd_batch_release(b, s, nullptr));
         for (auto& sn : b->snap) {
