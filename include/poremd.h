@@ -325,7 +325,9 @@ int pmd_debug_lists(pmd_system *sys, int64_t *rebuilds, int64_t *max_len);
  * max_slots bounds the number of resident systems. */
 int pmd_batch_create(size_t hbm_budget, int max_slots, void *hip_stream,
                      pmd_batch **out);
-/* Move a system into the batch with nsteps steps to run.  Returns
+/* Move a system into the batch with nsteps steps to run.  Waits for the
+ * work already queued on the batch (admission changes the batch's tables).
+ * Returns
  * PMD_EAGAIN if no slot or budget is free, or if the batch's wall slots
  * would exceed the limit of pmd_batch_wall_room.  The system handle stays
  * valid but may not be stepped or read until released. */

@@ -694,6 +694,8 @@ int pool_capture(Pool& p, int R, int reps)
 {
     GPU_LOCK;
     if (p.gexec) {
+        // launches of the old graph may still be queued on the stream
+        HIPCHK(hipStreamSynchronize(p.stream));
         HIPCHK(hipGraphExecDestroy(p.gexec));
         p.gexec = nullptr;
     }
@@ -2025,6 +2027,10 @@ int pmd_batch_admit(pmd_batch* b, pmd_system* sys, int64_t nsteps, int* slot)
         if (sys->batch) return fail(PMD_ESTATE, "system already resident in a batch");
         if (nsteps < 0 || nsteps > (int64_t)1 << 30) return fail(PMD_EINVAL, "nsteps out of range");
         CHK(sys_sync(sys));
+        // admission rewrites the pool's tables (and a repack frees the old
+        // pool): the chunks still queued on the batch's stream read them, so
+        // they must have finished first
+        if (b->configured) HIPCHK(hipStreamSynchronize(b->pool->stream));
         Pool& sp0 = *sys->own;
         if (b->configured) {
             if (sp0.precision != b->pool->precision) return fail(PMD_EINVAL, "precision differs from the batch's");
