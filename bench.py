@@ -603,7 +603,7 @@ def pore_sweep_leg(poremd, kinds, steps, autotune_steps, tuning_kw, precisions=(
                 row.update(fig)  # the mixed figures at the top level of the row
             else:
                 row[prec] = fig
-        if "mixed" in row and "fp64" in row:
+        if "value" in row and "fp64" in row:
             row["mixed_over_fp64"] = row["value"] / row["fp64"]["value"]
         out[kind] = row
     return out, keep
