@@ -19,6 +19,10 @@ constexpr int kRebuildBlock = 256;   // threads per workgroup of the per-atom re
 constexpr int kMaxBlock = 1024;      // largest workgroup of the brick kernels (multiple of 64)
 constexpr unsigned kIndexBits = 26;  // neighbour-list entry: index | cell-offset code << 26
 constexpr unsigned kIndexMask = (1u << kIndexBits) - 1u;
+// cell-offset code of a list's pad entries: 3 in every 2-bit field (a value
+// no neighbour cell has), whose shift -2h per axis puts the partner beyond
+// the cutoff
+constexpr unsigned kPadCode = 63u << kIndexBits;
 
 enum Phase : int {
     PH_INIT = 0,  // forces not yet computed

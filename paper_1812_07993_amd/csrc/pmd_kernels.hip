@@ -781,7 +781,9 @@ __device__ __forceinline__ double box_gap(double l, int d, double h)
 
 // Neighbour lists (radius r_c + skin for vapour, r_c + skin/2 for the fixed
 // walls) of the atoms of one brick, in a fixed order: neighbour cells 0..26,
-// staged order inside a cell; vapour entries first, then walls.  Vapour
+// staged order inside a cell; vapour entries first, then walls, each part
+// padded to whole chunks of four entries (list positions 0 .. nv4 - 1 for
+// vapour, nv4 .. nv4 + nw - 1 for walls, nv4 = nv rounded up to 4).  Vapour
 // entries index the brick's staged tile, which the step kernel rebuilds
 // identically from the same cell tables; wall entries are wall slots.  Wall
 // candidates are read from global memory (the static wall coordinates stay
@@ -888,7 +890,13 @@ __global__ void __launch_bounds__(kMaxBlock) k_list_build(PoolDev P)
                 }
             }
         }
+        // the vapour entries end on a chunk boundary: the rest of the last
+        // chunk holds pad entries (the atom itself under the pad code), so the
+        // step kernel reads whole chunks with no per-entry length test
+        const int nv4 = (nv + 3) & ~3;
+        for (int k = nv; k < min(nv4, cap); ++k) P.list[list_at(vt, i, k)] = (unsigned)aself | kPadCode;
         int nw = 0;
+        unsigned lastw = 0;
 #pragma unroll 1
         for (int dz = -1; dz <= 1; ++dz) {
             const double gz = box_gap(lz, dz, sp.h[2]), gz2 = gz * gz;
@@ -918,16 +926,21 @@ __global__ void __launch_bounds__(kMaxBlock) k_list_build(PoolDev P)
                         for (int u = 0; u < kWallRound; ++u) {
                             const T ex = px - o[u].x, ey = py - o[u].y, ez = pz - o[u].z;
                             const bool hit = (w + u < w1) & (ex * ex + ey * ey + ez * ez < rw2);
-                            if (hit && nv + nw < cap) P.list[list_at(vt, i, nv + nw)] = (unsigned)(w + u) | code;
+                            if (hit && nv4 + nw < cap) P.list[list_at(vt, i, nv4 + nw)] = (unsigned)(w + u) | code;
+                            lastw = hit ? (unsigned)(w + u) : lastw;
                             nw += hit;
                         }
                     }
                 }
             }
         }
-        const bool ok = nv + nw <= cap;
+        // the wall entries start at chunk nv4 / 4 and end on a chunk boundary
+        // too (pads: the last wall entry's slot under the pad code)
+        const int nt = nv4 + ((nw + 3) & ~3);
+        for (int k = nv4 + nw; k < min(nt, cap); ++k) P.list[list_at(vt, i, k)] = lastw | kPadCode;
+        const bool ok = nt <= cap;
         P.nlist[i] = ok ? (nv | (nw << 16)) : 0;
-        mx = max(mx, nv + nw);
+        mx = max(mx, nt);
     }
     mx = wave_max(mx);
     if ((threadIdx.x & 63) == 0 && mx > 0) {
@@ -1025,7 +1038,7 @@ __device__ void record_energies(const PoolDev& P, const SysParams& sp, int s, in
 constexpr int kGroupV = 4;  // vapour list entries fetched together in the step kernel (multiple of 4)
 // wall list entries (and wall positions) fetched together: 8 FP32 positions,
 // 6 FP64 ones (8 would spill the FP64 kernel's registers)
-template <typename T> constexpr int kGroupW = sizeof(T) == 4 ? 8 : 6;
+template <typename T> constexpr int kGroupW = sizeof(T) == 4 ? 8 : 4;
 
 
 
@@ -1131,10 +1144,10 @@ __device__ __forceinline__ void pair_term(const StepCtx<T>& x, Acc& a, T dx, T d
     const T A = wall ? x.Aw : x.Av, B = wall ? x.Bw : x.Bv;
     const T sr2 = inv_of<T>(r2);
     const T sr6 = sr2 * sr2 * sr2;
-    const T w = sr2 * sr6 * ((wall ? x.A12w : x.A12v) * sr6 - (wall ? x.B6w : x.B6v));
-    a.fx += (double)(w * dx);
-    a.fy += (double)(w * dy);
-    a.fz += (double)(w * dz);
+    const double w = (double)(sr2 * sr6 * ((wall ? x.A12w : x.A12v) * sr6 - (wall ? x.B6w : x.B6v)));
+    a.fx = fma(w, (double)dx, a.fx);
+    a.fy = fma(w, (double)dy, a.fy);
+    a.fz = fma(w, (double)dz, a.fz);
     if (x.doE) {
         const double u_ = (double)(sr6 * (A * sr6 - B) - (wall ? x.ucw : x.ucv));
         if (wall)
@@ -1142,7 +1155,7 @@ __device__ __forceinline__ void pair_term(const StepCtx<T>& x, Acc& a, T dx, T d
         else
             a.ev += u_;
         if constexpr (VIR) {
-            const double v_ = (double)(w * r2);  // r . f of the pair
+            const double v_ = w * (double)r2;  // r . f of the pair
             if (wall)
                 a.ww += v_;
             else
@@ -1190,22 +1203,26 @@ __device__ __forceinline__ void edge_entry(const PoolDev& P, const SysParams& sp
 
 // The pairs of atom i that the pair loops left out (FP32 r^2 within the band
 // around the cutoff), decided on the FP64 master positions and added in list
-// order.  The loops record the list positions of the first two such entries
-// (ne counts them all); only an atom with more than two rescans its list.
+// order.  The loops record the list positions of the last two such entries
+// (k0 the later one; ne counts them all); only an atom with more than two
+// rescans its list (vapour positions 0 .. nvap - 1, walls from the chunk
+// boundary nv4 on).
 template <typename T, bool VIR>
 __device__ void edge_pass(const PoolDev& P, const SysParams& sp, const StepCtx<T>& x,
-                          const Tile<T>& tl, int i, int nvap, int nall, int ne, int k0, int k1,
+                          const Tile<T>& tl, int i, int nvap, int nwal, int ne, int k0, int k1,
                           Acc& a)
 {
     const int vt = P.vt;
     const typename V4<T>::type me = x.Lc[i];
     const double xi = x.X[i], yi = x.X[vt + i], zi = x.X[2 * vt + i];
     if (ne <= 2) {
-        edge_entry<T, VIR>(P, sp, x, tl, i, k0, nvap, me, xi, yi, zi, a);
         if (ne == 2) edge_entry<T, VIR>(P, sp, x, tl, i, k1, nvap, me, xi, yi, zi, a);
+        edge_entry<T, VIR>(P, sp, x, tl, i, k0, nvap, me, xi, yi, zi, a);
         return;
     }
-    for (int k = 0; k < nall; ++k) edge_entry<T, VIR>(P, sp, x, tl, i, k, nvap, me, xi, yi, zi, a);
+    const int nv4 = (nvap + 3) & ~3;
+    for (int k = 0; k < nvap; ++k) edge_entry<T, VIR>(P, sp, x, tl, i, k, nvap, me, xi, yi, zi, a);
+    for (int k = nv4; k < nv4 + nwal; ++k) edge_entry<T, VIR>(P, sp, x, tl, i, k, nvap, me, xi, yi, zi, a);
 }
 
 // What a lane reads of its atom before the pair loops: the local position,
@@ -1356,8 +1373,8 @@ __device__ void step_reduce(const PoolDev& P, const SysParams& sp, int s, int b,
 }
 
 // Shift -d h of every 6-bit cell-offset code (2 bits per axis, d + 1 in
-// {0, 1, 2}; code 3 does not occur): one LDS read per list entry instead of
-// decoding the three fields.
+// {0, 1, 2}; a field of 3 occurs only in the pad code, shift -2h): one LDS
+// read per list entry instead of decoding the three fields.
 template <typename T>
 __device__ __forceinline__ typename V4<T>::type shift_lut_entry(int q, T hx, T hy, T hz)
 {
@@ -1388,13 +1405,32 @@ __device__ __forceinline__ typename V4<T>::type shift_at(const typename V4<T>::t
     }
 }
 
-// A list entry in the band around the cutoff: counted, and the first two
-// list positions kept for the pass that decides them in FP64.
-__device__ __forceinline__ void note_edge(int& ne, int& k0, int& k1, int k)
+// A list entry in the band around the cutoff: counted, and the list
+// positions of the last two kept (k0 the latest) for the pass that decides
+// them in FP64.
+__device__ __forceinline__ void note_edge(int& ne, int& k0, int& k1, int k, bool near)
 {
-    k0 = ne == 0 ? k : k0;
-    k1 = ne == 1 ? k : k1;
-    ++ne;
+    k1 = near ? k0 : k1;
+    k0 = near ? k : k0;
+    ne += near;
+}
+
+// The cutoff-band entries of one group of G list entries starting at list
+// position k: a branch on the whole wave (band entries are rare, about one
+// group in a thousand holds one in any lane), so the common case costs a few
+// scalar instructions instead of the bookkeeping per entry; the empty asm
+// keeps the compiler from turning the branch back into selects.
+template <int G>
+__device__ __forceinline__ void note_group(const bool (&nr)[G], int& ne, int& k0, int& k1, int k)
+{
+    bool any = false;
+#pragma unroll
+    for (int u = 0; u < G; ++u) any |= nr[u];
+    if (__builtin_amdgcn_ballot_w64(any) != 0) {
+        asm volatile("");
+#pragma unroll
+        for (int u = 0; u < G; ++u) note_edge(ne, k0, k1, k + u, nr[u]);
+    }
 }
 
 // One list entry's pair with no branch: w (and the energy) is masked to 0
@@ -1408,10 +1444,12 @@ __device__ __forceinline__ void pair_masked(const StepCtx<T>& x, Acc& a, T dx, T
     const T sr2 = inv_of<T>(in ? r2 : (T)1);
     const T sr6 = sr2 * sr2 * sr2;
     const T wf = sr2 * sr6 * ((wall ? x.A12w : x.A12v) * sr6 - (wall ? x.B6w : x.B6v));
-    const T w = in ? wf : (T)0;
-    a.fx += (double)(w * dx);
-    a.fy += (double)(w * dy);
-    a.fz += (double)(w * dz);
+    // w d added in FP64 (one rounding: the FP64 product of two FP32 values is
+    // exact); the pair's two atoms add exact negatives
+    const double w = (double)(in ? wf : (T)0);
+    a.fx = fma(w, (double)dx, a.fx);
+    a.fy = fma(w, (double)dy, a.fy);
+    a.fz = fma(w, (double)dz, a.fz);
     if constexpr (DOE) {
         const T u = sr6 * ((wall ? x.Aw : x.Av) * sr6 - (wall ? x.Bw : x.Bv)) - (wall ? x.ucw : x.ucv);
         const double ud = (double)(in ? u : (T)0);
@@ -1420,7 +1458,7 @@ __device__ __forceinline__ void pair_masked(const StepCtx<T>& x, Acc& a, T dx, T
         else
             a.ev += ud;
         if constexpr (VIR) {
-            const double vd = (double)(w * r2);  // r . f of the pair
+            const double vd = w * (double)r2;  // r . f of the pair
             if (wall)
                 a.ww += vd;
             else
@@ -1444,88 +1482,108 @@ __device__ __forceinline__ void step_atoms(PoolDev& P, const SysParams& sp, cons
         const AtomIn<T> in = i == i0 + (int)threadIdx.x ? first : atom_in<T>(P, x, i);
         const V me = in.me;
         const int nl = in.nl;
-        const int nvap = nl & 0xFFFF, nall = nvap + (nl >> 16);
+        const int nvap = nl & 0xFFFF;
         a.fx = a.fy = a.fz = 0.0;
         if constexpr (VIR) a.wv = 0.0;
-        // entries come kGroupV (vapour, as kGroupV / 4 chunk loads) or
-        // kGroupW<T> (walls) at a time, the next group's loads in flight while
-        // the current one is evaluated; a group's partner positions (from LDS
-        // for vapour, from global memory for walls) and shifts are all read
-        // before any is used.  Pairs whose FP32 r^2 lies within a narrow band
-        // around the cutoff are left out here and decided in FP64 after the
-        // whole list (a rare slow path: a few atoms per step).  Every load is
-        // unconditional, with indices clamped to valid memory (list chunks
-        // past the end of this atom's list exist up to the capacity; their
-        // values are not used), so the code is straight-line and each wait
-        // covers only the loads it needs
-        int ne = 0, ke0 = 0, ke1 = 0;  // cutoff-band entries: count, first two list positions
-        const int lastrow = P.cap - 1, lastchunk = P.cap / 4 - 1;
+        // entries come in chunks of four (one 16-byte load each): one chunk
+        // per vapour group, kGroupW<T> / 4 per wall group; the next group's
+        // chunks are in flight while the current one is evaluated, and a
+        // group's partner positions (from LDS for vapour, from global memory
+        // for walls) and shifts are all read before any is used.  Each part
+        // of the list ends on a chunk boundary with pad entries whose shift
+        // puts the partner beyond the cutoff, so no entry needs a length
+        // test.  Pairs whose FP32 r^2 lies within a narrow band around the
+        // cutoff are left out here and decided in FP64 after the whole list
+        // (a rare slow path: a few atoms per step).  Chunk loads past the end
+        // of this atom's list are clamped to the capacity and their values
+        // are not used, so the code is straight-line and each wait covers
+        // only the loads it needs
+        int ne = 0, ke0 = 0, ke1 = 0;  // cutoff-band entries: count, last two list positions
+        const int nv4 = (nvap + 3) & ~3, nwal = nl >> 16;
+        const int lastchunk = P.cap / 4 - 1;
         const uint4* lst4 = (const uint4*)P.list + i;  // chunk c of this atom at lst4[c * vt]
         static_assert(kGroupV == 4, "the vapour loop takes one 16-byte chunk per group");
-        // one group of four vapour entries (one chunk) at list position k
+        // one group of four vapour entries (one chunk) at list position k; a
+        // vapour entry's tile index is below 2^22, so e >> 22 is its code
+        // times 16, the byte offset of its shift in the table
         auto vapour_group = [&](const uint4 c, int k) {
             const unsigned ec[4] = {c.x, c.y, c.z, c.w};
             V o[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) o[u] = tl.pos[k + u < nvap ? (int)(ec[u] & kIndexMask) : 0];
+            for (int u = 0; u < 4; ++u) o[u] = tl.pos[ec[u] & kIndexMask];
             V sh[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) sh[u] = shift_at<T>(lut, ec[u], x);
+            for (int u = 0; u < 4; ++u) {
+                if constexpr (sizeof(T) == 4)
+                    sh[u] = *(const V*)((const char*)lut + (ec[u] >> (kIndexBits - 4)));
+                else
+                    sh[u] = shift_at<T>(lut, ec[u], x);
+            }
+            bool nr[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const bool live = k + u < nvap;
                 const T dx = me.x - o[u].x + sh[u].x;
                 const T dy = me.y - o[u].y + sh[u].y;
                 const T dz = me.z - o[u].z + sh[u].z;
                 const T r2 = dx * dx + dy * dy + dz * dz;
-                const bool near = live && sizeof(T) == 4 && fabs(r2 - x.rc2) < x.band;
-                if (near) note_edge(ne, ke0, ke1, k + u);
-                pair_masked<T, VIR, DOE>(x, a, dx, dy, dz, r2, live && r2 < x.rc2 && !near, false);
+                nr[u] = sizeof(T) == 4 && fabs(r2 - x.rc2) < x.band;
+                pair_masked<T, VIR, DOE>(x, a, dx, dy, dz, r2, r2 < x.rc2 && !nr[u], false);
             }
+            note_group<4>(nr, ne, ke0, ke1, k);
         };
         // two chunks per trip in alternating registers: the next chunk's
         // load is in flight while the current one is evaluated (the empty
         // asm with a memory clobber keeps the compiler from folding the
         // prefetched load and the first one into a single load at the top)
         uint4 ca = in.c0, cb;
-        for (int k0 = 0; k0 < nvap; k0 += 8) {
+        for (int k0 = 0; k0 < nv4; k0 += 8) {
             cb = lst4[(size_t)min((k0 >> 2) + 1, lastchunk) * vt];
             asm volatile("" ::: "memory");
             vapour_group(ca, k0);
-            if (k0 + 4 >= nvap) break;
+            if (k0 + 4 >= nv4) break;
             ca = lst4[(size_t)min((k0 >> 2) + 2, lastchunk) * vt];
             asm volatile("" ::: "memory");
             vapour_group(cb, k0 + 4);
         }
-        if (nall > nvap) {
-            unsigned cw[kGroupW<T>];
+        if (nwal > 0) {
+            // wall chunks c0 .. c0 + ncw - 1; a group's chunks past the last
+            // one take the group's first entry under the pad code
+            constexpr int G = kGroupW<T> / 4;
+            const int c0 = nv4 >> 2, ncw = (nwal + 3) >> 2;
+            const V* Lw = x.Lc + vt;
+            uint4 cw[G];
 #pragma unroll
-            for (int u = 0; u < kGroupW<T>; ++u) cw[u] = P.list[list_at(vt, i, min(nvap + u, lastrow))];
-            for (int k0 = nvap; k0 < nall; k0 += kGroupW<T>) {
+            for (int q = 0; q < G; ++q) cw[q] = lst4[(size_t)min(c0 + q, lastchunk) * vt];
+            for (int c = 0; c < ncw; c += G) {
+                unsigned e[kGroupW<T>];
+#pragma unroll
+                for (int q = 0; q < G; ++q) {
+                    const bool live = q == 0 || c + q < ncw;
+                    e[4 * q] = live ? cw[q].x : (cw[0].x | kPadCode);
+                    e[4 * q + 1] = live ? cw[q].y : (cw[0].x | kPadCode);
+                    e[4 * q + 2] = live ? cw[q].z : (cw[0].x | kPadCode);
+                    e[4 * q + 3] = live ? cw[q].w : (cw[0].x | kPadCode);
+                }
                 V ow[kGroupW<T>];
 #pragma unroll
-                for (int u = 0; u < kGroupW<T>; ++u) ow[u] = x.Lc[vt + (k0 + u < nall ? (int)(cw[u] & kIndexMask) : 0)];
-                unsigned nw[kGroupW<T>];
+                for (int u = 0; u < kGroupW<T>; ++u) ow[u] = Lw[e[u] & kIndexMask];
 #pragma unroll
-                for (int u = 0; u < kGroupW<T>; ++u)
-                    nw[u] = P.list[list_at(vt, i, min(k0 + kGroupW<T> + u, lastrow))];
+                for (int q = 0; q < G; ++q) cw[q] = lst4[(size_t)min(c0 + c + G + q, lastchunk) * vt];
+                bool nr[kGroupW<T>];
 #pragma unroll
                 for (int u = 0; u < kGroupW<T>; ++u) {
-                    const bool live = k0 + u < nall;
-                    const V sw = shift_at<T>(lut, cw[u], x);
+                    const V sw = shift_at<T>(lut, e[u], x);
                     const T dx = me.x - ow[u].x + sw.x;
                     const T dy = me.y - ow[u].y + sw.y;
                     const T dz = me.z - ow[u].z + sw.z;
                     const T r2 = dx * dx + dy * dy + dz * dz;
-                    const bool near = live && sizeof(T) == 4 && fabs(r2 - x.rc2) < x.band;
-                    if (near) note_edge(ne, ke0, ke1, k0 + u);
-                    pair_masked<T, VIR, DOE>(x, a, dx, dy, dz, r2, live && r2 < x.rc2 && !near, true);
+                    nr[u] = sizeof(T) == 4 && fabs(r2 - x.rc2) < x.band;
+                    pair_masked<T, VIR, DOE>(x, a, dx, dy, dz, r2, r2 < x.rc2 && !nr[u], true);
                 }
-#pragma unroll
-                for (int u = 0; u < kGroupW<T>; ++u) cw[u] = nw[u];
+                note_group<kGroupW<T>>(nr, ne, ke0, ke1, nv4 + 4 * c);
             }
         }
-        if (ne) edge_pass<T, VIR>(P, sp, x, tl, i, nvap, nall, ne, ke0, ke1, a);
+        if (ne) edge_pass<T, VIR>(P, sp, x, tl, i, nvap, nwal, ne, ke0, ke1, a);
         const double kei = atom_epilogue<T>(P, x, i, a, flags);
         ke += kei;
         if constexpr (VIR && DOE) {
@@ -1895,9 +1953,10 @@ __global__ void k_debug_pairs(PoolDev P, int slot, int* out, int cap, int* count
     const int i0 = P.cstart[sp.coff + key0], i1 = P.cstart[sp.coff + key0 + sp.bcells];
     for (int i = i0 + (int)threadIdx.x; i < i1; i += blockDim.x) {
         const int nl = P.nlist[i];
-        const int nvap = nl & 0xFFFF, n = nvap + (nl >> 16);
+        const int nvap = nl & 0xFFFF, nv4 = (nvap + 3) & ~3, n = nv4 + (nl >> 16);
         const double xi = X[i], yi = X[vt + i], zi = X[2 * vt + i];
         for (int k = 0; k < n; ++k) {
+            if (k >= nvap && k < nv4) continue;  // the vapour part's pad entries
             const unsigned e = P.list[list_at(vt, i, k)];
             const int a = (int)(e & kIndexMask);
             double ox, oy, oz;
