@@ -872,17 +872,22 @@ __global__ void __launch_bounds__(kMaxBlock) k_list_build(PoolDev P)
                     const int h = hs + dx + dy * hstr1 + dz * hstr2;
                     const int a1 = t.hoff[h + 1];
                     for (int a = t.hoff[h]; a < a1; a += 4) {
+                        // four candidates through one pointer; the reads past
+                        // the cell's last atom (at most three, a + 3 <= cap + 2)
+                        // stay inside the workgroup's LDS (the slot table
+                        // follows the positions) and are never used
+                        const V* pa = t.pos + a;
                         V o[4];
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) o[u] = t.pos[min(a + u, a1 - 1)];
+                        for (int u = 0; u < 4; ++u) o[u] = pa[u];
+                        const int rem = a1 - a, dself = aself - a;
 #pragma unroll
                         for (int u = 0; u < 4; ++u) {
                             const T ex = px - o[u].x, ey = py - o[u].y, ez = pz - o[u].z;
                             // one branch per candidate (the tests combined
-                            // without short-circuit; the clamped loads make
-                            // all of them safe): the store only when the entry
-                            // is in range and fits
-                            const bool hit = (a + u < a1) & (ex * ex + ey * ey + ez * ez < rl2) & (a + u != aself);
+                            // without short-circuit): the store only when the
+                            // entry is in range and fits
+                            const bool hit = (u < rem) & (ex * ex + ey * ey + ez * ez < rl2) & (u != dself);
                             if (hit && nv < cap) P.list[list_at(vt, i, nv)] = (unsigned)(a + u) | code;
                             nv += hit;
                         }
