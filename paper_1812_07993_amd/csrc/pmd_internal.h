@@ -79,7 +79,19 @@ struct SysParams {
     int pkind;
     int pad1;
     double pz0, pz1, pr0, pr1, pvol;
+    // reciprocals of the brick extents, for exact quotients by FP64
+    // multiplication: 1/bdim per axis, 1/nbk0, 1/(nbk0 nbk1), 1/bcells
+    double inv_bdim[3], inv_nbk0, inv_nbk01, inv_bcells;
 };
+
+// Quotient n / d for 0 <= n < 2^50 from inv = 1/d (rounded): (n + 1/2)/d lies
+// at least 1/(2d) from an integer, far more than the rounding of the FP64
+// product, so the truncation is exact.  Three instructions in place of the
+// forty or so of an integer division by a value known only at run time.
+__host__ __device__ __forceinline__ int quot(int n, double inv)
+{
+    return (int)(((double)n + 0.5) * inv);
+}
 
 // Per-system dynamic state, written by kernels.
 struct SysState {

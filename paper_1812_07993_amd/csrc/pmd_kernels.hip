@@ -380,7 +380,7 @@ hipError_t launch_wall_bin(const PoolDev& P, int sys, const double* raw, int rs,
 // slots after sorting.
 __device__ __forceinline__ int cell_key(const SysParams& sp, int cx, int cy, int cz)
 {
-    const int Bx = cx / sp.bdim[0], By = cy / sp.bdim[1], Bz = cz / sp.bdim[2];
+    const int Bx = quot(cx, sp.inv_bdim[0]), By = quot(cy, sp.inv_bdim[1]), Bz = quot(cz, sp.inv_bdim[2]);
     const int lx = cx - Bx * sp.bdim[0], ly = cy - By * sp.bdim[1], lz = cz - Bz * sp.bdim[2];
     const int b = Bx + sp.nbk[0] * (By + sp.nbk[1] * Bz);
     return b * sp.bcells + lx + sp.bdim[0] * (ly + sp.bdim[1] * lz);
@@ -388,9 +388,11 @@ __device__ __forceinline__ int cell_key(const SysParams& sp, int cx, int cy, int
 
 __device__ __forceinline__ void key_cell(const SysParams& sp, int key, int& cx, int& cy, int& cz)
 {
-    const int b = key / sp.bcells, l = key - b * sp.bcells;
-    const int Bx = b % sp.nbk[0], By = (b / sp.nbk[0]) % sp.nbk[1], Bz = b / (sp.nbk[0] * sp.nbk[1]);
-    const int lx = l % sp.bdim[0], ly = (l / sp.bdim[0]) % sp.bdim[1], lz = l / (sp.bdim[0] * sp.bdim[1]);
+    const int b = quot(key, sp.inv_bcells), l = key - b * sp.bcells;
+    const int Bz = quot(b, sp.inv_nbk01), b2 = b - Bz * sp.nbk[0] * sp.nbk[1];
+    const int By = quot(b2, sp.inv_nbk0), Bx = b2 - By * sp.nbk[0];
+    const int lz = quot(l, sp.inv_bdim[0] * sp.inv_bdim[1]), l2 = l - lz * sp.bdim[0] * sp.bdim[1];
+    const int ly = quot(l2, sp.inv_bdim[0]), lx = l2 - ly * sp.bdim[0];
     cx = Bx * sp.bdim[0] + lx;
     cy = By * sp.bdim[1] + ly;
     cz = Bz * sp.bdim[2] + lz;
@@ -642,7 +644,17 @@ struct HaloGeo {
     int start[3];  // first cell of the brick along each axis
     int hd[3];     // halo box extent (brick extent + 2)
     int H;         // halo cells
+    double inv0, inv01;  // 1 / hd[0], 1 / (hd[0] hd[1])
 };
+
+// Halo cell h as (hx, hy, hz), x fastest (exact quotients, see quot).
+__device__ __forceinline__ void halo_xyz(const HaloGeo& g, int h, int& hx, int& hy, int& hz)
+{
+    hz = quot(h, g.inv01);
+    const int r = h - hz * g.hd[0] * g.hd[1];
+    hy = quot(r, g.inv0);
+    hx = r - hy * g.hd[0];
+}
 
 __device__ __forceinline__ HaloGeo halo_geo(const SysParams& sp, int b)
 {
@@ -655,6 +667,8 @@ __device__ __forceinline__ HaloGeo halo_geo(const SysParams& sp, int b)
         g.hd[k] = end - g.start[k] + 2;
         g.H *= g.hd[k];
     }
+    g.inv0 = 1.0 / g.hd[0];
+    g.inv01 = 1.0 / (g.hd[0] * g.hd[1]);
     return g;
 }
 
@@ -712,7 +726,8 @@ __device__ int stage_halo(const PoolDev& P, const SysParams& sp, const HaloGeo& 
     const int lo = threadIdx.x * per, hi = min(g.H, lo + per);
     int sum = 0;
     for (int h = lo; h < hi; ++h) {
-        const int hx = h % g.hd[0], hy = (h / g.hd[0]) % g.hd[1], hz = h / (g.hd[0] * g.hd[1]);
+        int hx, hy, hz;
+        halo_xyz(g, h, hx, hy, hz);
         const int cx = wrap_cell(g.start[0] - 1 + hx, sp.nc[0]);
         const int cy = wrap_cell(g.start[1] - 1 + hy, sp.nc[1]);
         const int cz = wrap_cell(g.start[2] - 1 + hz, sp.nc[2]);
@@ -809,7 +824,8 @@ __global__ void __launch_bounds__(kMaxBlock) k_list_build(PoolDev P)
     {
         const int* wcs = P.wcstart + sp.wcoff;
         for (int h = threadIdx.x; h < g.H; h += blockDim.x) {
-            const int hx = h % g.hd[0], hy = (h / g.hd[0]) % g.hd[1], hz = h / (g.hd[0] * g.hd[1]);
+            int hx, hy, hz;
+            halo_xyz(g, h, hx, hy, hz);
             const int cl = wrap_cell(g.start[0] - 1 + hx, sp.nc[0]) +
                            sp.nc[0] * (wrap_cell(g.start[1] - 1 + hy, sp.nc[1]) +
                                        sp.nc[1] * wrap_cell(g.start[2] - 1 + hz, sp.nc[2]));

@@ -619,7 +619,11 @@ void choose_bricks(SysParams& sp, double target, size_t atom_bytes)
         sp.nbk[k] = (sp.nc[k] + best[k] - 1) / best[k];
         sp.bcells *= best[k];
         sp.nbrick *= sp.nbk[k];
+        sp.inv_bdim[k] = 1.0 / best[k];
     }
+    sp.inv_nbk0 = 1.0 / sp.nbk[0];
+    sp.inv_nbk01 = 1.0 / ((double)sp.nbk[0] * sp.nbk[1]);
+    sp.inv_bcells = 1.0 / sp.bcells;
     sp.nkey = sp.nbrick * sp.bcells;
 }
 
