@@ -847,9 +847,9 @@ __global__ void __launch_bounds__(kMaxBlock) k_list_build(PoolDev P)
     // the rounding of the local coordinates)
     const double cull_v = sp.rl2 * (1.0 + 1e-6), cull_w = sp.rw2 * (1.0 + 1e-6);
     const int cap = P.cap;
-    // wall candidates loaded together: 12 FP32 positions, 8 FP64 ones (12
-    // would spill the FP64 kernel's registers)
-    constexpr int kWallRound = sizeof(T) == 4 ? 12 : 8;
+    // wall candidates per load round (a window is two rounds): 12 FP32
+    // positions, 4 FP64 ones (more would spill the FP64 kernel's registers)
+    constexpr int kWallRound = sizeof(T) == 4 ? 12 : 4;
     int mx = 0;
     for (int i = i0 + (int)threadIdx.x; i < i1; i += blockDim.x) {
         const V me = Lc[i];
@@ -887,25 +887,37 @@ __global__ void __launch_bounds__(kMaxBlock) k_list_build(PoolDev P)
                     const unsigned code = offset_code((dx + 1) + 3 * (dy + 1) + 9 * (dz + 1)) << kIndexBits;
                     const int h = hs + dx + dy * hstr1 + dz * hstr2;
                     const int a1 = t.hoff[h + 1];
-                    for (int a = t.hoff[h]; a < a1; a += 4) {
-                        // four candidates through one pointer; the reads past
-                        // the cell's last atom (at most three, a + 3 <= cap + 2)
-                        // stay inside the workgroup's LDS (the slot table
-                        // follows the positions) and are never used
-                        const V* pa = t.pos + a;
-                        V o[4];
+                    // windows of 32 candidates: the tests of a window set
+                    // bits of a mask (no branch per candidate), then only
+                    // the hits are written, in candidate order
+                    for (int w0 = t.hoff[h]; w0 < a1; w0 += 32) {
+                        const int wend = min(a1, w0 + 32);
+                        unsigned bits = 0u;
+                        for (int a = w0; a < wend; a += 4) {
+                            // four candidates through one pointer; the reads
+                            // past the cell's last atom (at most three,
+                            // a + 3 <= cap + 2) stay inside the workgroup's
+                            // LDS (the slot table follows the positions) and
+                            // their bits are dropped below
+                            const V* pa = t.pos + a;
+                            V o[4];
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) o[u] = pa[u];
-                        const int rem = a1 - a, dself = aself - a;
+                            for (int u = 0; u < 4; ++u) o[u] = pa[u];
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            const T ex = px - o[u].x, ey = py - o[u].y, ez = pz - o[u].z;
-                            // one branch per candidate (the tests combined
-                            // without short-circuit): the store only when the
-                            // entry is in range and fits
-                            const bool hit = (u < rem) & (ex * ex + ey * ey + ez * ez < rl2) & (u != dself);
-                            if (hit && nv < cap) P.list[list_at(vt, i, nv)] = (unsigned)(a + u) | code;
-                            nv += hit;
+                            for (int u = 0; u < 4; ++u) {
+                                const T ex = px - o[u].x, ey = py - o[u].y, ez = pz - o[u].z;
+                                bits |= (unsigned)(ex * ex + ey * ey + ez * ez < rl2) << (a - w0 + u);
+                            }
+                        }
+                        // candidates past the cell's end, and the atom itself
+                        const int nwin = wend - w0, dself = aself - w0;
+                        bits &= nwin >= 32 ? ~0u : ((1u << nwin) - 1u);
+                        bits &= ~((unsigned)(dself >= 0 && dself < 32) << (dself & 31));
+                        while (bits) {
+                            const int u = __builtin_ctz(bits);
+                            bits &= bits - 1u;
+                            if (nv < cap) P.list[list_at(vt, i, nv)] = (unsigned)(w0 + u) | code;
+                            ++nv;
                         }
                     }
                 }
@@ -933,23 +945,36 @@ __global__ void __launch_bounds__(kMaxBlock) k_list_build(PoolDev P)
                     const double gx = box_gap(lx, dx, sp.h[0]);
                     if (fma(gx, gx, gyz) >= cull_w) continue;
                     const int h = hs + dx + dy * hstr1 + dz * hstr2;
-                    const int w0 = wrange[2 * h], w1 = wrange[2 * h + 1];
-                    if (w0 >= w1) continue;
+                    const int w0c = wrange[2 * h], w1 = wrange[2 * h + 1];
+                    if (w0c >= w1) continue;
                     const T px = me.x - (T)dx * hx;
                     const unsigned code = offset_code((dx + 1) + 3 * (dy + 1) + 9 * (dz + 1)) << kIndexBits;
-                    // kWallRound candidates per round, loads issued together
-                    // (indices clamped to the cell's last wall)
-                    for (int w = w0; w < w1; w += kWallRound) {
-                        V o[kWallRound];
+                    // windows of two rounds of kWallRound candidates (loads
+                    // of a round issued together, indices clamped to the
+                    // cell's last wall): tests into a mask, then the hits
+                    for (int w0 = w0c; w0 < w1; w0 += 2 * kWallRound) {
+                        unsigned bits = 0u;
 #pragma unroll
-                        for (int u = 0; u < kWallRound; ++u) o[u] = Lw[min(w + u, w1 - 1)];
+                        for (int rd = 0; rd < 2; ++rd) {
+                            const int wr = w0 + rd * kWallRound;
+                            V o[kWallRound];
 #pragma unroll
-                        for (int u = 0; u < kWallRound; ++u) {
-                            const T ex = px - o[u].x, ey = py - o[u].y, ez = pz - o[u].z;
-                            const bool hit = (w + u < w1) & (ex * ex + ey * ey + ez * ez < rw2);
-                            if (hit && nv4 + nw < cap) P.list[list_at(vt, i, nv4 + nw)] = (unsigned)(w + u) | code;
-                            lastw = hit ? (unsigned)(w + u) : lastw;
-                            nw += hit;
+                            for (int u = 0; u < kWallRound; ++u) o[u] = Lw[min(wr + u, w1 - 1)];
+#pragma unroll
+                            for (int u = 0; u < kWallRound; ++u) {
+                                const T ex = px - o[u].x, ey = py - o[u].y, ez = pz - o[u].z;
+                                bits |= (unsigned)(ex * ex + ey * ey + ez * ez < rw2) << (rd * kWallRound + u);
+                            }
+                        }
+                        const int nwin = w1 - w0;
+                        bits &= nwin >= 2 * kWallRound ? ~0u : ((1u << nwin) - 1u);
+                        while (bits) {
+                            const int u = __builtin_ctz(bits);
+                            bits &= bits - 1u;
+                            const unsigned w = (unsigned)(w0 + u);
+                            if (nv4 + nw < cap) P.list[list_at(vt, i, nv4 + nw)] = w | code;
+                            lastw = w;
+                            ++nw;
                         }
                     }
                 }
