@@ -171,6 +171,7 @@ struct PoolDev {
     int* cstart;          // per cell + padding + end: first slot (global)
     int* arr;             // arrival rank within the cell (per slot)
     int* tmp;             // slots in arrival order
+    int* tmpid;           // caller index of the atom at each arrival position
     int* cell_tmp;        // cell key of each old slot
     // neighbour lists, entry k of slot i at ((k / 4) * vt + i) * 4 + k % 4
     // (chunks of four entries per slot): vapour entries index the brick's

@@ -551,7 +551,11 @@ __global__ void k_bin_scatter(PoolDev P)
     if (!rebuild_ctx(P, c)) return;
     const SysParams& sp = P.sp[c.s];
     const int cell = P.cell_tmp[c.i];
-    P.tmp[cell_begin(P, sp, cell) + P.arr[c.i]] = c.i;
+    const int q = cell_begin(P, sp, cell) + P.arr[c.i];
+    P.tmp[q] = c.i;
+    // the caller index beside it, so the placement ranks a cell's arrivals
+    // from one contiguous range instead of a gather per arrival
+    P.tmpid[q] = P.id[P.st[c.s].ibuf_prev][c.i];
 }
 
 template <typename T>
@@ -567,18 +571,14 @@ __global__ void k_bin_place(PoolDev P)
     const int o = P.tmp[c.i];
     const int cell = P.cell_tmp[o];
     const int b0 = cell_begin(P, sp, cell), b1 = cell_begin(P, sp, cell + 1);
-    const int* ids = P.id[st.ibuf_prev];
-    const int myid = ids[o];
+    const int myid = P.tmpid[c.i];
     int rank = 0;
-    // the cell's arrivals eight at a time, loads issued together (indices
-    // clamped to the cell's last arrival)
+    // the caller indices of the cell's arrivals eight at a time, loads
+    // issued together (indices clamped to the cell's last arrival)
     for (int q = b0; q < b1; q += 8) {
-        int t[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) t[u] = P.tmp[min(q + u, b1 - 1)];
         int idq[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) idq[u] = ids[t[u]];
+        for (int u = 0; u < 8; ++u) idq[u] = P.tmpid[min(q + u, b1 - 1)];
 #pragma unroll
         for (int u = 0; u < 8; ++u) rank += (q + u < b1 && idq[u] < myid) ? 1 : 0;
     }

@@ -293,6 +293,7 @@ struct Pool {
     int* cstart = nullptr;
     int* arr = nullptr;
     int* tmp = nullptr;
+    int* tmpid = nullptr;
     int* cell_tmp = nullptr;
     unsigned* list = nullptr;
     int* nlist = nullptr;
@@ -398,6 +399,7 @@ struct Pool {
         d.cstart = cstart;
         d.arr = arr;
         d.tmp = tmp;
+        d.tmpid = tmpid;
         d.cell_tmp = cell_tmp;
         d.list = list;
         d.nlist = nlist;
@@ -421,7 +423,7 @@ size_t pool_bytes(int precision, int vt, int wt, int ct, int wct, int nbt, int n
     s += 2 * (size_t)vt * 4 + 2 * (size_t)vt * 4;          // id x2, cref, cell_lin
     s += (size_t)vt * 16;                                  // reference positions
     s += 2 * (size_t)(vt + wt) * lsize(precision);         // local coordinates x2
-    s += 3 * (size_t)ct * 4 + 3 * (size_t)std::max(vt, wt) * 4;
+    s += 3 * (size_t)ct * 4 + 4 * (size_t)std::max(vt, wt) * 4;
     s += (size_t)vt * cap * 4 + (size_t)vt * 4;            // lists
     s += 3 * (size_t)wt * 8 + (size_t)wt * 4 + (size_t)wct * 4;
     s += 2 * kPartial * (size_t)nbt * 8 + (size_t)nslots * erings * sizeof(EnergyRec);
@@ -466,6 +468,7 @@ int pool_allocate(Pool& p)
     const int sc = std::max(vt, wt);
     CHK(p.alloc(&p.arr, sc));
     CHK(p.alloc(&p.tmp, sc));
+    CHK(p.alloc(&p.tmpid, sc));
     CHK(p.alloc(&p.cell_tmp, sc));
     CHK(p.alloc(&p.list, (size_t)vt * p.cap));
     CHK(p.alloc(&p.nlist, vt));
