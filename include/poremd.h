@@ -459,7 +459,7 @@ int64_t pmd_pm_record_rows(int64_t nsteps, int64_t energy_every);
  *   rec_dev       device, rec_cap records (NULL = none): step 0, every
  *                 energy_every-th step and the last step, in order.
  *   stream        hipStream_t (NULL = the default stream); queued, no wait.
- * Working memory ((dim + 3) n + 2 doubles) is taken from the stream-ordered
+ * Working memory ((dim + 4) n + 2 + 4 ceil(n / 256) doubles) is taken from the stream-ordered
  * allocator for the call and returned at its end.  Sums are in a fixed
  * order: repeated runs give identical results.  Returns PMD_EINVAL for a
  * dim other than 2 or 3, a precision other than 1 or 2, n outside 0..2^20,
@@ -475,7 +475,7 @@ int pmd_pm_run(const pmd_pm_model *model, int64_t n, double *x_dev,
  * graph capture, tight serving loops, harnesses that forbid allocation): the
  * same arguments, steps and results, but the working memory is a static
  * device array of the library, one per GPU, held until the process ends,
- * sized for n <= 65536 molecules (3.1 MB).  Makes no allocation of any kind.
+ * sized for n <= 65536 molecules (3.7 MB).  Makes no allocation of any kind.
  * Every call on a GPU shares that GPU's array: calls that overlap on one GPU
  * (on different streams, or from different threads) race and give wrong
  * results; calls queued on one stream are safe.  Returns PMD_EINVAL for

@@ -10,11 +10,15 @@
 //                and read straight from memory (a few hundred KB at the
 //                paper's sizes, L2-resident), the lane sums combined by a
 //                fixed tree of shuffles; lane 0 forms the acceleration, the
-//                F3 half-kick, the kinetic energy and the energy share;
-//   k_pm_update  one workgroup: the step's kinetic and potential energies in
-//                a fixed order, the record, the Berendsen factor, and for
-//                every molecule F4 and the next step's F2 with the boundary
-//                trace.
+//                F3 half-kick, the kinetic energy, the energy share and
+//                whether the molecule is in the pore;
+//   k_pm_update  one workgroup per 256 molecules: each sums the step's
+//                energies and the pore's sums in the same fixed order (so
+//                all find the same Berendsen factor), workgroup 0 writes the
+//                record, and each does F4 and the next step's F2 with the
+//                boundary trace for its molecules.
+// (One workgroup doing the per-molecule work for all molecules took 14-25 us
+// a step; a third launch for it cost more in launch rate than it saved.)
 // This file shares nothing with the cell-list path or the all-pairs entry.
 #include <hip/hip_runtime.h>
 
@@ -54,7 +58,6 @@ hipError_t pm_scratch_ptr(double** out)
 }
 
 constexpr int kPmLanes = 64;
-constexpr int kPmUpdate = 1024;
 
 // 1 / r^2: in FP32 the hardware estimate refined by one Newton-Raphson step
 // for the reciprocal (y + y (1 - a y)), in FP64 one division.
@@ -70,6 +73,24 @@ template <>
 __device__ __forceinline__ double pm_recip<double>(double a)
 {
     return 1.0 / a;
+}
+
+// Whether a position lies in the model's domain (pore or outer space).
+template <int D>
+__device__ bool pm_inside(const PmArgs& a, const double* p)
+{
+    const double Lw[3] = {a.lx, a.ly, a.lz};
+    bool in;
+    if (p[0] >= 0.0 && p[0] < a.lx) {
+        in = true;
+#pragma unroll
+        for (int k = 1; k < D; ++k) in = in && p[k] >= 0.0 && p[k] <= Lw[k];
+    } else {
+        in = p[0] >= a.lx && p[0] < (a.k + 1.0) * a.lx;
+#pragma unroll
+        for (int k = 1; k < D; ++k) in = in && p[k] >= -a.k * Lw[k] && p[k] < (a.k + 1.0) * Lw[k];
+    }
+    return in;
 }
 
 // Forces (F1) at the current positions, then with KICK the F3 half-kick;
@@ -131,6 +152,7 @@ __global__ void __launch_bounds__(kPmLanes) k_pm_forces(const double* __restrict
         w.ke[i] = 0.5 * a.mass * ke;
         w.u[i] = 0.5 * us;
         w.vir[i] = 0.5 * ws;
+        w.where[i] = (xi[0] < a.lx ? 1.0 : 0.0) + (pm_inside<D>(a, xi) ? 0.0 : 2.0);
     }
 }
 
@@ -216,32 +238,14 @@ __device__ int pm_trace(const PmArgs& a, double* p, double* dl, double* v)
     return -1;
 }
 
-// Whether a position lies in the model's domain (pore or outer space).
-template <int D>
-__device__ bool pm_inside(const PmArgs& a, const double* p)
-{
-    const double Lw[3] = {a.lx, a.ly, a.lz};
-    bool in;
-    if (p[0] >= 0.0 && p[0] < a.lx) {
-        in = true;
-#pragma unroll
-        for (int k = 1; k < D; ++k) in = in && p[k] >= 0.0 && p[k] <= Lw[k];
-    } else {
-        in = p[0] >= a.lx && p[0] < (a.k + 1.0) * a.lx;
-#pragma unroll
-        for (int k = 1; k < D; ++k) in = in && p[k] >= -a.k * Lw[k] && p[k] < (a.k + 1.0) * Lw[k];
-    }
-    return in;
-}
-
 // Fixed-order workgroup sums of K values at once: each wave combines its
 // lanes by a fixed tree of shuffles, then the waves' sums are added in wave
 // order; every thread receives the K totals.
-template <int K>
+template <int K, int B = kPmDrift>
 __device__ void pm_block_sums(double (&v)[K], double* red)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    constexpr int kWaves = kPmUpdate / 64;
+    constexpr int kWaves = B / 64;
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) {
 #pragma unroll
@@ -261,95 +265,99 @@ __device__ void pm_block_sums(double (&v)[K], double* red)
     __syncthreads();
 }
 
-// End of step `step` (0 = the initial state): the energies (kinetic energy of
-// the F3 velocities, pair energy at the current positions), the pressure in
-// the pore (Sec. 2: P = (2 K + W) / (d V) over the molecules in the pore,
-// V the pore's volume, W their shares of the pair virials), the record, and
-// then, for every molecule, F4 (Berendsen scaling, steps >= 1 with a
-// thermostat) and, with drift, the next step's F2: dl = v dt + a dt^2 / 2,
-// v <- v + a dt / 2, the molecule carried along dl through the boundaries.
+// End of step `step` (0 = the initial state), one workgroup per 256
+// molecules.  Every workgroup sums, in the same fixed order, the step's
+// energies (kinetic energy of the F3 velocities, pair energy at the current
+// positions), the pore's K and W (Sec. 2: P = (2 K + W) / (d V) over the
+// molecules in the pore, V the pore's volume, W their shares of the pair
+// virials) and the previous step's drift counts, so each finds the same
+// Berendsen factor without another launch; workgroup 0 writes the record
+// and the run's counters.  Then each workgroup does, for its molecules, F4
+// (v <- lambda v, steps >= 1 with a thermostat) and, with drift, the next
+// step's F2: dl = v dt + a dt^2 / 2, v <- v + a dt / 2, the molecule carried
+// along dl through the boundaries; its counts of reflections and failed
+// traces go to the slot of this step's parity.  nprev: workgroups of the
+// previous launch (0 at step 0).
 template <int D>
-__global__ void __launch_bounds__(kPmUpdate) k_pm_update(double* __restrict__ x, double* __restrict__ v,
-                                                        PmWork w, PmArgs a, long long step, int rec_row,
-                                                        int thermo, int drift, PmRecord* __restrict__ rec)
+__global__ void __launch_bounds__(kPmDrift) k_pm_update(double* __restrict__ x, double* __restrict__ v, PmWork w,
+                                                       PmArgs a, long long step, int rec_row, int thermo,
+                                                       int drift, int nprev, PmRecord* __restrict__ rec)
 {
-    __shared__ double red[6 * (kPmUpdate / 64)];
-    const int tid = threadIdx.x;
+    __shared__ double red[8 * (kPmDrift / 64)];
+    const int tid = threadIdx.x, nb = (int)gridDim.x;
     double ke = 0.0, pe = 0.0, np = 0.0, out = 0.0, kp = 0.0, wp = 0.0;
-    for (int i = tid; i < a.n; i += kPmUpdate) {
-        const double kei = w.ke[i];
+    for (int i = tid; i < a.n; i += kPmDrift) {
+        const double kei = w.ke[i], wh = w.where[i];
         ke += kei;
         pe += w.u[i];
-        double p[D];
-#pragma unroll
-        for (int k = 0; k < D; ++k) p[k] = x[(size_t)D * i + k];
-        if (p[0] < a.lx) {
-            np += 1.0;
-            kp += kei;
-            wp += w.vir[i];
-        }
-        out += pm_inside<D>(a, p) ? 0.0 : 1.0;
+        const bool pore = wh == 1.0 || wh == 3.0;
+        np += pore ? 1.0 : 0.0;
+        kp += pore ? kei : 0.0;
+        wp += pore ? w.vir[i] : 0.0;
+        out += wh >= 2.0 ? 1.0 : 0.0;
     }
-    double sums[6] = {ke, pe, np, out, kp, wp};
-    pm_block_sums<6>(sums, red);
-    ke = sums[0];
-    pe = sums[1];
-    np = sums[2];
-    out = sums[3];
-    kp = sums[4];
-    wp = sums[5];
-    const double T = a.n > 0 ? 2.0 * ke / ((double)D * (double)a.n) : 0.0;
-    if (tid == 0 && rec_row >= 0) {
-        PmRecord r;
-        r.step = step;
-        r.ke = ke;
-        r.pe = pe;
-        r.etotal = ke + pe;
-        r.temperature = T;
-        r.pressure = (2.0 * kp + wp) / ((double)D * a.vol);
-        r.n_pore = (long long)np;
-        r.reflections = step == 0 ? 0LL : w.counts[0];
-        r.n_outside = (long long)out + (step == 0 ? 0LL : w.counts[1]);
-        rec[rec_row] = r;
-    }
-    const double lam = thermo && a.n > 0 ? sqrt(1.0 + (a.dt / a.tau) * (a.t0 / T - 1.0)) : 1.0;
     double refl = 0.0, bad = 0.0;
-    if (thermo || drift) {
-        for (int i = tid; i < a.n; i += kPmUpdate) {
-            double p[D], vv[D], dl[D];
+    const double* prev = w.part + 2 * (size_t)nprev * ((step + 1) & 1);
+    for (int b = tid; b < nprev; b += kPmDrift) {
+        refl += prev[b];
+        bad += prev[nprev + b];
+    }
+    double sums[8] = {ke, pe, np, out, kp, wp, refl, bad};
+    pm_block_sums<8>(sums, red);
+    const double T = a.n > 0 ? 2.0 * sums[0] / ((double)D * (double)a.n) : 0.0;
+    if (blockIdx.x == 0 && tid == 0) {
+        // the counts start with the run (no memset node: callers may capture)
+        const long long r0 = step == 0 ? 0LL : w.counts[0] + (long long)sums[6];
+        const long long r1 = step == 0 ? 0LL : w.counts[1] + (long long)sums[7];
+        w.counts[0] = r0;
+        w.counts[1] = r1;
+        if (rec_row >= 0) {
+            PmRecord r;
+            r.step = step;
+            r.ke = sums[0];
+            r.pe = sums[1];
+            r.etotal = sums[0] + sums[1];
+            r.temperature = T;
+            r.pressure = (2.0 * sums[4] + sums[5]) / ((double)D * a.vol);
+            r.n_pore = (long long)sums[2];
+            r.reflections = r0;
+            r.n_outside = (long long)sums[3] + r1;
+            rec[rec_row] = r;
+        }
+    }
+    if (!thermo && !drift) return;
+    const double lam = thermo && a.n > 0 ? sqrt(1.0 + (a.dt / a.tau) * (a.t0 / T - 1.0)) : 1.0;
+    const int i = blockIdx.x * kPmDrift + tid;
+    double cnt[2] = {0.0, 0.0};
+    if (i < a.n) {
+        double p[D], vv[D], dl[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) vv[k] = lam * v[(size_t)D * i + k];
+        if (drift) {
 #pragma unroll
             for (int k = 0; k < D; ++k) {
-                vv[k] = v[(size_t)D * i + k];
-                if (thermo) vv[k] *= lam;
+                const double ak = w.acc[(size_t)D * i + k];
+                p[k] = x[(size_t)D * i + k];
+                dl[k] = vv[k] * a.dt + 0.5 * ak * a.dt * a.dt;
+                vv[k] += a.hdt * ak;
             }
-            if (drift) {
+            const int r = pm_trace<D>(a, p, dl, vv);
+            if (r < 0)
+                cnt[1] = 1.0;
+            else
+                cnt[0] = (double)r;
 #pragma unroll
-                for (int k = 0; k < D; ++k) {
-                    const double ak = w.acc[(size_t)D * i + k];
-                    p[k] = x[(size_t)D * i + k];
-                    dl[k] = vv[k] * a.dt + 0.5 * ak * a.dt * a.dt;
-                    vv[k] += a.hdt * ak;
-                }
-                const int r = pm_trace<D>(a, p, dl, vv);
-                if (r < 0)
-                    bad += 1.0;
-                else
-                    refl += (double)r;
-#pragma unroll
-                for (int k = 0; k < D; ++k) x[(size_t)D * i + k] = p[k];
-            }
-#pragma unroll
-            for (int k = 0; k < D; ++k) v[(size_t)D * i + k] = vv[k];
+            for (int k = 0; k < D; ++k) x[(size_t)D * i + k] = p[k];
         }
+#pragma unroll
+        for (int k = 0; k < D; ++k) v[(size_t)D * i + k] = vv[k];
     }
-    double cnt[2] = {refl, bad};
+    if (!drift) return;
     pm_block_sums<2>(cnt, red);
-    refl = cnt[0];
-    bad = cnt[1];
     if (tid == 0) {
-        // the counts start with the run (no memset node: callers may capture)
-        w.counts[0] = (step == 0 ? 0LL : w.counts[0]) + (long long)refl;
-        w.counts[1] = (step == 0 ? 0LL : w.counts[1]) + (long long)bad;
+        double* cur = w.part + 2 * (size_t)nb * (step & 1);
+        cur[blockIdx.x] = cnt[0];
+        cur[nb + blockIdx.x] = cnt[1];
     }
 }
 
@@ -357,7 +365,9 @@ template <int D>
 static hipError_t pm_run_dim(const PmArgs& a, double* x, double* v, PmWork w, long long nsteps,
                              long long every, PmRecord* rec, hipStream_t s)
 {
-    const dim3 gf((unsigned)a.n), bf(kPmLanes), gu(1), bu(kPmUpdate);
+    const dim3 gf((unsigned)a.n), bf(kPmLanes);
+    const int nb = (int)pm_drift_blocks(a.n);
+    const dim3 gu((unsigned)nb), bu(kPmDrift);
     const bool thermo = a.tau > 0.0;
     int row = 0;
     if (a.n > 0) {
@@ -367,7 +377,7 @@ static hipError_t pm_run_dim(const PmArgs& a, double* x, double* v, PmWork w, lo
             hipLaunchKernelGGL((k_pm_forces<double, D, false>), gf, bf, 0, s, x, v, w, a);
     }
     hipLaunchKernelGGL(k_pm_update<D>, gu, bu, 0, s, x, v, w, a, 0LL, rec ? row++ : -1, 0,
-                       nsteps > 0 ? 1 : 0, rec);
+                       nsteps > 0 ? 1 : 0, 0, rec);
     for (long long st = 1; st <= nsteps; ++st) {
         if (a.n > 0) {
             if (a.precision == 1)
@@ -377,7 +387,7 @@ static hipError_t pm_run_dim(const PmArgs& a, double* x, double* v, PmWork w, lo
         }
         const bool record = rec && (st == nsteps || (every > 0 && st % every == 0));
         hipLaunchKernelGGL(k_pm_update<D>, gu, bu, 0, s, x, v, w, a, st, record ? row++ : -1,
-                           thermo ? 1 : 0, st < nsteps ? 1 : 0, rec);
+                           thermo ? 1 : 0, st < nsteps ? 1 : 0, nb, rec);
     }
     return hipGetLastError();
 }
