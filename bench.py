@@ -38,13 +38,9 @@ PEAK_HBM_GBS = 8000.0
 # the lists are rebuilt, not what one step launch reads and writes.  Any
 # other source, workload or tuning reports null.
 MEASURED_TRAFFIC = {
-    ("345e4388e18ffd19", 262144, 0.7, 512, 460): 92.43e6,
-    ("345e4388e18ffd19", 262144, 0.7, 256, 270): 95.93e6,
-    ("345e4388e18ffd19", 262144, 0.7, 256, 256): 98.87e6,
-    ("345e4388e18ffd19", 262144, 0.7, 256, 0): 96.84e6,
-    ("345e4388e18ffd19", 262144, 1.0, 256, 270): 101.99e6,
-    ("345e4388e18ffd19", 262144, 1.0, 512, 460): 92.76e6,
-    ("345e4388e18ffd19", 262144, 1.0, 256, 0): 102.79e6,
+    ("801981f8f6a22db4", 262144, 0.7, 512, 460): 95.73e6,
+    ("801981f8f6a22db4", 262144, 0.7, 256, 270): 99.49e6,
+    ("801981f8f6a22db4", 262144, 1.0, 512, 460): 96.01e6,
 }
 
 
