@@ -153,7 +153,57 @@ def autotune(poremd, desc, prec, trial_steps, tuning_kw):
     sk, rb, bl, ba = combos[fin[best3]]
     log("[%s] autotune choice: skin %.2f, rebuild every %d, block %d, atoms per brick %d: %.2f us/step"
         % (prec, sk, rb, bl, ba, us3[best3]))
-    return dict(skin=sk, rebin_every=rb, block=bl, brick_atoms=ba)
+    # candidates for tuning on the measured call length (see call_tune): the
+    # finalists, and the three fastest skins at the chosen shape with their
+    # period and with a period of 20 steps
+    fins = []
+    for c in [combos[i] for i in fin] + [(p[0], r, bl, ba) for p in pairs for r in (p[1], 20)]:
+        d = dict(skin=c[0], rebin_every=c[1], block=c[2], brick_atoms=c[3])
+        if d not in fins:
+            fins.append(d)
+    return dict(skin=sk, rebin_every=rb, block=bl, brick_atoms=ba, finalists=fins)
+
+
+# Timed calls shorter than this are tuned on the call itself (call_tune).
+CALL_TUNE_STEPS = 1000
+
+
+def call_tune(poremd, desc, prec, cands, steps, warmup, energy_every, reps=5):
+    """Among candidate tunings, the fastest for the measured call: every
+    pmd_step call begins with a rebuild and may stop early for a displacement
+    halt, so for a call of a few dozen steps the per-call costs outweigh the
+    steady-state rate the autotuner ranks by.  Each candidate system runs the
+    warm-up call and then `reps` timed calls of `steps` steps, synchronised
+    like the timed region; the median decides.  Untimed for the benchmark."""
+    import torch
+
+    times = []
+    for kw in cands:
+        stream = torch.cuda.Stream()
+        s = poremd.System.from_desc(desc, precision=prec,
+                                    tuning=poremd.make_tuning(energy_every=energy_every, **kw),
+                                    stream=stream.cuda_stream)
+        if warmup:
+            s.step(warmup)
+            s.sync()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            s.step(steps)
+            s.sync()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        s.close()
+        times.append(float(np.median(ts)) * 1000.0 / steps)
+    best = int(np.argmin(times))
+    log("[%s] call tuning (%d-step calls): %s" % (prec, steps, ", ".join(
+        "(%.2f, %d, %d, %d) %.2f" % (c["skin"], c["rebin_every"], c["block"], c["brick_atoms"], t)
+        for c, t in zip(cands, times))))
+    return dict(cands[best]), [dict(c, us_per_step=t) for c, t in zip(cands, times)]
 
 
 def run_path(poremd, desc, prec, steps, warmup, energy_every, tuning_kw):
@@ -578,7 +628,9 @@ def pore_sweep_leg(poremd, kinds, steps, autotune_steps, tuning_kw, precisions=(
         for prec in precisions:
             kw = dict(tuning_kw)
             if autotune_steps > 0:
-                kw.update(autotune(poremd, desc, prec, autotune_steps, tuning_kw))
+                t = autotune(poremd, desc, prec, autotune_steps, tuning_kw)
+                t.pop("finalists", None)  # the sweep times 500-step calls: steady state
+                kw.update(t)
             r = run_path(poremd, desc, prec, steps, max(steps // 10, 10), 10, kw)
             n_launch, kms = kernel_time(poremd, r["sys"], min(steps, 100))
             n = desc.n
@@ -690,10 +742,18 @@ def main():
 
     res = {}
     tuned = {}
+    call_tables = {}
     for prec in (["mixed"] if args.no_fp64 else ["mixed", "fp64"]):
         kw = dict(tkw)
         if args.autotune_steps > 0 and not (args.skin or args.rebin_every):
-            kw.update(autotune(poremd, desc, prec, args.autotune_steps, tkw))
+            t = autotune(poremd, desc, prec, args.autotune_steps, tkw)
+            fins = t.pop("finalists", None)
+            kw.update(t)
+            if fins and args.steps < CALL_TUNE_STEPS:
+                best, table = call_tune(poremd, desc, prec, [dict(t)] + [f for f in fins if f != t],
+                                        args.steps, args.warmup, args.energy_every)
+                kw.update(best)
+                call_tables[prec] = table
         tuned[prec] = kw
         r = run_path(poremd, desc, prec, args.steps, args.warmup, args.energy_every, kw)
         n_launch, kms = kernel_time(poremd, r["sys"], args.timing_steps)
@@ -757,7 +817,7 @@ def main():
                      "force_err_mixed_vs_fp64": eps_f,
                      "force_err_mixed_vs_oracle": None, "force_err_fp64_vs_oracle": None},
         "detail": {"mixed_rebuilds": m["rebuilds"], "mixed_max_list": m["max_list"],
-                   "tuning": tuned},
+                   "tuning": tuned, "call_tuning": call_tables or None},
     }
     if "fp64" in res:
         d = res["fp64"]

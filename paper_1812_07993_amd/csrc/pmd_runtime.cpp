@@ -311,8 +311,12 @@ struct Pool {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     hipStream_t cap_stream = nullptr;
-    hipGraphExec_t gexec = nullptr;
-    int g_R = 0, g_reps = 0;
+    // captured replays for the current rebuild period: gexec[0] holds one
+    // replay, gexec[1] holds kGraphReps; a call of any length launches the
+    // large one and then the small one as often as needed, so calls of
+    // different lengths never capture again
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    int g_R = 0;
     bool dirty = true;
     bool timing = false;
     double t_exit_ms = 0.0;  // duration of a step launch whose workgroups all return at once
@@ -332,8 +336,10 @@ struct Pool {
     void release()
     {
         if (stream) hipStreamSynchronize(stream);
-        if (gexec) hipGraphExecDestroy(gexec);
-        gexec = nullptr;
+        for (auto& g : gexec) {
+            if (g) hipGraphExecDestroy(g);
+            g = nullptr;
+        }
         for (auto& e : events) {
             hipEventDestroy(e.a);
             hipEventDestroy(e.b);
@@ -696,31 +702,38 @@ void fill_sys_params(SysParams& sp, const pmd_params& p, const Grid& g, const pm
                   tile_atom_bytes(p.precision));
 }
 
-// Capture `reps` replays of [rebuild, R steps] into one graph.
-int pool_capture(Pool& p, int R, int reps)
+constexpr int kGraphReps = 8;
+
+// Capture the two graphs of the rebuild period R: one replay of [rebuild,
+// R steps, commit], and kGraphReps of them.
+int pool_capture(Pool& p, int R)
 {
     GPU_LOCK;
-    if (p.gexec) {
-        // launches of the old graph may still be queued on the stream
+    if (p.gexec[0] || p.gexec[1]) {
+        // launches of the old graphs may still be queued on the stream
         HIPCHK(hipStreamSynchronize(p.stream));
-        HIPCHK(hipGraphExecDestroy(p.gexec));
-        p.gexec = nullptr;
+        for (auto& g : p.gexec) {
+            if (g) HIPCHK(hipGraphExecDestroy(g));
+            g = nullptr;
+        }
     }
     if (!p.cap_stream) HIPCHK(hipStreamCreateWithFlags(&p.cap_stream, hipStreamNonBlocking));
     const PoolDev d = p.dev();
-    HIPCHK(hipStreamBeginCapture(p.cap_stream, hipStreamCaptureModeThreadLocal));
-    for (int r = 0; r < reps; ++r) {
-        launch_rebuild(d, p.nslots, p.precision, p.cap_stream);
-        for (int k = 0; k < R; ++k) launch_step(d, k, p.precision, p.cap_stream, nullptr, nullptr);
-        launch_commit(d, p.nslots, R, p.cap_stream);
+    for (int q = 0; q < 2; ++q) {
+        const int reps = q == 0 ? 1 : kGraphReps;
+        HIPCHK(hipStreamBeginCapture(p.cap_stream, hipStreamCaptureModeThreadLocal));
+        for (int r = 0; r < reps; ++r) {
+            launch_rebuild(d, p.nslots, p.precision, p.cap_stream);
+            for (int k = 0; k < R; ++k) launch_step(d, k, p.precision, p.cap_stream, nullptr, nullptr);
+            launch_commit(d, p.nslots, R, p.cap_stream);
+        }
+        hipGraph_t g = nullptr;
+        HIPCHK(hipStreamEndCapture(p.cap_stream, &g));
+        hipError_t e = hipGraphInstantiate(&p.gexec[q], g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        HIPCHK(e);
     }
-    hipGraph_t g = nullptr;
-    HIPCHK(hipStreamEndCapture(p.cap_stream, &g));
-    hipError_t e = hipGraphInstantiate(&p.gexec, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
-    HIPCHK(e);
     p.g_R = R;
-    p.g_reps = reps;
     p.dirty = false;
     return PMD_OK;
 }
@@ -738,10 +751,9 @@ int pool_enqueue(Pool& p, int R, int use_graph, int64_t replays)
     if (replays <= 0) return PMD_OK;
     const PoolDev d = p.dev();
     if (use_graph && !p.timing) {
-        const int reps = (int)std::min<int64_t>(replays, 8);
-        if (p.dirty || !p.gexec || p.g_R != R || p.g_reps != reps) CHK(pool_capture(p, R, reps));
-        const int64_t launches = (replays + reps - 1) / reps;
-        for (int64_t g = 0; g < launches; ++g) HIPCHK(hipGraphLaunch(p.gexec, p.stream));
+        if (p.dirty || !p.gexec[0] || !p.gexec[1] || p.g_R != R) CHK(pool_capture(p, R));
+        for (int64_t g = 0; g < replays / kGraphReps; ++g) HIPCHK(hipGraphLaunch(p.gexec[1], p.stream));
+        for (int64_t g = 0; g < replays % kGraphReps; ++g) HIPCHK(hipGraphLaunch(p.gexec[0], p.stream));
         return PMD_OK;
     }
     for (int64_t r = 0; r < replays; ++r) {
