@@ -133,8 +133,9 @@ typedef struct {
  * per workgroup of the force kernels (a multiple of 64 from 64 to 1024; each
  * workgroup owns one brick of cells, sized to hold about 0.8 x block atoms
  * unless brick_atoms says otherwise); list_cap:
- * neighbour-list slots
- * per atom; energy_every: record energies every k steps (the last step of
+ * neighbour-list storage per atom in 32-bit words (a vapour partner takes
+ * half a word, a wall partner a word, each part rounded up to four words);
+ * energy_every: record energies every k steps (the last step of
  * every pmd_step call is always recorded). */
 typedef struct {
     double skin;
@@ -310,7 +311,7 @@ int pmd_debug_cells(pmd_system *sys, int32_t *cell_of_atom, int64_t n,
 int pmd_debug_pairs(pmd_system *sys, int32_t *vv, int64_t cap, int64_t *n_vv,
                     int32_t *vw, int64_t *n_vw);
 /* Number of neighbour-list rebuilds so far, and the longest list at the
- * last one. */
+ * last one (in 32-bit words, as list_cap counts them). */
 int pmd_debug_lists(pmd_system *sys, int64_t *rebuilds, int64_t *max_len);
 
 /* ---- Batching and serving ------------------------------------------------ */

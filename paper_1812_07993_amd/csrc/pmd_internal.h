@@ -17,12 +17,19 @@ constexpr int kChunk = 16;           // atoms per entry of the chunk -> system t
 constexpr int kTile = 4096;          // cells per workgroup of the cell-count scan
 constexpr int kRebuildBlock = 256;   // threads per workgroup of the per-atom rebuild kernels
 constexpr int kMaxBlock = 1024;      // largest workgroup of the brick kernels (multiple of 64)
-constexpr unsigned kIndexBits = 26;  // neighbour-list entry: index | cell-offset code << 26
+constexpr unsigned kIndexBits = 26;  // wall list entry: wall slot | neighbour-cell code << 26
 constexpr unsigned kIndexMask = (1u << kIndexBits) - 1u;
-// cell-offset code of a list's pad entries: 3 in every 2-bit field (a value
-// no neighbour cell has), whose shift -2h per axis puts the partner beyond
-// the cutoff
-constexpr unsigned kPadCode = 63u << kIndexBits;
+// Vapour list entries are 16 bits: the partner's staged-tile index relative
+// to the atom's neighbourhood base (the first staged atom of its neighbour
+// cell (-1, -1, -1); the 27 neighbour cells are consecutive tile ranges
+// after it) in the low kRelBits bits, the neighbour-cell code above them.
+constexpr unsigned kRelBits = 11;
+constexpr unsigned kRelMask = (1u << kRelBits) - 1u;
+// Neighbour-cell code q = (dx+1) + 3 (dy+1) + 9 (dz+1) in 0..26 of a list
+// entry; kPadQ marks pad entries, whose shift -2h per axis puts the partner
+// beyond the cutoff.
+constexpr unsigned kPadQ = 31u;
+constexpr unsigned kPadCode = kPadQ << kIndexBits;   // a wall pad entry's code bits
 
 enum Phase : int {
     PH_INIT = 0,  // forces not yet computed
@@ -35,8 +42,10 @@ enum Status : int {
     ST_OVERFLOW = 2,   // a neighbour list exceeded its capacity
     ST_NONFINITE = 4,  // a non-finite force or position appeared
     ST_TILE = 8,       // a brick's halo did not fit the LDS tile
-    ST_STALL = 16      // a rebuild overflowed: later rebuilds and steps wait
+    ST_STALL = 16,     // a rebuild overflowed: later rebuilds and steps wait
                        // until the host has grown the buffer and cleared this bit
+    ST_SPAN = 32       // an atom's neighbourhood in the staged tile spans more
+                       // than 2^kRelBits atoms: the bricks must shrink
 };
 
 // Per-system constants (set on the host at admission).
@@ -173,10 +182,13 @@ struct PoolDev {
     int* tmp;             // slots in arrival order
     int* tmpid;           // caller index of the atom at each arrival position
     int* cell_tmp;        // cell key of each old slot
-    // neighbour lists, entry k of slot i at ((k / 4) * vt + i) * 4 + k % 4
-    // (chunks of four entries per slot): vapour entries index the brick's
-    // staged tile, wall entries are wall slots; both carry the cell-offset
-    // code above kIndexBits.  nlist = n_vapour | n_wall << 16
+    // neighbour lists in 16-byte chunks, chunk c of slot i at bytes
+    // (c * vt + i) * 16: first the vapour entries, eight 16-bit ones per
+    // chunk (entry k at uint16 index ((k / 8) * vt + i) * 8 + k % 8), then,
+    // from chunk ceil(n_vapour / 8), the wall entries, four 32-bit ones per
+    // chunk; each part ends on a chunk boundary with pad entries.  The
+    // capacity `cap` counts 32-bit words (four per chunk).
+    // nlist = n_vapour | n_wall << 16
     unsigned* list;
     int* nlist;
     // walls

@@ -41,31 +41,40 @@ __device__ __forceinline__ int logical_block()
     return (b & 7) * q + (b >> 3);
 }
 
-// Cell-offset code of a list entry: 2 bits per axis above kIndexBits, the
-// neighbour cell's offset d in {-1, 0, 1} stored as d + 1.
-__device__ __forceinline__ unsigned offset_code(int q)
+// Storage of the neighbour lists.  Entries are kept in 16-byte chunks of
+// consecutive entries of one atom; chunk c of every slot is contiguous (16
+// bytes per slot, stride vt), so a lane's chunk is one 16-byte load, a
+// wave's chunk loads cover one contiguous 1 KB, and the list build's writes
+// of one atom fill 16-byte pieces.  Vapour entries come first, eight 16-bit
+// entries per chunk (two per 32-bit word, the lower half first); the wall
+// entries follow from the next chunk boundary, four 32-bit entries per chunk.
+
+// uint32 index of 32-bit word kw of slot i's list (four words per chunk).
+__device__ __forceinline__ size_t list_at(int vt, int i, int kw)
 {
-    return (unsigned)(q % 3) | ((unsigned)((q / 3) % 3) << 2) | ((unsigned)(q / 9) << 4);
+    return (((size_t)(kw >> 2) * vt + i) << 2) + (kw & 3);
 }
 
-// Shift -d h that moves the neighbour's cell-local coordinate into the frame
-// of the atom's cell along one axis (exactly h, 0 or -h).
+// uint16 index of vapour entry k of slot i.
+__device__ __forceinline__ size_t vlist_at(int vt, int i, int k)
+{
+    return (((size_t)(k >> 3) * vt + i) << 3) + (k & 7);
+}
+
+// Shift -d h of neighbour-cell code q (d = offset of the neighbour cell,
+// exactly h, 0 or -h per axis) that moves the neighbour's cell-local
+// coordinate into the frame of the atom's cell; the pad code gives -2h per
+// axis.
 template <typename T>
-__device__ __forceinline__ T shift_of(unsigned e, int bit, T h)
+__device__ __forceinline__ typename V4<T>::type shift_q(int q, T hx, T hy, T hz)
 {
-    const T b = (T)((e >> (kIndexBits + bit)) & 3u);
-    return fma(-b, h, h);
-}
-
-// Storage index of neighbour-list entry k of slot i.  Entries are kept in
-// chunks of four consecutive entries of one atom; chunk c of every slot is
-// contiguous (16 bytes per slot, stride vt), so a lane's four entries are one
-// 16-byte load, a wave's chunk loads cover one contiguous 1 KB, and the list
-// build's writes of one atom fill a 16-byte piece instead of one word in each
-// of four rows.  The capacity is a multiple of four entries.
-__device__ __forceinline__ size_t list_at(int vt, int i, int k)
-{
-    return (((size_t)(k >> 2) * vt + i) << 2) + (k & 3);
+    const int fx = q >= 27 ? 3 : q % 3, fy = q >= 27 ? 3 : (q / 3) % 3, fz = q >= 27 ? 3 : q / 9;
+    typename V4<T>::type v;
+    v.x = (T)(1 - fx) * hx;
+    v.y = (T)(1 - fy) * hy;
+    v.z = (T)(1 - fz) * hz;
+    v.w = (T)0;
+    return v;
 }
 
 __device__ __forceinline__ int wrap_cell(int c, int n)
@@ -538,7 +547,7 @@ __global__ void k_bin_scan_finish(PoolDev P, int nslots)
     st->sbuf ^= 1;
     st->ibuf_prev = st->ibuf;
     st->ibuf ^= 1;
-    st->status &= ~(ST_HALT | ST_OVERFLOW | ST_TILE);
+    st->status &= ~(ST_HALT | ST_OVERFLOW | ST_TILE | ST_SPAN);
     if (st->phase == PH_REST) st->phase = PH_RUN;
     st->rebins += 1;
     st->max_nbr = 0;
@@ -796,9 +805,8 @@ __device__ __forceinline__ double box_gap(double l, int d, double h)
 
 // Neighbour lists (radius r_c + skin for vapour, r_c + skin/2 for the fixed
 // walls) of the atoms of one brick, in a fixed order: neighbour cells 0..26,
-// staged order inside a cell; vapour entries first, then walls, each part
-// padded to whole chunks of four entries (list positions 0 .. nv4 - 1 for
-// vapour, nv4 .. nv4 + nw - 1 for walls, nv4 = nv rounded up to 4).  Vapour
+// staged order inside a cell; vapour entries first (16 bits each), then
+// walls (32 bits each), each part padded to whole 16-byte chunks.  Vapour
 // entries index the brick's staged tile, which the step kernel rebuilds
 // identically from the same cell tables; wall entries are wall slots.  Wall
 // candidates are read from global memory (the static wall coordinates stay
@@ -868,7 +876,28 @@ __global__ void __launch_bounds__(kMaxBlock) k_list_build(PoolDev P)
         // frame (px = me.x - dx h_x, and so on)
         const int hstr1 = g.hd[0], hstr2 = g.hd[0] * g.hd[1];
         const T hx = (T)sp.h[0], hy = (T)sp.h[1], hz = (T)sp.h[2];
+        // vapour entries are 16-bit: the partner's staged index relative to
+        // the first staged atom of neighbour cell (-1, -1, -1) (the 27 cells
+        // lie in the tile range from there to the end of cell (1, 1, 1)),
+        // with the neighbour-cell code above; a range longer than the index
+        // field stops the system until the host has shrunk its bricks
+        const int base = t.hoff[halo_cell(g, cx, cy, cz, 0)];
+        if (t.hoff[halo_cell(g, cx, cy, cz, 26) + 1] - base > (int)kRelMask + 1) {
+            P.nlist[i] = 0;
+            atomicOr(&P.st[c.s].status, ST_OVERFLOW | ST_TILE | ST_SPAN);
+            continue;
+        }
+        // two entries per 32-bit store: an even entry waits in `pend`
         int nv = 0;
+        unsigned pend = 0u;
+        auto emit = [&](unsigned v) {
+            if (nv & 1) {
+                if ((nv >> 1) < cap) P.list[list_at(vt, i, nv >> 1)] = pend | (v << 16);
+            } else {
+                pend = v;
+            }
+            ++nv;
+        };
 #pragma unroll 1
         for (int dz = -1; dz <= 1; ++dz) {
             const double gz = box_gap(lz, dz, sp.h[2]), gz2 = gz * gz;
@@ -884,7 +913,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_list_build(PoolDev P)
                     const double gx = box_gap(lx, dx, sp.h[0]);
                     if (fma(gx, gx, gyz) >= cull_v) continue;
                     const T px = me.x - (T)dx * hx;
-                    const unsigned code = offset_code((dx + 1) + 3 * (dy + 1) + 9 * (dz + 1)) << kIndexBits;
+                    const unsigned code = (unsigned)((dx + 1) + 3 * (dy + 1) + 9 * (dz + 1)) << kRelBits;
                     const int h = hs + dx + dy * hstr1 + dz * hstr2;
                     const int a1 = t.hoff[h + 1];
                     // windows of 32 candidates: the tests of a window set
@@ -916,8 +945,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_list_build(PoolDev P)
                         while (bits) {
                             const int u = __builtin_ctz(bits);
                             bits &= bits - 1u;
-                            if (nv < cap) P.list[list_at(vt, i, nv)] = (unsigned)(w0 + u) | code;
-                            ++nv;
+                            emit((unsigned)(w0 + u - base) | code);
                         }
                     }
                 }
@@ -925,9 +953,10 @@ __global__ void __launch_bounds__(kMaxBlock) k_list_build(PoolDev P)
         }
         // the vapour entries end on a chunk boundary: the rest of the last
         // chunk holds pad entries (the atom itself under the pad code), so the
-        // step kernel reads whole chunks with no per-entry length test
-        const int nv4 = (nv + 3) & ~3;
-        for (int k = nv; k < min(nv4, cap); ++k) P.list[list_at(vt, i, k)] = (unsigned)aself | kPadCode;
+        // step kernel reads whole groups with no per-entry length test
+        const int nvap = nv;
+        const int nvw = ((nv + 7) >> 3) << 2;  // 32-bit words of the vapour part
+        while (nv < 2 * nvw) emit((unsigned)(aself - base) | (kPadQ << kRelBits));
         int nw = 0;
         unsigned lastw = 0;
 #pragma unroll 1
@@ -948,7 +977,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_list_build(PoolDev P)
                     const int w0c = wrange[2 * h], w1 = wrange[2 * h + 1];
                     if (w0c >= w1) continue;
                     const T px = me.x - (T)dx * hx;
-                    const unsigned code = offset_code((dx + 1) + 3 * (dy + 1) + 9 * (dz + 1)) << kIndexBits;
+                    const unsigned code = (unsigned)((dx + 1) + 3 * (dy + 1) + 9 * (dz + 1)) << kIndexBits;
                     // windows of two rounds of kWallRound candidates (loads
                     // of a round issued together, indices clamped to the
                     // cell's last wall): tests into a mask, then the hits
@@ -972,7 +1001,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_list_build(PoolDev P)
                             const int u = __builtin_ctz(bits);
                             bits &= bits - 1u;
                             const unsigned w = (unsigned)(w0 + u);
-                            if (nv4 + nw < cap) P.list[list_at(vt, i, nv4 + nw)] = w | code;
+                            if (nvw + nw < cap) P.list[list_at(vt, i, nvw + nw)] = w | code;
                             lastw = w;
                             ++nw;
                         }
@@ -980,12 +1009,13 @@ __global__ void __launch_bounds__(kMaxBlock) k_list_build(PoolDev P)
                 }
             }
         }
-        // the wall entries start at chunk nv4 / 4 and end on a chunk boundary
-        // too (pads: the last wall entry's slot under the pad code)
-        const int nt = nv4 + ((nw + 3) & ~3);
-        for (int k = nv4 + nw; k < min(nt, cap); ++k) P.list[list_at(vt, i, k)] = lastw | kPadCode;
+        // the wall entries start at word nvw (a chunk boundary) and end on a
+        // chunk boundary too (pads: the last wall entry's slot under the pad
+        // code); nt counts 32-bit words
+        const int nt = nvw + ((nw + 3) & ~3);
+        for (int k = nvw + nw; k < min(nt, cap); ++k) P.list[list_at(vt, i, k)] = lastw | kPadCode;
         const bool ok = nt <= cap;
-        P.nlist[i] = ok ? (nv | (nw << 16)) : 0;
+        P.nlist[i] = ok ? (nvap | (nw << 16)) : 0;
         mx = max(mx, nt);
     }
     mx = wave_max(mx);
@@ -1212,21 +1242,34 @@ __device__ __forceinline__ void pair_term(const StepCtx<T>& x, Acc& a, T dx, T d
 
 // List entry k of atom i if its FP32 r^2 lies within the band around the
 // cutoff: the pair is decided on the FP64 master positions.
+// List position k of atom i: vapour entry k for k < nvap, else wall entry
+// k - nvap (whose words start at word nvw); base is the atom's neighbourhood
+// base in the staged tile.
 template <typename T, bool VIR>
 __device__ __forceinline__ void edge_entry(const PoolDev& P, const SysParams& sp, const StepCtx<T>& x,
-                                           const Tile<T>& tl, int i, int k, int nvap,
-                                           const typename V4<T>::type& me, double xi, double yi,
-                                           double zi, Acc& a)
+                                           const Tile<T>& tl, const typename V4<T>::type* lut, int i,
+                                           int k, int nvap, int base, const typename V4<T>::type& me,
+                                           double xi, double yi, double zi, Acc& a)
 {
     using V = typename V4<T>::type;
     const int vt = P.vt;
-    const unsigned e = P.list[list_at(vt, i, k)];
     const bool wall = k >= nvap;
-    const int ai = (int)(e & kIndexMask);
+    int ai, q;
+    if (wall) {
+        const int nvw = ((nvap + 7) >> 3) << 2;
+        const unsigned e = P.list[list_at(vt, i, nvw + k - nvap)];
+        ai = (int)(e & kIndexMask);
+        q = (int)(e >> kIndexBits);
+    } else {
+        const unsigned e = ((const unsigned short*)P.list)[vlist_at(vt, i, k)];
+        ai = base + (int)(e & kRelMask);
+        q = (int)(e >> kRelBits);
+    }
     const V o = wall ? x.Lc[vt + ai] : tl.pos[ai];
-    const T dx = me.x - o.x + shift_of<T>(e, 0, x.hx);
-    const T dy = me.y - o.y + shift_of<T>(e, 2, x.hy);
-    const T dz = me.z - o.z + shift_of<T>(e, 4, x.hz);
+    const V sh = lut[q];
+    const T dx = me.x - o.x + sh.x;
+    const T dy = me.y - o.y + sh.y;
+    const T dz = me.z - o.z + sh.z;
     const T r2 = dx * dx + dy * dy + dz * dz;
     if (!(fabs(r2 - x.rc2) < x.band)) return;
     double ox, oy, oz;
@@ -1251,24 +1294,23 @@ __device__ __forceinline__ void edge_entry(const PoolDev& P, const SysParams& sp
 // around the cutoff), decided on the FP64 master positions and added in list
 // order.  The loops record the list positions of the last two such entries
 // (k0 the later one; ne counts them all); only an atom with more than two
-// rescans its list (vapour positions 0 .. nvap - 1, walls from the chunk
-// boundary nv4 on).
+// rescans its list (positions 0 .. nvap - 1 for the vapour entries, nvap on
+// for the wall entries).
 template <typename T, bool VIR>
 __device__ void edge_pass(const PoolDev& P, const SysParams& sp, const StepCtx<T>& x,
-                          const Tile<T>& tl, int i, int nvap, int nwal, int ne, int k0, int k1,
-                          Acc& a)
+                          const Tile<T>& tl, const typename V4<T>::type* lut, int i, int nvap, int nwal,
+                          int base, int ne, int k0, int k1, Acc& a)
 {
     const int vt = P.vt;
     const typename V4<T>::type me = x.Lc[i];
     const double xi = x.X[i], yi = x.X[vt + i], zi = x.X[2 * vt + i];
     if (ne <= 2) {
-        if (ne == 2) edge_entry<T, VIR>(P, sp, x, tl, i, k1, nvap, me, xi, yi, zi, a);
-        edge_entry<T, VIR>(P, sp, x, tl, i, k0, nvap, me, xi, yi, zi, a);
+        if (ne == 2) edge_entry<T, VIR>(P, sp, x, tl, lut, i, k1, nvap, base, me, xi, yi, zi, a);
+        edge_entry<T, VIR>(P, sp, x, tl, lut, i, k0, nvap, base, me, xi, yi, zi, a);
         return;
     }
-    const int nv4 = (nvap + 3) & ~3;
-    for (int k = 0; k < nvap; ++k) edge_entry<T, VIR>(P, sp, x, tl, i, k, nvap, me, xi, yi, zi, a);
-    for (int k = nv4; k < nv4 + nwal; ++k) edge_entry<T, VIR>(P, sp, x, tl, i, k, nvap, me, xi, yi, zi, a);
+    for (int k = 0; k < nvap + nwal; ++k)
+        edge_entry<T, VIR>(P, sp, x, tl, lut, i, k, nvap, base, me, xi, yi, zi, a);
 }
 
 // What a lane reads of its atom before the pair loops: the local position,
@@ -1280,6 +1322,7 @@ template <typename T>
 struct AtomIn {
     typename V4<T>::type me;
     int nl;
+    int cr;  // packed cell coordinates (the neighbourhood base in the tile follows from them)
     uint4 c0;
 };
 
@@ -1290,6 +1333,7 @@ __device__ __forceinline__ AtomIn<T> atom_in(const PoolDev& P, const StepCtx<T>&
     AtomIn<T> r;
     r.me = x.Lc[i];
     r.nl = P.nlist[i];
+    r.cr = P.cref[i];
     r.c0 = ((const uint4*)P.list)[i];  // chunk 0 of slot i
     (void)vt;
     return r;
@@ -1418,39 +1462,6 @@ __device__ void step_reduce(const PoolDev& P, const SysParams& sp, int s, int b,
     }
 }
 
-// Shift -d h of every 6-bit cell-offset code (2 bits per axis, d + 1 in
-// {0, 1, 2}; a field of 3 occurs only in the pad code, shift -2h): one LDS
-// read per list entry instead of decoding the three fields.
-template <typename T>
-__device__ __forceinline__ typename V4<T>::type shift_lut_entry(int q, T hx, T hy, T hz)
-{
-    typename V4<T>::type v;
-    v.x = fma(-(T)(q & 3), hx, hx);
-    v.y = fma(-(T)((q >> 2) & 3), hy, hy);
-    v.z = fma(-(T)((q >> 4) & 3), hz, hz);
-    v.w = (T)0;
-    return v;
-}
-
-// Shift of a list entry's cell-offset code: from the LDS table in FP32 (one
-// read), decoded arithmetically in FP64 (where a table of double4 would hold
-// too many registers per group of entries).
-template <typename T>
-__device__ __forceinline__ typename V4<T>::type shift_at(const typename V4<T>::type* lut, unsigned e,
-                                                         const StepCtx<T>& x)
-{
-    if constexpr (sizeof(T) == 4) {
-        return lut[e >> kIndexBits];
-    } else {
-        typename V4<T>::type v;
-        v.x = shift_of<T>(e, 0, x.hx);
-        v.y = shift_of<T>(e, 2, x.hy);
-        v.z = shift_of<T>(e, 4, x.hz);
-        v.w = (T)0;
-        return v;
-    }
-}
-
 // A list entry in the band around the cutoff: counted, and the list
 // positions of the last two kept (k0 the latest) for the pass that decides
 // them in FP64.
@@ -1518,8 +1529,9 @@ __device__ __forceinline__ void pair_masked(const StepCtx<T>& x, Acc& a, T dx, T
 // with VIR the virial sums and the pore's sums too).
 template <typename T, bool VIR, bool DOE>
 __device__ __forceinline__ void step_atoms(PoolDev& P, const SysParams& sp, const StepCtx<T>& x,
-                                           const Tile<T>& tl, const typename V4<T>::type* lut, int i0,
-                                           int i1, const AtomIn<T>& first, Acc& a, double& ke, double& lwv,
+                                           const HaloGeo& g, const Tile<T>& tl,
+                                           const typename V4<T>::type* lut, int i0, int i1,
+                                           const AtomIn<T>& first, Acc& a, double& ke, double& lwv,
                                            double& lkp, double& lwp, double& lnp, int& flags)
 {
     using V = typename V4<T>::type;
@@ -1531,40 +1543,38 @@ __device__ __forceinline__ void step_atoms(PoolDev& P, const SysParams& sp, cons
         const int nvap = nl & 0xFFFF;
         a.fx = a.fy = a.fz = 0.0;
         if constexpr (VIR) a.wv = 0.0;
-        // entries come in chunks of four (one 16-byte load each): one chunk
-        // per vapour group, kGroupW<T> / 4 per wall group; the next group's
-        // chunks are in flight while the current one is evaluated, and a
-        // group's partner positions (from LDS for vapour, from global memory
-        // for walls) and shifts are all read before any is used.  Each part
-        // of the list ends on a chunk boundary with pad entries whose shift
-        // puts the partner beyond the cutoff, so no entry needs a length
-        // test.  Pairs whose FP32 r^2 lies within a narrow band around the
-        // cutoff are left out here and decided in FP64 after the whole list
-        // (a rare slow path: a few atoms per step).  Chunk loads past the end
-        // of this atom's list are clamped to the capacity and their values
-        // are not used, so the code is straight-line and each wait covers
-        // only the loads it needs
+        // entries come in 16-byte chunks (one load each): eight 16-bit
+        // vapour entries (two groups) or four 32-bit wall entries per chunk,
+        // kGroupW<T> / 4 chunks per wall group; the next chunk is in flight
+        // while the current one is evaluated, and a group's partner
+        // positions (from LDS for vapour, from global memory for walls) and
+        // shifts are all read before any is used.  Each part of the list
+        // ends on a chunk boundary with pad entries whose shift puts the
+        // partner beyond the cutoff, so no entry needs a length test.  Pairs
+        // whose FP32 r^2 lies within a narrow band around the cutoff are left
+        // out here and decided in FP64 after the whole list (a rare slow
+        // path: a few atoms per step).  Chunk loads past the end of this
+        // atom's list are clamped to the capacity and their values are not
+        // used, so the code is straight-line and each wait covers only the
+        // loads it needs
         int ne = 0, ke0 = 0, ke1 = 0;  // cutoff-band entries: count, last two list positions
-        const int nv4 = (nvap + 3) & ~3, nwal = nl >> 16;
+        const int nwal = nl >> 16;
         const int lastchunk = P.cap / 4 - 1;
         const uint4* lst4 = (const uint4*)P.list + i;  // chunk c of this atom at lst4[c * vt]
-        static_assert(kGroupV == 4, "the vapour loop takes one 16-byte chunk per group");
-        // one group of four vapour entries (one chunk) at list position k; a
-        // vapour entry's tile index is below 2^22, so e >> 22 is its code
-        // times 16, the byte offset of its shift in the table
-        auto vapour_group = [&](const uint4 c, int k) {
-            const unsigned ec[4] = {c.x, c.y, c.z, c.w};
+        // the atom's neighbourhood in the tile starts at the first staged
+        // atom of its neighbour cell (-1, -1, -1)
+        const V* posb = tl.pos + tl.hoff[halo_cell(g, in.cr & 1023, (in.cr >> 10) & 1023, in.cr >> 20, 0)];
+        static_assert(kGroupV == 4, "the vapour loop takes half a 16-byte chunk per group");
+        // one group of four vapour entries (two 32-bit words of a chunk) at
+        // list position k
+        auto vapour_group = [&](const unsigned w0, const unsigned w1, int k) {
+            const unsigned ec[4] = {w0 & 0xFFFFu, w0 >> 16, w1 & 0xFFFFu, w1 >> 16};
             V o[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) o[u] = tl.pos[ec[u] & kIndexMask];
+            for (int u = 0; u < 4; ++u) o[u] = posb[ec[u] & kRelMask];
             V sh[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                if constexpr (sizeof(T) == 4)
-                    sh[u] = *(const V*)((const char*)lut + (ec[u] >> (kIndexBits - 4)));
-                else
-                    sh[u] = shift_at<T>(lut, ec[u], x);
-            }
+            for (int u = 0; u < 4; ++u) sh[u] = lut[ec[u] >> kRelBits];
             bool nr[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -1582,20 +1592,25 @@ __device__ __forceinline__ void step_atoms(PoolDev& P, const SysParams& sp, cons
         // asm with a memory clobber keeps the compiler from folding the
         // prefetched load and the first one into a single load at the top)
         uint4 ca = in.c0, cb;
-        for (int k0 = 0; k0 < nv4; k0 += 8) {
-            cb = lst4[(size_t)min((k0 >> 2) + 1, lastchunk) * vt];
+        for (int k0 = 0; k0 < nvap; k0 += 16) {
+            cb = lst4[(size_t)min((k0 >> 3) + 1, lastchunk) * vt];
             asm volatile("" ::: "memory");
-            vapour_group(ca, k0);
-            if (k0 + 4 >= nv4) break;
-            ca = lst4[(size_t)min((k0 >> 2) + 2, lastchunk) * vt];
+            vapour_group(ca.x, ca.y, k0);
+            if (k0 + 4 >= nvap) break;
+            vapour_group(ca.z, ca.w, k0 + 4);
+            if (k0 + 8 >= nvap) break;
+            ca = lst4[(size_t)min((k0 >> 3) + 2, lastchunk) * vt];
             asm volatile("" ::: "memory");
-            vapour_group(cb, k0 + 4);
+            vapour_group(cb.x, cb.y, k0 + 8);
+            if (k0 + 12 >= nvap) break;
+            vapour_group(cb.z, cb.w, k0 + 12);
         }
         if (nwal > 0) {
-            // wall chunks c0 .. c0 + ncw - 1; a group's chunks past the last
-            // one take the group's first entry under the pad code
+            // wall chunks c0 .. c0 + ncw - 1 (c0: the first chunk after the
+            // vapour part); a group's chunks past the last one take the
+            // group's first entry under the pad code
             constexpr int G = kGroupW<T> / 4;
-            const int c0 = nv4 >> 2, ncw = (nwal + 3) >> 2;
+            const int c0 = (nvap + 7) >> 3, ncw = (nwal + 3) >> 2;
             const V* Lw = x.Lc + vt;
             uint4 cw[G];
 #pragma unroll
@@ -1618,7 +1633,7 @@ __device__ __forceinline__ void step_atoms(PoolDev& P, const SysParams& sp, cons
                 bool nr[kGroupW<T>];
 #pragma unroll
                 for (int u = 0; u < kGroupW<T>; ++u) {
-                    const V sw = shift_at<T>(lut, e[u], x);
+                    const V sw = lut[e[u] >> kIndexBits];
                     const T dx = me.x - ow[u].x + sw.x;
                     const T dy = me.y - ow[u].y + sw.y;
                     const T dz = me.z - ow[u].z + sw.z;
@@ -1626,10 +1641,11 @@ __device__ __forceinline__ void step_atoms(PoolDev& P, const SysParams& sp, cons
                     nr[u] = sizeof(T) == 4 && fabs(r2 - x.rc2) < x.band;
                     pair_masked<T, VIR, DOE>(x, a, dx, dy, dz, r2, r2 < x.rc2 && !nr[u], true);
                 }
-                note_group<kGroupW<T>>(nr, ne, ke0, ke1, nv4 + 4 * c);
+                note_group<kGroupW<T>>(nr, ne, ke0, ke1, nvap + 4 * c);
             }
         }
-        if (ne) edge_pass<T, VIR>(P, sp, x, tl, i, nvap, nwal, ne, ke0, ke1, a);
+        if (ne)
+            edge_pass<T, VIR>(P, sp, x, tl, lut, i, nvap, nwal, (int)(posb - tl.pos), ne, ke0, ke1, a);
         const double kei = atom_epilogue<T>(P, x, i, a, flags);
         ke += kei;
         if constexpr (VIR && DOE) {
@@ -1668,9 +1684,10 @@ __device__ __forceinline__ void step_body(PoolDev& P, int kk)
     }
     const HaloGeo g = halo_geo(sp, c.b);
     Tile<T> tl = tile_of<T>(smem, P);
-    // shift of each cell-offset code (made visible by the staging's barriers)
-    __shared__ V lut[sizeof(T) == 4 ? 64 : 1];
-    if (sizeof(T) == 4 && tid < 64) lut[tid] = shift_lut_entry<T>(tid, x.hx, x.hy, x.hz);
+    // shift of each neighbour-cell code (made visible by the staging's
+    // barriers): one LDS read per list entry instead of decoding the code
+    __shared__ V lut[32];
+    if (tid < 32) lut[tid] = shift_q<T>(tid, x.hx, x.hy, x.hz);
     const int key0 = c.b * sp.bcells;
     const int i0 = P.cstart[sp.coff + key0], i1 = P.cstart[sp.coff + key0 + sp.bcells];
     // the lane's first atom: its loads are in flight during the staging
@@ -1690,9 +1707,9 @@ __device__ __forceinline__ void step_body(PoolDev& P, int kk)
     // choice between two builds of the pair loops
     if (tot >= 0) {
         if (x.doE)
-            step_atoms<T, VIR, true>(P, sp, x, tl, lut, i0, i1, first, a, ke, lwv, lkp, lwp, lnp, flags);
+            step_atoms<T, VIR, true>(P, sp, x, g, tl, lut, i0, i1, first, a, ke, lwv, lkp, lwp, lnp, flags);
         else
-            step_atoms<T, VIR, false>(P, sp, x, tl, lut, i0, i1, first, a, ke, lwv, lkp, lwp, lnp, flags);
+            step_atoms<T, VIR, false>(P, sp, x, g, tl, lut, i0, i1, first, a, ke, lwv, lkp, lwp, lnp, flags);
     }
     // vapour pairs were met from both atoms: half of each sum (and each
     // pair's virial is shared equally by its two molecules)
@@ -1999,12 +2016,14 @@ __global__ void k_debug_pairs(PoolDev P, int slot, int* out, int cap, int* count
     const int i0 = P.cstart[sp.coff + key0], i1 = P.cstart[sp.coff + key0 + sp.bcells];
     for (int i = i0 + (int)threadIdx.x; i < i1; i += blockDim.x) {
         const int nl = P.nlist[i];
-        const int nvap = nl & 0xFFFF, nv4 = (nvap + 3) & ~3, n = nv4 + (nl >> 16);
+        const int nvap = nl & 0xFFFF, nvw = ((nvap + 7) >> 3) << 2, n = nvap + (nl >> 16);
         const double xi = X[i], yi = X[vt + i], zi = X[2 * vt + i];
+        const int cr = P.cref[i];
+        const int base = t.hoff[halo_cell(g, cr & 1023, (cr >> 10) & 1023, cr >> 20, 0)];
         for (int k = 0; k < n; ++k) {
-            if (k >= nvap && k < nv4) continue;  // the vapour part's pad entries
-            const unsigned e = P.list[list_at(vt, i, k)];
-            const int a = (int)(e & kIndexMask);
+            const int a = k >= nvap
+                ? (int)(P.list[list_at(vt, i, nvw + k - nvap)] & kIndexMask)
+                : base + (int)(((const unsigned short*)P.list)[vlist_at(vt, i, k)] & kRelMask);
             double ox, oy, oz;
             int kind, bb;
             if (k >= nvap) {

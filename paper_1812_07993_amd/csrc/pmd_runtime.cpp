@@ -594,9 +594,15 @@ int pool_layout(Pool& p)
     return PMD_OK;
 }
 
+// Staged-tile range of one atom's 27 neighbour cells in a brick of halo
+// dimensions hx x hy x hz: from cell (-1, -1, -1) to cell (1, 1, 1) in the
+// halo's x-fastest order (two planes, two rows and three cells of the halo).
+int span_cells(int hx, int hy) { return 2 * hx * hy + 2 * hx + 3; }
+
 // Brick shape: the largest brick (at most 8 cells per axis) whose expected
-// atom count fits `target` and whose halo box, at 1.3 times the mean
-// occupancy (room for density fluctuations), fits the LDS tile; near-cubic
+// atom count fits `target`, whose halo box fits the LDS tile and whose
+// neighbourhood range fits a vapour list entry's index field, both at 1.3
+// times the mean occupancy (room for density fluctuations); near-cubic
 // shapes (smallest halo per cell) are preferred.  `target` scales with the
 // workgroup size.
 void choose_bricks(SysParams& sp, double target, size_t atom_bytes)
@@ -612,6 +618,7 @@ void choose_bricks(SysParams& sp, double target, size_t atom_bytes)
                 const int H = (bx + 2) * (by + 2) * (bz + 2);
                 const double fit = (double)(kTileBytesMax - (size_t)(2 * H + 1) * 4) / atom_bytes;
                 if (1.3 * H * occ > fit && P > 1) continue;
+                if (1.3 * span_cells(bx + 2, by + 2) * occ > kRelMask + 1 && P > 1) continue;
                 const double halo = (double)(bx + 2) * (by + 2) * (bz + 2) / P;
                 const double score = P - 0.01 * halo;
                 if (score > best_score) {
@@ -641,13 +648,15 @@ int key_capacity(const Grid& g) { return (g.nc[0] + 7) * (g.nc[1] + 7) * (g.nc[2
 int key_capacity(const SysParams& sp) { return (sp.nc[0] + 7) * (sp.nc[1] + 7) * (sp.nc[2] + 7) + 2; }
 
 // A brick's halo overflowed the LDS tile: grow the tile up to its limit,
-// then shrink the system's bricks.  The next rebuild uses the new layout.
-int pool_fix_tile(Pool& p, int slot)
+// then shrink the system's bricks.  An atom's neighbourhood range that
+// overflowed a vapour list entry's index field (status ST_SPAN) shrinks the
+// bricks at once.  The next rebuild uses the new layout.
+int pool_fix_tile(Pool& p, int slot, int status)
 {
     const size_t ab = tile_atom_bytes(p.precision);
     const size_t ints = (size_t)(2 * p.hmax + 1) * 4;
     const int lds_max = (int)((kTileBytesMax - std::min(ints, kTileBytesMax / 2)) / ab);
-    if (p.lds_atoms < lds_max) {
+    if (p.lds_atoms < lds_max && !(status & ST_SPAN)) {
         p.lds_atoms = std::min(lds_max, 2 * p.lds_atoms);
         p.dirty = true;
         return PMD_OK;
@@ -844,7 +853,7 @@ int sys_sync(pmd_system* s)
             return fail(PMD_ENUMERIC, "non-finite force or position at step %lld", (long long)st.step);
         if (st.remaining <= 0) return PMD_OK;
         if (st.status & ST_TILE) {
-            CHK(pool_fix_tile(p, s->slot));
+            CHK(pool_fix_tile(p, s->slot, st.status));
         } else if (st.status & ST_OVERFLOW) {
             const int need = round_up(std::max(st.max_nbr + st.max_nbr / 4 + 8, p.cap + 16), 16);
             if (need > 4096) return fail(PMD_ENOMEM, "neighbour list needs %d entries per atom", need);
@@ -899,7 +908,7 @@ int load_state(pmd_system* sys, const double* pos, const double* vel, int64_t st
         if (st.status & ST_NONFINITE) return fail(PMD_ENUMERIC, "non-finite initial forces");
         if (st.phase == PH_REST) return PMD_OK;
         if (st.status & ST_TILE) {
-            CHK(pool_fix_tile(q, slot));
+            CHK(pool_fix_tile(q, slot, st.status));
         } else if (st.status & ST_OVERFLOW) {
             const int need = round_up(std::max(st.max_nbr + st.max_nbr / 4 + 8, q.cap), 16);
             if (need > 4096) return fail(PMD_ENOMEM, "neighbour list needs %d entries", need);
@@ -2207,7 +2216,7 @@ static int batch_poll_impl(pmd_batch* b, int* done, int cap, int* n_done, bool w
     for (int s = 0; s < p.nslots; ++s) {
         if (!b->resident[s]) continue;
         if (st[s].status & ST_TILE) {
-            CHK(pool_fix_tile(p, s));
+            CHK(pool_fix_tile(p, s, st[s].status));
         } else if (st[s].status & ST_OVERFLOW) {
             grow = true;
             need = std::max(need, st[s].max_nbr + st[s].max_nbr / 4 + 8);
