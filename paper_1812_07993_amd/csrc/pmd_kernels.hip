@@ -870,10 +870,10 @@ __global__ void __launch_bounds__(kMaxBlock) k_list_build(PoolDev P)
         const int hs = halo_cell(g, cx, cy, cz, 13);
         const int aself = t.hoff[hs] + (i - t.hbeg[hs]);
         // neighbour cells in the order q = (dx+1) + 3 (dy+1) + 9 (dz+1), as
-        // nested z, y, x loops: each level culls with the partial box gap of
-        // the levels above it (a whole plane or row of cells at once) and
-        // carries the atom's coordinate shifted into the neighbour cell's
-        // frame (px = me.x - dx h_x, and so on)
+        // nested z, y loops over rows of three cells: each level culls with
+        // the partial box gap of the levels above it (a whole plane or row of
+        // cells at once) and carries the atom's coordinate shifted into the
+        // neighbour cell's frame (px = me.x - dx h_x, and so on)
         const int hstr1 = g.hd[0], hstr2 = g.hd[0] * g.hd[1];
         const T hx = (T)sp.h[0], hy = (T)sp.h[1], hz = (T)sp.h[2];
         // vapour entries are 16-bit: the partner's staged index relative to
@@ -908,45 +908,51 @@ __global__ void __launch_bounds__(kMaxBlock) k_list_build(PoolDev P)
                 const double gy = box_gap(ly, dy, sp.h[1]), gyz = fma(gy, gy, gz2);
                 if (gyz >= cull_v) continue;
                 const T py = me.y - (T)dy * hy;
-#pragma unroll 1
-                for (int dx = -1; dx <= 1; ++dx) {
-                    const double gx = box_gap(lx, dx, sp.h[0]);
-                    if (fma(gx, gx, gyz) >= cull_v) continue;
-                    const T px = me.x - (T)dx * hx;
-                    const unsigned code = (unsigned)((dx + 1) + 3 * (dy + 1) + 9 * (dz + 1)) << kRelBits;
-                    const int h = hs + dx + dy * hstr1 + dz * hstr2;
-                    const int a1 = t.hoff[h + 1];
-                    // windows of 32 candidates: the tests of a window set
-                    // bits of a mask (no branch per candidate), then only
-                    // the hits are written, in candidate order
-                    for (int w0 = t.hoff[h]; w0 < a1; w0 += 32) {
-                        const int wend = min(a1, w0 + 32);
-                        unsigned bits = 0u;
-                        for (int a = w0; a < wend; a += 4) {
-                            // four candidates through one pointer; the reads
-                            // past the cell's last atom (at most three,
-                            // a + 3 <= cap + 2) stay inside the workgroup's
-                            // LDS (the slot table follows the positions) and
-                            // their bits are dropped below
-                            const V* pa = t.pos + a;
-                            V o[4];
+                // the row's cells dx = -1, 0, 1 are consecutive in the tile
+                // (x-fastest halo order): one candidate range, less the end
+                // cells that lie beyond the radius; a candidate's x frame
+                // follows from which cell's range holds it
+                const int hrow = hs + dy * hstr1 + dz * hstr2;
+                const int b1 = t.hoff[hrow], b2 = t.hoff[hrow + 1];
+                const double gxm = box_gap(lx, -1, sp.h[0]), gxp = box_gap(lx, 1, sp.h[0]);
+                const int lo = fma(gxm, gxm, gyz) >= cull_v ? b1 : t.hoff[hrow - 1];
+                const int hi = fma(gxp, gxp, gyz) >= cull_v ? b2 : t.hoff[hrow + 2];
+                const T pxm = me.x + hx, pxp = me.x - hx;  // frames of cells dx = -1, +1
+                const unsigned qrow = (unsigned)(3 * (dy + 1) + 9 * (dz + 1));
+                // windows of 32 candidates: the tests of a window set bits of
+                // a mask (no branch per candidate), then only the hits are
+                // written, in candidate order
+                for (int w0 = lo; w0 < hi; w0 += 32) {
+                    const int wend = min(hi, w0 + 32);
+                    unsigned bits = 0u;
+                    for (int a = w0; a < wend; a += 4) {
+                        // four candidates through one pointer; the reads past
+                        // the range's last atom (at most three, a + 3 <=
+                        // cap + 2) stay inside the workgroup's LDS (the slot
+                        // table follows the positions) and their bits are
+                        // dropped below
+                        const V* pa = t.pos + a;
+                        V o[4];
 #pragma unroll
-                            for (int u = 0; u < 4; ++u) o[u] = pa[u];
+                        for (int u = 0; u < 4; ++u) o[u] = pa[u];
 #pragma unroll
-                            for (int u = 0; u < 4; ++u) {
-                                const T ex = px - o[u].x, ey = py - o[u].y, ez = pz - o[u].z;
-                                bits |= (unsigned)(ex * ex + ey * ey + ez * ez < rl2) << (a - w0 + u);
-                            }
+                        for (int u = 0; u < 4; ++u) {
+                            const int ac = a + u;
+                            const T px = ac < b1 ? pxm : (ac < b2 ? me.x : pxp);
+                            const T ex = px - o[u].x, ey = py - o[u].y, ez = pz - o[u].z;
+                            bits |= (unsigned)(ex * ex + ey * ey + ez * ez < rl2) << (a - w0 + u);
                         }
-                        // candidates past the cell's end, and the atom itself
-                        const int nwin = wend - w0, dself = aself - w0;
-                        bits &= nwin >= 32 ? ~0u : ((1u << nwin) - 1u);
-                        bits &= ~((unsigned)(dself >= 0 && dself < 32) << (dself & 31));
-                        while (bits) {
-                            const int u = __builtin_ctz(bits);
-                            bits &= bits - 1u;
-                            emit((unsigned)(w0 + u - base) | code);
-                        }
+                    }
+                    // candidates past the range's end, and the atom itself
+                    const int nwin = wend - w0, dself = aself - w0;
+                    bits &= nwin >= 32 ? ~0u : ((1u << nwin) - 1u);
+                    bits &= ~((unsigned)(dself >= 0 && dself < 32) << (dself & 31));
+                    while (bits) {
+                        const int u = __builtin_ctz(bits);
+                        bits &= bits - 1u;
+                        const int ac = w0 + u;
+                        const unsigned q = qrow + (unsigned)(ac >= b1) + (unsigned)(ac >= b2);
+                        emit((unsigned)(ac - base) | (q << kRelBits));
                     }
                 }
             }
