@@ -1118,9 +1118,10 @@ __device__ void record_energies(const PoolDev& P, const SysParams& sp, int s, in
 }
 
 constexpr int kGroupV = 4;  // vapour list entries fetched together in the step kernel (multiple of 4)
-// wall list entries (and wall positions) fetched together: 8 FP32 positions,
-// 6 FP64 ones (8 would spill the FP64 kernel's registers)
-template <typename T> constexpr int kGroupW = sizeof(T) == 4 ? 8 : 4;
+// wall list entries (and wall positions) fetched together: one chunk of four
+// in both precisions (groups of eight FP32 positions held four more
+// registers and made the step about 1% slower)
+template <typename T> constexpr int kGroupW = 4;
 
 
 
