@@ -855,9 +855,10 @@ __global__ void __launch_bounds__(kMaxBlock) k_list_build(PoolDev P)
     // the rounding of the local coordinates)
     const double cull_v = sp.rl2 * (1.0 + 1e-6), cull_w = sp.rw2 * (1.0 + 1e-6);
     const int cap = P.cap;
-    // wall candidates per load round (a window is two rounds): 12 FP32
-    // positions, 4 FP64 ones (more would spill the FP64 kernel's registers)
-    constexpr int kWallRound = sizeof(T) == 4 ? 12 : 4;
+    // wall candidates per load round (a window is two rounds): four in both
+    // precisions (rounds of 12 FP32 positions held 20 more registers and
+    // made the rebuild slower)
+    constexpr int kWallRound = 4;
     int mx = 0;
     for (int i = i0 + (int)threadIdx.x; i < i1; i += blockDim.x) {
         const V me = Lc[i];

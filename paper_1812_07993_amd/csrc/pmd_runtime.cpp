@@ -562,8 +562,11 @@ int pool_layout(Pool& p)
         for (int t = 0; t < sp.nbrick; ++t) p.hbrick.push_back(s);
         const int H = halo_cells(sp);
         hmax = std::max(hmax, H);
+        // room for 1.3 times the mean occupancy (the brick shapes are chosen
+        // to fit that); a denser halo grows the tile.  A larger margin takes
+        // LDS that more resident workgroups could use
         const double occ = (double)sp.nv / sp.ncell;
-        lds_want = std::max(lds_want, 2.0 * H * occ + 128.0);
+        lds_want = std::max(lds_want, 1.3 * H * occ + 128.0);
     }
     p.nchunk = (int)p.hchunk.size();
     p.ntile = (int)p.htile.size();
