@@ -32,20 +32,16 @@ PEAK_HBM_GBS = 8000.0
 
 # HBM bytes per k_step<float> launch from the FETCH_SIZE / WRITE_SIZE counter
 # passes summarised in profiles/k_step_slit128_mixed.md (128^3 slit workload,
-# skins 0.6 to 1.0), keyed by the hash of the device sources they were taken on, the
+# skins 0.7 and 1.0), keyed by the hash of the device sources they were taken on, the
 # vapour atom count, the skin and the workgroup shape (block, target atoms per
 # brick).  The rebuild period is not part of the key: it changes how often
 # the lists are rebuilt, not what one step launch reads and writes.  Any
 # other source, workload or tuning reports null.
 MEASURED_TRAFFIC = {
-    ("801981f8f6a22db4", 262144, 0.7, 512, 460): 95.73e6,
-    ("801981f8f6a22db4", 262144, 0.7, 256, 270): 99.49e6,
-    ("801981f8f6a22db4", 262144, 0.7, 256, 256): 102.04e6,
-    ("801981f8f6a22db4", 262144, 0.7, 256, 0): 100.09e6,
-    ("801981f8f6a22db4", 262144, 0.6, 512, 460): 94.11e6,
-    ("801981f8f6a22db4", 262144, 0.8, 512, 460): 99.09e6,
-    ("801981f8f6a22db4", 262144, 1.0, 512, 460): 96.01e6,
-    ("801981f8f6a22db4", 262144, 1.0, 256, 0): 106.17e6,
+    ("3cfe6f5030f3ebaf", 262144, 0.7, 256, 270): 86.99e6,
+    ("3cfe6f5030f3ebaf", 262144, 0.7, 512, 460): 83.63e6,
+    ("3cfe6f5030f3ebaf", 262144, 1.0, 256, 270): 89.10e6,
+    ("3cfe6f5030f3ebaf", 262144, 1.0, 256, 256): 91.06e6,
 }
 
 
