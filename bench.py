@@ -483,7 +483,7 @@ def serve_leg(n_requests, budget_gb, chunk, workers=2):
 def batch_autotune(poremd, descs, trial_steps, stream):
     """Tuning of the replica batch on the batch itself: the library's
     autotuner ranks (skin, rebuild period) on the median replica, then the
-    three best pairs times two workgroup shapes are each timed on all the
+    three best pairs times three workgroup shapes are each timed on all the
     replicas resident in one batch (trial_steps steps, wall clock), and the
     fastest is kept.  The systems are created once per workgroup shape at the
     smallest skin (the largest cell grid) and retuned per (skin, period)."""
@@ -502,7 +502,7 @@ def batch_autotune(poremd, descs, trial_steps, stream):
             break
     smin = min(sk for sk, _ in pairs)
     cands, times = [], []
-    for bl, ba in ((256, 0), (512, 460)):
+    for bl, ba in ((256, 0), (256, 270), (512, 460)):
         # the replicas are created once per workgroup shape (a shape sizes the
         # cell tables), at the smallest skin, and retuned per (skin, period)
         hs = [poremd.System.from_desc(d, tuning=poremd.make_tuning(skin=smin, block=bl, brick_atoms=ba),

@@ -205,16 +205,17 @@ int64_t host_wall_count(const pmd_params& p, const pmd_pore& q)
     return n;
 }
 
-// Neighbour-list slots per atom for a skin: 1.5 x the mean count in the list
-// sphere (at least at density 0.3, adsorbed layers are denser than the
-// mean), plus room for wall partners.
+// Neighbour-list words per atom for a skin: room for 1.5 x the mean count in
+// the list sphere (at least at density 0.3, adsorbed layers are denser than
+// the mean) at two vapour entries per word, plus room for wall partners (a
+// word each) and the chunk padding.
 int default_list_cap(const pmd_params& p, int64_t nv, double skin)
 {
     const double V = p.box[0] * p.box[1] * p.box[2];
     const double rho = std::max(0.3, (double)nv / V);
     const double rl = p.cutoff + skin;
     const double sphere = 4.0 / 3.0 * M_PI * rl * rl * rl;
-    return round_up((int)std::ceil(1.5 * sphere * rho) + 48, 16);
+    return round_up((int)std::ceil(0.75 * sphere * rho) + 48, 16);
 }
 
 pmd_tuning default_tuning(const pmd_params& p, int64_t nv)
