@@ -695,8 +695,9 @@ def main():
     ap.add_argument("--paper-model", default="fp64",
                     help="precision of the paper-model table (fp64 or mixed), or 'none'")
     ap.add_argument("--copy-mib", type=int, default=0,
-                    help="before the timed run, one plain device-to-device copy of this many "
-                         "MiB (a known-size kernel to scale the hardware byte counters by)")
+                    help="before the timed run, two elementwise kernels of known traffic (this "
+                         "many MiB read and written; this many read and half written) to scale "
+                         "the hardware byte counters by")
     ap.add_argument("--autotune-steps", type=int, default=200,
                     help="timed steps per autotuner candidate (0 = library defaults); "
                          "skipped when --skin or --rebin-every is given")
@@ -731,8 +732,14 @@ def main():
         torch.cuda.synchronize()
         torch.mul(src, 2.0, out=dst)
         torch.cuda.synchronize()
-        log("copy calibration: %d MiB read + %d MiB written by one elementwise kernel"
-            % (args.copy_mib, args.copy_mib))
+        # a second calibration kernel of another shape: two operands of
+        # copy_mib / 2 MiB read, copy_mib / 2 MiB written
+        half = src.shape[0] // 2
+        torch.add(src[:half], src[half:], out=dst[:half])
+        torch.cuda.synchronize()
+        log("copy calibration: %d MiB read + %d MiB written by one elementwise kernel, "
+            "then %d MiB read + %d MiB written by a two-operand one"
+            % (args.copy_mib, args.copy_mib, args.copy_mib, args.copy_mib // 2))
         del src, dst
     t0 = time.perf_counter()
     desc = synth.slit_large(n=args.n, box=args.box)
