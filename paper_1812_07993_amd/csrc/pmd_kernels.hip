@@ -749,23 +749,17 @@ __device__ int stage_halo(const PoolDev& P, const SysParams& sp, const HaloGeo& 
     }
     int tot;
     int run = block_exclusive_scan(sum, lds_scan, &tot);
+    if (tot > cap) return -1;  // (tot is the same in every thread)
+    // the thread owning a halo cell writes its first staged index and the
+    // storage slots of its staged atoms (a cell's atoms are consecutive
+    // slots)
     for (int h = lo; h < hi; ++h) {
-        const int n = t.hoff[h];
+        const int n = t.hoff[h], b0 = t.hbeg[h];
         t.hoff[h] = run;
+        for (int k = 0; k < n; ++k) t.slot[run + k] = b0 + k;
         run += n;
     }
     if (threadIdx.x == 0) t.hoff[g.H] = tot;
-    __syncthreads();
-    if (tot > cap) return -1;
-    // each staged atom learns its halo cell from the thread owning the cell
-    // (written into slot[] first), then turns it into its storage slot
-    for (int h = lo; h < hi; ++h)
-        for (int a = t.hoff[h], a1 = t.hoff[h + 1]; a < a1; ++a) t.slot[a] = h;
-    __syncthreads();
-    for (int a = threadIdx.x; a < tot; a += T_) {
-        const int h = t.slot[a];
-        t.slot[a] = t.hbeg[h] + (a - t.hoff[h]);
-    }
     __syncthreads();
     if (with_pos) {
         // each thread issues 4 independent loads (indices clamped to a valid
