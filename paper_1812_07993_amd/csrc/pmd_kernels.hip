@@ -143,7 +143,7 @@ __device__ __forceinline__ int wave_max(int v)
 
 // Exclusive scan over the workgroup (any size up to 1024, multiple of 64).
 // Returns the exclusive prefix; *total receives the workgroup sum.
-__device__ int block_exclusive_scan(int v, int* lds /* >= 17 ints */, int* total)
+__device__ int block_exclusive_scan(int v, int* lds /* >= 16 ints */, int* total)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nw = blockDim.x >> 6;
@@ -155,20 +155,17 @@ __device__ int block_exclusive_scan(int v, int* lds /* >= 17 ints */, int* total
     }
     if (lane == 63) lds[wave] = x;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        int run = 0;
-        for (int w = 0; w < nw; ++w) {
-            int t = lds[w];
-            lds[w] = run;
-            run += t;
-        }
-        lds[16] = run;
+    // every thread sums the wave totals itself (at most 16 broadcast reads)
+    // instead of waiting for one thread to prefix them: one barrier, and lds
+    // is not written again, so a kernel may call this once without another
+    int pre = 0, all = 0;
+    for (int w = 0; w < nw; ++w) {
+        const int t = lds[w];
+        pre += w < wave ? t : 0;
+        all += t;
     }
-    __syncthreads();
-    int r = lds[wave] + x - v;
-    *total = lds[16];
-    __syncthreads();
-    return r;
+    *total = all;
+    return pre + x - v;
 }
 
 __device__ __forceinline__ double atomic_load_f64(const double* p)
