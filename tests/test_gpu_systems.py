@@ -49,12 +49,23 @@ def test_nve_drift_cylinder_slab(prec):
     assert np.isclose(E["ke"][0], 0.5 * (3 * desc.n - 3) * 1.2, rtol=1e-12)
 
 
+# (skin, rebuild period, block, atoms per brick): the library default and
+# the shapes the benchmark's tuning chose for this workload (256-thread
+# bricks of 4 x 4 x 4 cells in mixed precision, 512-thread ones in FP64)
+SLIT_TUNINGS = [None, (0.7, 10, 256, 270), (0.7, 10, 512, 460)]
+
+
+@pytest.mark.parametrize("tune", SLIT_TUNINGS)
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_slit_128_sampled_forces(prec):
+def test_slit_128_sampled_forces(prec, tune):
     """262144 vapour + 131072 wall atoms: forces of 2048 sampled atoms against
-    the oracle's all-pairs sums, at creation and after 60 steps."""
+    the oracle's all-pairs sums, at creation and after 60 steps, with the
+    default tuning and with the benchmark's launch configurations."""
     desc = synth.slit_large()
-    s = poremd.System.from_desc(desc, precision=prec)
+    t = None
+    if tune is not None:
+        t = poremd.make_tuning(skin=tune[0], rebin_every=tune[1], block=tune[2], brick_atoms=tune[3])
+    s = poremd.System.from_desc(desc, precision=prec, tuning=t)
     walls = oracle_walls(desc)
     assert s.n_wall == walls.shape[0] == 131072
     p = oracle.make_params(desc.params.box)
@@ -68,6 +79,7 @@ def test_slit_128_sampled_forces(prec):
     F = s.forces()
     Fr, _ = oracle.forces_subset(X, walls, p, sel)
     check_forces(F[sel], Fr, prec, what="slit 128^3 after 60 steps")
+    s.close()
 
 
 _SWEEP = {}
@@ -87,12 +99,15 @@ def _sweep_desc(variant):
                           for p in ("mixed", "fp64")])
 def test_pore_sweep_4m_sampled_forces(variant, n_wall, prec):
     """4194304 vapour atoms in a 256 x 256 x 128 box with an 8-thick slab and
-    each of the three pores, in both precisions: the wall count derived by
-    hand, and the forces of 256 sampled atoms (half of them drawn from the
-    atoms within 3 sigma of a wall site) against the oracle's all-pairs sums,
-    at creation and after 20 steps, at the GPU's positions."""
+    each of the three pores, in both precisions, at the benchmark's launch
+    configuration: the wall count derived by hand, and the forces of 256
+    sampled atoms (half of them drawn from the atoms within 3 sigma of a wall
+    site) against the oracle's all-pairs sums, at creation and after 20
+    steps, at the GPU's positions."""
     desc = _sweep_desc(variant)
-    s = poremd.System.from_desc(desc, precision=prec)
+    # the launch configuration the benchmark's tuning chose for this workload
+    t = poremd.make_tuning(skin=0.4, rebin_every=6, block=512, brick_atoms=460)
+    s = poremd.System.from_desc(desc, precision=prec, tuning=t)
     assert s.n_wall == n_wall
     walls = oracle_walls(desc)
     assert walls.shape[0] == n_wall
