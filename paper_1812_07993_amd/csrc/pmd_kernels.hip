@@ -678,11 +678,39 @@ __device__ __forceinline__ HaloGeo halo_geo(const SysParams& sp, int b)
     return g;
 }
 
+// A staged position in the LDS tile: the float4 itself in FP32 (one 16-byte
+// access), x, y, z in FP64 (24 bytes instead of 32, so that more workgroups
+// fit a compute unit's LDS).
+struct d3t {
+    double x, y, z;
+};
+template <typename T> struct TileAtom;
+template <> struct TileAtom<float> { using type = f4; };
+template <> struct TileAtom<double> { using type = d3t; };
+
+__device__ __forceinline__ f4 tile_get(const f4* p) { return *p; }
+__device__ __forceinline__ d4 tile_get(const d3t* p)
+{
+    d4 v;
+    v.x = p->x;
+    v.y = p->y;
+    v.z = p->z;
+    v.w = 0.0;
+    return v;
+}
+__device__ __forceinline__ void tile_put(f4* p, const f4& v) { *p = v; }
+__device__ __forceinline__ void tile_put(d3t* p, const d4& v)
+{
+    p->x = v.x;
+    p->y = v.y;
+    p->z = v.z;
+}
+
 // LDS tile: staged positions, their slots, and per halo cell the first slot
 // and the first staged index.
 template <typename T>
 struct Tile {
-    typename V4<T>::type* pos;
+    typename TileAtom<T>::type* pos;
     int* slot;
     int* hbeg;   // [hmax] first slot of the halo cell
     int* hoff;   // [hmax + 1] first staged index of the halo cell
@@ -693,8 +721,8 @@ template <typename T>
 __device__ __forceinline__ Tile<T> tile_at(unsigned char* smem, size_t offset, int cap, int hmax)
 {
     Tile<T> t;
-    t.pos = (typename V4<T>::type*)(smem + offset);
-    t.slot = (int*)(smem + offset + (size_t)cap * sizeof(typename V4<T>::type));
+    t.pos = (typename TileAtom<T>::type*)(smem + offset);
+    t.slot = (int*)(smem + offset + (size_t)cap * sizeof(typename TileAtom<T>::type));
     t.hbeg = t.slot + cap;
     t.hoff = t.hbeg + hmax;
     return t;
@@ -703,7 +731,7 @@ __device__ __forceinline__ Tile<T> tile_at(unsigned char* smem, size_t offset, i
 template <typename T>
 __device__ __forceinline__ size_t tile_size(int cap, int hmax)
 {
-    return ((size_t)cap * (sizeof(typename V4<T>::type) + 4) + (size_t)(2 * hmax + 1) * 4 + 31) & ~(size_t)31;
+    return ((size_t)cap * (sizeof(typename TileAtom<T>::type) + 4) + (size_t)(2 * hmax + 1) * 4 + 31) & ~(size_t)31;
 }
 
 template <typename T>
@@ -767,10 +795,10 @@ __device__ int stage_halo(const PoolDev& P, const SysParams& sp, const HaloGeo& 
             const typename V4<T>::type v1 = Lc[t.slot[min(a1, tot - 1)]];
             const typename V4<T>::type v2 = Lc[t.slot[min(a2, tot - 1)]];
             const typename V4<T>::type v3 = Lc[t.slot[min(a3, tot - 1)]];
-            t.pos[a0] = v0;
-            if (a1 < tot) t.pos[a1] = v1;
-            if (a2 < tot) t.pos[a2] = v2;
-            if (a3 < tot) t.pos[a3] = v3;
+            tile_put(t.pos + a0, v0);
+            if (a1 < tot) tile_put(t.pos + a1, v1);
+            if (a2 < tot) tile_put(t.pos + a2, v2);
+            if (a3 < tot) tile_put(t.pos + a3, v3);
         }
     }
     __syncthreads();
@@ -923,10 +951,10 @@ __global__ void __launch_bounds__(kMaxBlock) k_list_build(PoolDev P)
                         // cap + 2) stay inside the workgroup's LDS (the slot
                         // table follows the positions) and their bits are
                         // dropped below
-                        const V* pa = t.pos + a;
+                        const auto* pa = t.pos + a;
                         V o[4];
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) o[u] = pa[u];
+                        for (int u = 0; u < 4; ++u) o[u] = tile_get(pa + u);
 #pragma unroll
                         for (int u = 0; u < 4; ++u) {
                             const int ac = a + u;
@@ -1025,7 +1053,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_list_build(PoolDev P)
 
 size_t tile_bytes(const PoolDev& P, int precision)
 {
-    const size_t v = precision == 1 ? sizeof(f4) : sizeof(d4);
+    const size_t v = precision == 1 ? sizeof(f4) : 3 * sizeof(double);
     return ((size_t)P.lds_atoms * (v + 4) + (size_t)(2 * P.hmax + 1) * 4 + 31) & ~(size_t)31;
 }
 
@@ -1264,7 +1292,7 @@ __device__ __forceinline__ void edge_entry(const PoolDev& P, const SysParams& sp
         ai = base + (int)(e & kRelMask);
         q = (int)(e >> kRelBits);
     }
-    const V o = wall ? x.Lc[vt + ai] : tl.pos[ai];
+    const V o = wall ? x.Lc[vt + ai] : tile_get(tl.pos + ai);
     const V sh = lut[q];
     const T dx = me.x - o.x + sh.x;
     const T dy = me.y - o.y + sh.y;
@@ -1562,7 +1590,7 @@ __device__ __forceinline__ void step_atoms(PoolDev& P, const SysParams& sp, cons
         const uint4* lst4 = (const uint4*)P.list + i;  // chunk c of this atom at lst4[c * vt]
         // the atom's neighbourhood in the tile starts at the first staged
         // atom of its neighbour cell (-1, -1, -1)
-        const V* posb = tl.pos + tl.hoff[halo_cell(g, in.cr & 1023, (in.cr >> 10) & 1023, in.cr >> 20, 0)];
+        const auto* posb = tl.pos + tl.hoff[halo_cell(g, in.cr & 1023, (in.cr >> 10) & 1023, in.cr >> 20, 0)];
         static_assert(kGroupV == 4, "the vapour loop takes half a 16-byte chunk per group");
         // one group of four vapour entries (two 32-bit words of a chunk) at
         // list position k
@@ -1570,7 +1598,7 @@ __device__ __forceinline__ void step_atoms(PoolDev& P, const SysParams& sp, cons
             const unsigned ec[4] = {w0 & 0xFFFFu, w0 >> 16, w1 & 0xFFFFu, w1 >> 16};
             V o[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) o[u] = posb[ec[u] & kRelMask];
+            for (int u = 0; u < 4; ++u) o[u] = tile_get(posb + (ec[u] & kRelMask));
             V sh[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) sh[u] = lut[ec[u] >> kRelBits];

@@ -523,7 +523,7 @@ int pool_grow_lists(Pool& p, int new_cap)
 
 constexpr size_t kTileBytesMax = 60 * 1024;  // dynamic LDS of the staged halo tile
 
-size_t tile_atom_bytes(int precision) { return (precision == PMD_MIXED ? sizeof(f4) : sizeof(d4)) + 4; }
+size_t tile_atom_bytes(int precision) { return (precision == PMD_MIXED ? sizeof(f4) : 3 * sizeof(double)) + 4; }
 
 int halo_cells(const SysParams& sp)
 {
