@@ -38,10 +38,10 @@ PEAK_HBM_GBS = 8000.0
 # the lists are rebuilt, not what one step launch reads and writes.  Any
 # other source, workload or tuning reports null.
 MEASURED_TRAFFIC = {
-    ("6cf906ca60b14688", 262144, 0.7, 256, 270): 87.00e6,
-    ("6cf906ca60b14688", 262144, 0.7, 512, 460): 83.63e6,
-    ("6cf906ca60b14688", 262144, 1.0, 256, 270): 89.09e6,
-    ("6cf906ca60b14688", 262144, 1.0, 256, 256): 91.07e6,
+    ("2f5fb16131aad05e", 262144, 0.7, 256, 270): 87.00e6,
+    ("2f5fb16131aad05e", 262144, 0.7, 512, 460): 83.62e6,
+    ("2f5fb16131aad05e", 262144, 1.0, 256, 270): 89.08e6,
+    ("2f5fb16131aad05e", 262144, 1.0, 256, 256): 91.06e6,
 }
 
 
